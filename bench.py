@@ -1,0 +1,182 @@
+"""Throughput of the training iteration of the object-aware Gaussian rasterizer.
+
+One step = project/cull/bin + sort + render forward + object loss + render
+backward + project backward + Adam, on the 200k-Gaussian room (20 object blobs
+plus 30% background, ids 0..20) seen whole by a 640x480 camera (f = 600), all
+inputs resident on the GPU.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2503_02223_amd import binding as B  # noqa: E402
+from paper_2503_02223_amd import scenes  # noqa: E402
+
+METRIC = "fwd+bwd iters/s @640x480, 200k Gaussians; time-to-PSNR learned vs plain init"
+MI355X_FP32_VECTOR_TFLOPS = 157.3   # published fp32 vector peak (256 CUs, 2.4 GHz)
+# Algorithmic FLOPs of the render backward (see the design notes):
+FLOP_PER_EXAMINED = 11.0   # contribution test of one (pixel, pair) at or before the pixel's last blend
+FLOP_PER_BLENDED = 46.0    # gradient of one blended (pixel, Gaussian) incl. its share of the reduction
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(seed=0, n=200_000):
+    sc = scenes.slam_view_scene(seed=seed, n=n)
+    dev = "cuda"
+    p = torch.tensor(sc["params"], dtype=torch.float32, device=dev)
+    ids = torch.tensor(sc["ids"], device=dev)
+    # Targets: the same scene perturbed (means, scales, opacities, colours), rendered once.
+    pt = torch.tensor(scenes.perturb(sc["params"], seed + 1), dtype=torch.float32, device=dev)
+    r0 = B.Rasterizer(sc["cams"], n, sc["K"])
+    t0 = r0.forward(pt, ids, probs=True, id_map=True)
+    torch.cuda.synchronize()
+    targets = dict(color=t0["color"].clone(), depth=t0["depth"].clone(), id=t0["id_map"].clone())
+    del r0, t0
+    return sc, p, ids, targets
+
+
+def backward_work(tr):
+    """Examined (pixel, pair) count E and blended count B of the current state."""
+    f = tr.r.frame
+    img = f.new_images(target=tr.targets["id"], n_blend=True)
+    f.project_cull_bin(tr.params, tr.ids)
+    f.sort()
+    f.render_forward(img)
+    torch.cuda.synchronize()
+    last = img["last"][0].long()
+    tw, th = tr.r.ctx.config.tile_w, tr.r.ctx.config.tile_h
+    H, W = last.shape
+    tx = (torch.arange(W, device=last.device) // tw)
+    ty = (torch.arange(H, device=last.device) // th)
+    tile = ty[:, None] * f.layout.tiles_x + tx[None, :]
+    ranges = f.buf("ranges", torch.int32).view(-1, 2).long()
+    start = ranges[tile, 0]
+    E = torch.where(last >= 0, last - start + 1, torch.zeros_like(last)).sum().item()
+    Bn = img["n_blend"].long().sum().item()
+    return int(E), int(Bn)
+
+
+def cpu_baseline(sc, targets_seed=1, n_pix=1024, seed=0):
+    """The FP64 oracle (every Gaussian at every sampled pixel) on a bounded
+    sample of the same workload: forward + loss + backward over n_pix random
+    pixels of the 640x480 frame with all 200k Gaussians, plus Adam over all
+    Gaussians; scaled to a full 307,200-pixel iteration."""
+    import oracle
+    cam = sc["cams"][0]
+    HW = cam["width"] * cam["height"]
+    rng = np.random.default_rng(seed)
+    pix = np.sort(rng.choice(HW, size=n_pix, replace=False)).astype(np.int64)
+    K = sc["K"]
+    tg = oracle.render(scenes.perturb(sc["params"], targets_seed), sc["ids"], cam, K=K, pix=pix)
+    t_id = oracle.id_map(tg["P"], tg["Tf"])
+    t0 = time.perf_counter()
+    out = oracle.render(sc["params"], sc["ids"], cam, K=K, pix=pix)
+    p_t = np.where(t_id >= 0, np.take_along_axis(out["P"], np.maximum(t_id, 0)[None], 0)[0], out["Tf"])
+    lo = oracle.object_loss(out["C"], out["D"], p_t, tg["C"], tg["D"], t_id)
+    gP = np.zeros((K, n_pix))
+    for k in range(K):
+        gP[k] = np.where(t_id == k, lo["gp"], 0.0)
+    gT = np.where(t_id == -1, lo["gp"], 0.0)
+    grads, _ = oracle.render_backward(sc["params"], sc["ids"], cam, K=K, gC=lo["gC"], gD=lo["gD"], gP=gP, gT=gT,
+                                      pix=pix)
+    t_render = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    z = np.zeros_like(sc["params"])
+    oracle.adam(sc["params"], grads, z, z, 1, B.default_lrs())
+    t_adam = time.perf_counter() - t1
+    per_iter = t_render * (HW / n_pix) + t_adam
+    return dict(value=1.0 / per_iter, unit="iters/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"FP64 forward+object loss+backward over {n_pix} of {HW} pixels with all "
+                       f"{sc['params'].shape[1]} Gaussians ({t_render:.1f} s) scaled by the pixel count, "
+                       f"plus one Adam step over all Gaussians ({t_adam:.2f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=200_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-pixels", type=int, default=49152)
+    ap.add_argument("--tile", default="8x8", help="pixel tile WxH (8x8, 16x8, 16x16, 32x8, 8x32)")
+    args = ap.parse_args()
+    tw, th = (int(x) for x in args.tile.split("x"))
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the multi-GPU (view-sharded) path is designed but not built; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.init()
+    log("building workload")
+    sc, p, ids, targets = build_workload(n=args.n)
+    tr = B.Trainer(p, ids, sc["cams"], sc["K"], targets, ctx=B.Context(tile_w=tw, tile_h=th))
+    log(f"pair capacity {tr.r.frame.capacity}")
+    for _ in range(args.warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    tr.check()
+    # timed region: K whole steps; HIP events around the render backward on the
+    # stream it is launched on (torch's current stream)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    orig = tr.r.frame.render_backward
+    it = iter(ev)
+
+    def timed_bwd(img, grads, s=None):
+        a, b = next(it)
+        a.record(stream)
+        orig(img, grads, s)
+        b.record(stream)
+
+    tr.r.frame.render_backward = timed_bwd
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tr.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tr.r.frame.render_backward = orig
+    npairs = tr.check()
+    bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms = dt * 1e3 / args.steps
+    loss = tr.loss.cpu().numpy().tolist()
+    E, Bn = backward_work(tr)
+    flops = FLOP_PER_EXAMINED * E + FLOP_PER_BLENDED * Bn
+    achieved = flops / (bwd_ms * 1e-3) / 1e12
+    roof = dict(bound="alu", kernel=f"render_backward_kernel<float,{tw},{th}>", achieved=round(achieved, 3),
+                peak=MI355X_FP32_VECTOR_TFLOPS, unit="TFLOP/s", frac=round(achieved / MI355X_FP32_VECTOR_TFLOPS, 4),
+                traffic=None, avg_ms=round(bwd_ms, 4), examined_pairs=E, blended_pairs=Bn,
+                flop_per_examined=FLOP_PER_EXAMINED, flop_per_blended=FLOP_PER_BLENDED)
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(sc, n_pix=args.cpu_pixels)
+    out = {
+        "metric": METRIC, "value": round(1e3 / ms, 2), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "room of 200k Gaussians (20 object blobs + 30% background, K=21) at 640x480, "
+                               "f=600; step = project/bin + sort + render fwd + object loss (L1 rgb + L1 depth + "
+                               "object CE) + render bwd + project bwd + Adam",
+                   "n_gaussians": args.n, "width": 640, "height": 480, "K": sc["K"], "pairs": npairs,
+                   "tile": args.tile, "loss": [round(x, 6) for x in loss]},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

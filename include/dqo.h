@@ -1,0 +1,290 @@
+/*
+ * libdqo — MI355X (gfx950) kernels for the GPU-side optimization of DQO-MAP
+ * (object-aware 3D Gaussian Splatting): differentiable rasterization of colour,
+ * depth and per-Gaussian object id, the object loss it feeds, the Adam step, and
+ * the per-object dual-quadric fit from 2D boxes.
+ *
+ * Paper passages the calls follow:
+ *   - Gaussians share the quadric's shape: mean, rotation, axis scales
+ *     (Sec. III-A, Eq. (2)-(3)); each Gaussian carries an object id
+ *     (Sec. III-C, the text after Eq. (7)-(8)).
+ *   - Colour and depth are rendered by alpha blending, and the instance
+ *     channel ins of Eq. (12) bounds an object's outline (Sec. III-D).
+ *   - The object loss is Eq. (10)-(14): colour, depth and instance terms,
+ *     weighted by lambda.
+ *   - Rasterization and its backward run as GPU kernels (Sec. IV,
+ *     implementation detail).
+ *   - The object quadric Q*_k satisfies pi^T Q* pi = 0 for the planes
+ *     back-projected from box edges (Eq. (1)); cameras are P = K [R|t]
+ *     (text after Eq. (4)).
+ *
+ * Conventions shared by every call
+ *   - Every data pointer is DEVICE memory owned by the caller (e.g. torch
+ *     tensors).  The library never allocates, frees or synchronises in the
+ *     compute calls; every compute call only enqueues kernels on `stream`
+ *     (a hipStream_t, NULL = default stream), so a sequence of calls can be
+ *     captured in a HIP graph.  Host pointers are marked "host".
+ *   - `dtype` selects the arithmetic: DQO_F32 (float) or DQO_F64 (double).
+ *     Every floating-point buffer of a call is of that type.
+ *   - Gaussian parameters are structure-of-arrays params[14][n], row r holds
+ *     component r of every Gaussian: rows 0-2 mean (world), 3-5 log-scale,
+ *     6-9 quaternion (w,x,y,z; need not be normalised), 10 opacity logit,
+ *     11-13 colour.  ids[n] are int32 object ids.
+ *   - Images are [V][C][H][W] row-major, V = number of views.
+ *   - Return value: DQO_OK (0) or a negative DQO_E* code; on error the
+ *     context's dqo_last_error() holds a message and nothing was enqueued.
+ *     Argument validation happens on the host before any launch.
+ *   - Errors found on the device (pair-list overflow, non-finite inputs) set
+ *     bits in a status word inside the state buffer; read it with
+ *     dqo_read_status() at a point of the caller's choosing.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef DQO_H
+#define DQO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DQO_MAX_VIEWS 16
+#define DQO_MAX_K 64
+#define DQO_NUM_PARAMS 14
+
+enum dqo_status {
+    DQO_OK = 0,
+    DQO_EINVAL = -1,      /* bad argument: NULL, size, dtype, K, view count, tile shape */
+    DQO_ECAPACITY = -2,   /* pair list needs more than pair_capacity entries */
+    DQO_ENONFINITE = -3,  /* a parameter was NaN/Inf (those Gaussians were culled) */
+    DQO_EDEGENERATE = -4, /* not enough independent constraints */
+    DQO_EHIP = -5,        /* a HIP runtime call failed; message in dqo_last_error */
+    DQO_EINTERNAL = -6    /* a device-side wait exceeded its bound (library bug) */
+};
+
+enum dqo_dtype { DQO_F32 = 0, DQO_F64 = 1 };
+
+/* Bits of the device status word (dqo_read_status). */
+enum dqo_status_bits {
+    DQO_STATUS_OVERFLOW = 1,   /* more pairs than pair_capacity: outputs undefined */
+    DQO_STATUS_NONFINITE = 2,  /* non-finite parameters met (Gaussians culled) */
+    DQO_STATUS_TIMEOUT = 4     /* a bounded device wait gave up: outputs undefined */
+};
+
+/* Rasterizer constants.  The paper does not state them; these are the readings
+ * used throughout (defaults from dqo_config_default). */
+typedef struct dqo_config {
+    int32_t tile_w, tile_h;  /* pixel tile: 16x16 default; 8x8, 16x8, 32x8, 8x32 also accepted */
+    double z_near;           /* 0.2: cull if camera depth <= z_near */
+    double dilation;         /* 0.3 px^2 added to the 2D covariance diagonal */
+    double q_max;            /* 9: contribute only where the Mahalanobis form Q <= q_max */
+    double alpha_min;        /* 1/255: contribute only if alpha >= alpha_min */
+    double alpha_max;        /* 0.99: alpha = min(alpha_max, o * exp(-Q/2)) */
+    double t_min;            /* 1e-4: stop before transmittance would drop below t_min */
+    double bg[3];            /* background colour added with weight T_final */
+} dqo_config;
+
+/* Pinhole camera: world -> camera x_c = R x_w + t; pixel = (fx x/z + cx, fy y/z + cy).
+ * Pixel (u, v) is sampled at (u + 1/2, v + 1/2).  Host struct. */
+typedef struct dqo_camera {
+    double R[9]; /* row-major */
+    double t[3];
+    double fx, fy, cx, cy;
+    int32_t width, height;
+} dqo_camera;
+
+/* Size of one frame of work.  All views must share width and height. */
+typedef struct dqo_frame_desc {
+    int64_t n;             /* Gaussians, >= 0 */
+    int32_t n_views;       /* 1..DQO_MAX_VIEWS */
+    int32_t K;             /* object classes for the instance channels, 0..DQO_MAX_K */
+    int64_t pair_capacity; /* max (tile, Gaussian) pairs over all views, <= 2^30 */
+    int32_t dtype;         /* DQO_F32 or DQO_F64 */
+    int32_t reserved;
+} dqo_frame_desc;
+
+/* Sub-buffers of the caller-allocated state buffer (dqo_state_layout). */
+enum dqo_buf {
+    DQO_BUF_SPLATS = 0,  /* [V*n] records of 12 values: mx,my,A,B,C,opacity,z,id,r,g,b,0 */
+    DQO_BUF_RECTS,       /* [V*n] int16x4 tile rectangle x0,y0,x1,y1 (inclusive), empty = x1<x0 */
+    DQO_BUF_COUNTS,      /* [V*n] uint32 tiles covered */
+    DQO_BUF_OFFSETS,     /* [V*n] uint32 first slot of the item's pairs in emission order */
+    DQO_BUF_DEPTH_KEYS,  /* [V*n] uint32 sorted depth keys (float bits of z; culled = 0xffffffff) */
+    DQO_BUF_DEPTH_ORDER, /* [V*n] uint32 item index (view*n + g) in depth order */
+    DQO_BUF_PAIR_KEYS,   /* [cap] uint32 sorted global tile id (view*tiles + tile) */
+    DQO_BUF_PAIR_VALS,   /* [cap] uint32 item index, in (tile, depth, index) order */
+    DQO_BUF_RANGES,      /* [V*tiles][2] uint32 [start, end) of each tile in the sorted pairs */
+    DQO_BUF_PARTIALS,    /* [cap][10] per-pair gradient partials (render backward) */
+    DQO_BUF_CONTROL,     /* status word, pair count, counters, histograms, loss partials */
+    DQO_BUF_SCRATCH,     /* sort double buffers and wait state */
+    DQO_BUF_COUNT
+};
+
+typedef struct dqo_layout {
+    int64_t offset[DQO_BUF_COUNT]; /* byte offset of each sub-buffer, 256-byte aligned */
+    int64_t bytes[DQO_BUF_COUNT];
+    int64_t total;                 /* bytes the caller must allocate */
+    int32_t tiles_x, tiles_y;      /* tile grid per view */
+    int32_t pair_key_bits;         /* significant bits of the pair keys */
+    int32_t reserved;
+} dqo_layout;
+
+/* Rendered images (device, caller-owned).  Optional pointers may be NULL. */
+typedef struct dqo_images {
+    void* color;           /* [V][3][H][W] colour incl. T_final * bg */
+    void* depth;           /* [V][H][W] sum of w_i z_i (camera depth, not normalised) */
+    void* t_final;         /* [V][H][W] transmittance after the last blended Gaussian */
+    int32_t* last;         /* [V][H][W] position in the sorted pair list of the last
+                              blended Gaussian, -1 if none */
+    void* probs;           /* optional [V][K][H][W] instance channels P_k = ins_k */
+    int32_t* id_map;       /* optional [V][H][W] argmax over (P_0..P_{K-1}, T_final), -1 = none;
+                              needs probs */
+    const int32_t* target; /* optional [V][H][W] target object id per pixel, -1 = none */
+    void* p_target;        /* optional [V][H][W] probability of the target: P_t, or
+                              T_final where target = -1; needs target */
+    int32_t* n_blend;      /* optional [V][H][W] number of Gaussians blended at the pixel */
+} dqo_images;
+
+/* Upstream gradients of the images (device).  Optional pointers may be NULL. */
+typedef struct dqo_image_grads {
+    void* d_color;     /* [V][3][H][W] */
+    void* d_depth;     /* [V][H][W] */
+    void* d_t_final;   /* optional [V][H][W] */
+    void* d_probs;     /* optional [V][K][H][W] */
+    void* d_p_target;  /* optional [V][H][W], interpreted through dqo_images.target */
+} dqo_image_grads;
+
+typedef struct dqo_targets {
+    const void* color;   /* [V][3][H][W] */
+    const void* depth;   /* [V][H][W]; pixels with depth <= 0 carry no depth term */
+    const int32_t* id;   /* [V][H][W] target object id, -1 = none */
+} dqo_targets;
+
+/* Loss weights: L = w_rgb * L_rgb + w_depth * L_depth + lambda * L_obj (Eq. (14)).
+ * ce_eps clamps the probability inside the log of the cross-entropy. */
+typedef struct dqo_loss_weights {
+    double w_rgb, w_depth, lambda, ce_eps;
+} dqo_loss_weights;
+
+/* Adam hyper-parameters, one learning rate per parameter row. */
+typedef struct dqo_adam {
+    double lr[DQO_NUM_PARAMS];
+    double beta1, beta2, eps;
+} dqo_adam;
+
+typedef struct dqo_ctx dqo_ctx;
+
+/* ---- context ------------------------------------------------------------ */
+void dqo_config_default(dqo_config* cfg /* host, out */);
+/* Creates a context (host memory only).  cfg may be NULL for the defaults. */
+int dqo_ctx_create(dqo_ctx** out, const dqo_config* cfg);
+int dqo_ctx_destroy(dqo_ctx* ctx);
+/* Message of the last failing call on this context ("" if none). */
+const char* dqo_last_error(const dqo_ctx* ctx);
+const char* dqo_status_string(int code);
+/* Library version string. */
+const char* dqo_version(void);
+
+/* ---- state buffer ------------------------------------------------------- */
+/* Layout of the state buffer for a frame (host computation only).  The caller
+ * allocates `total` bytes of device memory (256-byte aligned) and passes it to
+ * every call of that frame. */
+int dqo_state_layout(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams /* host [V] */,
+                     dqo_layout* out /* host */);
+/* Clears the control block (status word, counters) of a fresh state buffer. */
+int dqo_state_init(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams, void* state,
+                   void* stream);
+/* Synchronises `stream` and copies the status word and the pair count to the
+ * host.  Returns DQO_ECAPACITY / DQO_ENONFINITE / DQO_EINTERNAL when the
+ * matching status bit is set, else DQO_OK. */
+int dqo_read_status(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams, void* state,
+                    uint32_t* status /* host, out */, int64_t* num_pairs /* host, out */, void* stream);
+/* Clears the status word (enqueued on stream). */
+int dqo_clear_status(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams, void* state,
+                     void* stream);
+
+/* ---- hot path ----------------------------------------------------------- */
+/* Projection, culling and binning (EWA projection of the Gaussian shape of
+ * Eq. (2) into every view).  Per (view, Gaussian) item: 2D mean, conic,
+ * opacity, depth, tile rectangle of the 3-sigma box; then the items are sorted
+ * by depth (float bits of camera z, stable, so ties keep index order), and the
+ * (tile, item) pairs are emitted in that order into the pair list.  The pair
+ * count stays on the device; if it exceeds pair_capacity the OVERFLOW status
+ * bit is set.  params: [14][n] of dtype; ids: [n]. */
+int dqo_project_cull_bin(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
+                         const void* params, const int32_t* ids, void* state, void* stream);
+
+/* Stable radix sort of the pair list by global tile id (the list is already in
+ * depth order, so the result is ordered by (tile, depth, item index)), then the
+ * [start, end) range of every tile. */
+int dqo_sort(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams, void* state,
+             void* stream);
+
+/* Front-to-back alpha blending of colour, depth and the instance channels of
+ * Eq. (12) for every pixel of every view (Sec. III-D): Gaussian i contributes
+ * at pixel sample s iff Q_i(s) <= q_max and alpha_i = min(alpha_max,
+ * o_i exp(-Q_i/2)) >= alpha_min; w_i = alpha_i T_i; blending stops before a
+ * Gaussian that would take T below t_min.  P_k = sum of w_i over Gaussians with
+ * id k, so sum_k P_k + T_final = 1.  Needs dqo_project_cull_bin and dqo_sort
+ * on the same state.  probs requires K >= 1. */
+int dqo_render_forward(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
+                       const void* state, const dqo_images* img, void* stream);
+
+/* Object loss of Eq. (10)-(14), read as: L_rgb = mean |C - C^| over 3VHW,
+ * L_depth = mean |D - D^| over pixels with D^ > 0, L_obj = mean over VHW of
+ * -log max(p_t, ce_eps) with p_t = img->p_target; total = w_rgb L_rgb +
+ * w_depth L_depth + lambda L_obj.  Writes loss[4] = {total, L_rgb, L_depth,
+ * L_obj} (device double) and the upstream gradients d_color, d_depth and
+ * d_p_target of `g` (sign(0) = 0; no CE gradient where p_t < ce_eps).  The
+ * reduction order is fixed, so the result is bitwise reproducible. */
+int dqo_object_loss(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
+                    const dqo_images* img, const dqo_targets* tgt, const dqo_loss_weights* w,
+                    double* loss /* device [4] */, const dqo_image_grads* g, void* state, void* stream);
+
+/* Adjoint of dqo_render_forward with the blended set held fixed.  Walks each
+ * pixel back to front from its last blended Gaussian, recomputing the
+ * transmittance T_i = T_{i+1} / (1 - alpha_i) instead of storing it, and
+ * writes one gradient record per (tile, Gaussian) pair into the state
+ * (partials of mean2d, conic, opacity, colour, depth).  No atomics: the
+ * per-Gaussian sums are taken in dqo_project_backward in a fixed order. */
+int dqo_render_backward(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
+                        void* state, const dqo_images* img, const dqo_image_grads* g, void* stream);
+
+/* Sums each Gaussian's pair partials over tiles and views and applies the
+ * chain rule through the projection to grads[14][n] (same layout as params;
+ * overwritten; zero for Gaussians culled in every view). */
+int dqo_project_backward(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
+                         const void* params, const void* state, void* grads, void* stream);
+
+/* One Adam step (bias-corrected, PyTorch semantics) over params[14][n] with
+ * per-row learning rates; m and v are the moment buffers (same layout).
+ * step >= 1 is the 1-based step count. */
+int dqo_adam_step(const dqo_ctx* ctx, int32_t dtype, void* params, const void* grads, void* m, void* v,
+                  int64_t n, const dqo_adam* hp /* host */, int64_t step, void* stream);
+
+/* ---- quadric -------------------------------------------------------------- */
+enum dqo_quadric_status { DQO_QUADRIC_OK = 0, DQO_QUADRIC_DEGENERATE = 1, DQO_QUADRIC_NOT_ELLIPSOID = 2 };
+
+/* Per-object dual quadric from 2D boxes (Eq. (1)): every box edge line l of
+ * object k seen by camera P_v (3x4, P = K [R|t]) gives the plane pi = P_v^T l
+ * (normalised), and pi^T Q* pi = 0 is one linear equation in the 10 unique
+ * entries of the symmetric Q*.  Q* is the right singular vector of the
+ * smallest singular value of the stacked equations (FP64 one-sided Jacobi
+ * SVD), scaled so Q*_44 = -1, then decoupled as Eq. (2)-(3): mu = -Q*[0:3,3],
+ * Q*[0:3,0:3] + mu mu^T = R diag(a^2,b^2,c^2) R^T (axes ascending, det R = +1).
+ * Edges within `border` px of the image border are dropped when img_wh is
+ * given.  Inputs (device): boxes[n_boxes][4] (x0,y0,x1,y1), box_obj[n_boxes],
+ * box_view[n_boxes], P[n_views][12] row-major, img_wh[n_views][2] or NULL.
+ * Outputs (device): Q[n_obj][16], mu[n_obj][3], R[n_obj][9], axes[n_obj][3],
+ * status[n_obj] (dqo_quadric_status; DEGENERATE when fewer than 9 equations
+ * or a null space of dimension > 1).  At most 256 equations per object. */
+int dqo_fit_dual_quadric(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, const double* boxes,
+                         const int32_t* box_obj, const int32_t* box_view, int32_t n_views, const double* P,
+                         const int32_t* img_wh, double border, double* Q, double* mu, double* R, double* axes,
+                         int32_t* status, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DQO_H */

@@ -58,7 +58,7 @@ def _load():
         d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int32
         _lib.oracle_project.argtypes = [i64, P(d), P(_OCam), P(_OCfg), P(d)]
         _lib.oracle_render.argtypes = [i64, P(d), P(i32), P(_OCam), P(_OCfg), ctypes.c_int, i64,
-                                       P(i64), P(d), P(d), P(d), P(d), P(i64), P(i32), P(d), P(d)]
+                                       P(i64), P(d), P(d), P(d), P(d), P(i64), P(i32), P(d), P(d), P(d)]
         _lib.oracle_render.restype = ctypes.c_int
         _lib.oracle_render_backward.argtypes = [i64, P(d), P(i32), P(_OCam), P(_OCfg), ctypes.c_int,
                                                 i64, P(i64), P(d), P(d), P(d), P(d), P(d), P(d)]
@@ -144,7 +144,7 @@ def render(params, ids, cam, cfg=None, K=0, pix=None, want_P=True):
 
     pix: flat pixel indices (v * W + u) to evaluate, or None for the whole image.
     Returns C (3, npix), D, Tf, P (K, npix) or None, last (Gaussian index or -1),
-    nblend, margin, margin_clamp; reshaped to (…, H, W) when pix is None."""
+    nblend, margin, margin_clamp, depth_gap; reshaped to (…, H, W) when pix is None."""
     p = _params64(params)
     n = p.shape[1]
     ids = np.ascontiguousarray(np.asarray(ids, dtype=np.int32))
@@ -159,16 +159,17 @@ def render(params, ids, cam, cfg=None, K=0, pix=None, want_P=True):
     nb = np.zeros(npix, dtype=np.int32)
     mg = np.zeros(npix)
     mgc = np.zeros(npix)
+    gap = np.zeros(npix)
     c, g = _cam(cam), _cfg(cfg)
     rc = _load().oracle_render(n, _ptr(p, ctypes.c_double), _ptr(ids, ctypes.c_int32), ctypes.byref(c),
                                ctypes.byref(g), int(K), npix, _ptr(px, ctypes.c_int64),
                                _ptr(C, ctypes.c_double), _ptr(D, ctypes.c_double),
                                _ptr(Tf, ctypes.c_double), _ptr(P, ctypes.c_double),
                                _ptr(last, ctypes.c_int64), _ptr(nb, ctypes.c_int32),
-                               _ptr(mg, ctypes.c_double), _ptr(mgc, ctypes.c_double))
+                               _ptr(mg, ctypes.c_double), _ptr(mgc, ctypes.c_double), _ptr(gap, ctypes.c_double))
     if rc != 0:
         raise MemoryError("oracle_render failed")
-    out = dict(C=C, D=D, Tf=Tf, P=P, last=last, nblend=nb, margin=mg, margin_clamp=mgc)
+    out = dict(C=C, D=D, Tf=Tf, P=P, last=last, nblend=nb, margin=mg, margin_clamp=mgc, depth_gap=gap)
     if full:
         H, W = int(cam["height"]), int(cam["width"])
         for k, v in list(out.items()):

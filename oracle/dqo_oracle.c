@@ -178,16 +178,18 @@ static double rel_margin(double v, double thr) { return fabs(v - thr) / fabs(thr
  * Forward render of the listed pixels (pix[j] = v * W + u).
  * Outputs (per listed pixel j): C[3][npix], D[npix], Tf[npix], P[K][npix] (may be NULL),
  * last[npix] (index of the last blended Gaussian or -1), nblend[npix],
- * margin[npix] = smallest relative distance of any discrete decision taken at
- * the pixel (Q vs q_max, alpha vs alpha_min, T' vs t_min, depth order of
- * consecutive contributors) to its threshold, and margin_clamp[npix] = smallest
- * relative distance of an unclamped alpha to alpha_max (it changes gradients,
- * not values).
+ * margin[npix] = smallest relative distance of any threshold decision taken
+ * at the pixel (Q vs q_max, alpha vs alpha_min, T' vs t_min) to its threshold,
+ * margin_clamp[npix] = smallest relative distance of an unclamped alpha to
+ * alpha_max (it changes gradients, not values), and depth_gap[npix] = smallest
+ * relative depth difference between consecutive contributors (the order of two
+ * contributors at almost the same depth is a discrete decision too; its scale
+ * is the resolution of the depth values, not the threshold band).
  */
 int oracle_render(int64_t n, const double* params, const int32_t* ids, const ocam* cam,
                   const ocfg* cfg, int K, int64_t npix, const int64_t* pix,
                   double* C, double* D, double* Tf, double* P, int64_t* last, int32_t* nblend,
-                  double* margin, double* margin_clamp) {
+                  double* margin, double* margin_clamp, double* depth_gap) {
     oproj* pr = (oproj*)malloc(sizeof(oproj) * (size_t)(n > 0 ? n : 1));
     int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     if (!pr || !order) { free(pr); free(order); return -1; }
@@ -197,7 +199,7 @@ int oracle_render(int64_t n, const double* params, const int32_t* ids, const oca
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t j = 0; j < npix; ++j) {
         double su = (double)(pix[j] % W) + 0.5, sv = (double)(pix[j] / W) + 0.5;
-        double T = 1.0, c[3] = {0, 0, 0}, d = 0, mg = INFINITY, mgc = INFINITY;
+        double T = 1.0, c[3] = {0, 0, 0}, d = 0, mg = INFINITY, mgc = INFINITY, gapmin = INFINITY;
         double prev_z = -INFINITY;
         int64_t lst = -1;
         int32_t nb = 0;
@@ -219,7 +221,7 @@ int oracle_render(int64_t n, const double* params, const int32_t* ids, const oca
             /* a contributor: check the depth gap to the previous contributor */
             if (prev_z > -INFINITY) {
                 double gap = fabs(g->z - prev_z) / fabs(g->z);
-                if (gap < mg) mg = gap;
+                if (gap < gapmin) gapmin = gap;
             }
             prev_z = g->z;
             double Tn = T * (1.0 - a);
@@ -245,6 +247,7 @@ int oracle_render(int64_t n, const double* params, const int32_t* ids, const oca
         if (nblend) nblend[j] = nb;
         if (margin) margin[j] = mg;
         if (margin_clamp) margin_clamp[j] = mgc;
+        if (depth_gap) depth_gap[j] = gapmin;
     }
     free(pr);
     free(order);

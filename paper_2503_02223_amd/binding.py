@@ -1,0 +1,451 @@
+"""Thin ctypes binding of libdqo (include/dqo.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libdqo.so; torch supplies device memory and the current stream.  Loading
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libdqo.so")
+
+MAX_VIEWS = 16
+MAX_K = 64
+NUM_PARAMS = 14
+OK, EINVAL, ECAPACITY, ENONFINITE, EDEGENERATE, EHIP, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+F32, F64 = 0, 1
+STATUS_OVERFLOW, STATUS_NONFINITE, STATUS_TIMEOUT = 1, 2, 4
+BUF_NAMES = ["splats", "rects", "counts", "offsets", "depth_keys", "depth_order", "pair_keys", "pair_vals",
+             "ranges", "partials", "control", "scratch"]
+
+EXPORTED = ["dqo_config_default", "dqo_ctx_create", "dqo_ctx_destroy", "dqo_last_error", "dqo_status_string",
+            "dqo_version", "dqo_state_layout", "dqo_state_init", "dqo_read_status", "dqo_clear_status",
+            "dqo_project_cull_bin", "dqo_sort", "dqo_render_forward", "dqo_object_loss", "dqo_render_backward",
+            "dqo_project_backward", "dqo_adam_step", "dqo_fit_dual_quadric"]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("z_near", ctypes.c_double),
+                ("dilation", ctypes.c_double), ("q_max", ctypes.c_double), ("alpha_min", ctypes.c_double),
+                ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double), ("bg", ctypes.c_double * 3)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3), ("fx", ctypes.c_double),
+                ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class FrameDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_views", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("pair_capacity", ctypes.c_int64), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64 * 12), ("bytes", ctypes.c_int64 * 12), ("total", ctypes.c_int64),
+                ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32), ("pair_key_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Images(ctypes.Structure):
+    _fields_ = [("color", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("t_final", ctypes.c_void_p),
+                ("last", ctypes.c_void_p), ("probs", ctypes.c_void_p), ("id_map", ctypes.c_void_p),
+                ("target", ctypes.c_void_p), ("p_target", ctypes.c_void_p), ("n_blend", ctypes.c_void_p)]
+
+
+class ImageGrads(ctypes.Structure):
+    _fields_ = [("d_color", ctypes.c_void_p), ("d_depth", ctypes.c_void_p), ("d_t_final", ctypes.c_void_p),
+                ("d_probs", ctypes.c_void_p), ("d_p_target", ctypes.c_void_p)]
+
+
+class Targets(ctypes.Structure):
+    _fields_ = [("color", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("id", ctypes.c_void_p)]
+
+
+class LossWeights(ctypes.Structure):
+    _fields_ = [("w_rgb", ctypes.c_double), ("w_depth", ctypes.c_double), ("lam", ctypes.c_double),
+                ("ce_eps", ctypes.c_double)]
+
+
+class AdamParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double * NUM_PARAMS), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
+class DqoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdqo error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdqo.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"{LIBPATH} is missing: build it with paper_2503_02223_amd/build.py "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    L = ctypes.CDLL(LIBPATH)
+    P, vp, i32, i64, d = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    ctx = vp
+    L.dqo_config_default.argtypes = [P(Config)]
+    L.dqo_config_default.restype = None
+    L.dqo_ctx_create.argtypes = [P(vp), P(Config)]
+    L.dqo_ctx_destroy.argtypes = [ctx]
+    L.dqo_last_error.argtypes = [ctx]
+    L.dqo_last_error.restype = ctypes.c_char_p
+    L.dqo_status_string.argtypes = [ctypes.c_int]
+    L.dqo_status_string.restype = ctypes.c_char_p
+    L.dqo_version.restype = ctypes.c_char_p
+    fr = [ctx, P(FrameDesc), P(Camera)]
+    L.dqo_state_layout.argtypes = fr + [P(Layout)]
+    L.dqo_state_init.argtypes = fr + [vp, vp]
+    L.dqo_read_status.argtypes = fr + [vp, P(ctypes.c_uint32), P(i64), vp]
+    L.dqo_clear_status.argtypes = fr + [vp, vp]
+    L.dqo_project_cull_bin.argtypes = fr + [vp, vp, vp, vp]
+    L.dqo_sort.argtypes = fr + [vp, vp]
+    L.dqo_render_forward.argtypes = fr + [vp, P(Images), vp]
+    L.dqo_object_loss.argtypes = fr + [P(Images), P(Targets), P(LossWeights), vp, P(ImageGrads), vp, vp]
+    L.dqo_render_backward.argtypes = fr + [vp, P(Images), P(ImageGrads), vp]
+    L.dqo_project_backward.argtypes = fr + [vp, vp, vp, vp]
+    L.dqo_adam_step.argtypes = [ctx, i32, vp, vp, vp, vp, i64, P(AdamParams), i64, vp]
+    L.dqo_fit_dual_quadric.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp]
+    for f in EXPORTED:
+        if f not in ("dqo_config_default", "dqo_last_error", "dqo_status_string", "dqo_version"):
+            getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def default_config(**kw) -> Config:
+    c = Config()
+    lib().dqo_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        if k == "bg":
+            for i in range(3):
+                c.bg[i] = float(v[i])
+        else:
+            setattr(c, k, v)
+    return c
+
+
+class Context:
+    """A libdqo context (host-side configuration and error text)."""
+
+    def __init__(self, config: Optional[Config] = None, **kw):
+        cfg = config if config is not None else default_config(**kw)
+        h = ctypes.c_void_p()
+        rc = lib().dqo_ctx_create(ctypes.byref(h), ctypes.byref(cfg))
+        if rc != OK:
+            raise DqoError(rc, "dqo_ctx_create rejected the configuration")
+        self.h = h
+        self.config = cfg
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dqo_ctx_destroy(self.h)
+            self.h = None
+
+    def check(self, rc):
+        if rc != OK:
+            raise DqoError(rc, lib().dqo_last_error(self.h).decode())
+        return rc
+
+
+def make_cameras(cams: Sequence[dict]):
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        R = np.asarray(c["R"], np.float64).reshape(9)
+        t = np.asarray(c["t"], np.float64).reshape(3)
+        for k in range(9):
+            arr[i].R[k] = float(R[k])
+        for k in range(3):
+            arr[i].t[k] = float(t[k])
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = (float(c[k]) for k in ("fx", "fy", "cx", "cy"))
+        arr[i].width, arr[i].height = int(c["width"]), int(c["height"])
+    return arr
+
+
+_TORCH_DT = {F32: torch.float32, F64: torch.float64}
+
+
+class Frame:
+    """Caller-owned device state of one frame of work (n Gaussians, V views)."""
+
+    def __init__(self, ctx: Context, cams: Sequence[dict], n: int, K: int, capacity: int,
+                 dtype=torch.float32, device="cuda"):
+        self.ctx = ctx
+        self.cam_dicts = list(cams)
+        self.cams = make_cameras(cams)
+        self.dt = F64 if dtype == torch.float64 else F32
+        self.tdtype = dtype
+        self.device = torch.device(device)
+        self.desc = FrameDesc(n=int(n), n_views=len(cams), K=int(K), pair_capacity=int(capacity), dtype=self.dt)
+        self.layout = Layout()
+        ctx.check(lib().dqo_state_layout(ctx.h, ctypes.byref(self.desc), self.cams, ctypes.byref(self.layout)))
+        self.state = torch.empty(int(self.layout.total), dtype=torch.uint8, device=self.device)
+        ctx.check(lib().dqo_state_init(ctx.h, ctypes.byref(self.desc), self.cams, _ptr(self.state), _stream()))
+        self.W, self.H = int(cams[0]["width"]), int(cams[0]["height"])
+        self.V = len(cams)
+        self.n, self.K, self.capacity = int(n), int(K), int(capacity)
+
+    # -- views on the state buffer (for tests and diagnostics) --
+    def buf(self, name: str, dtype=torch.int32, count: Optional[int] = None) -> torch.Tensor:
+        i = BUF_NAMES.index(name)
+        off, nb = int(self.layout.offset[i]), int(self.layout.bytes[i])
+        item = torch.empty((), dtype=dtype).element_size()
+        cnt = nb // item if count is None else count
+        return self.state[off:off + cnt * item].view(dtype)
+
+    def _fr(self):
+        return (self.ctx.h, ctypes.byref(self.desc), self.cams)
+
+    def project_cull_bin(self, params: torch.Tensor, ids: torch.Tensor, stream=None):
+        assert params.dtype == self.tdtype and params.shape == (NUM_PARAMS, self.n)
+        assert ids.dtype == torch.int32 and ids.shape == (self.n,)
+        self.ctx.check(lib().dqo_project_cull_bin(*self._fr(), _ptr(params), _ptr(ids), _ptr(self.state),
+                                                  _stream(stream)))
+
+    def sort(self, stream=None):
+        self.ctx.check(lib().dqo_sort(*self._fr(), _ptr(self.state), _stream(stream)))
+
+    def read_status(self, stream=None):
+        st = ctypes.c_uint32()
+        npairs = ctypes.c_int64()
+        rc = lib().dqo_read_status(*self._fr(), _ptr(self.state), ctypes.byref(st), ctypes.byref(npairs),
+                                   _stream(stream))
+        return rc, int(st.value), int(npairs.value)
+
+    def clear_status(self, stream=None):
+        self.ctx.check(lib().dqo_clear_status(*self._fr(), _ptr(self.state), _stream(stream)))
+
+    def new_images(self, probs=False, id_map=False, target: Optional[torch.Tensor] = None,
+                   n_blend=False) -> Dict[str, torch.Tensor]:
+        V, H, W, dt, dev = self.V, self.H, self.W, self.tdtype, self.device
+        img = dict(color=torch.empty(V, 3, H, W, dtype=dt, device=dev), depth=torch.empty(V, H, W, dtype=dt, device=dev),
+                   t_final=torch.empty(V, H, W, dtype=dt, device=dev),
+                   last=torch.empty(V, H, W, dtype=torch.int32, device=dev))
+        if probs:
+            img["probs"] = torch.empty(V, self.K, H, W, dtype=dt, device=dev)
+        if id_map:
+            img["id_map"] = torch.empty(V, H, W, dtype=torch.int32, device=dev)
+        if target is not None:
+            img["target"] = target
+            img["p_target"] = torch.empty(V, H, W, dtype=dt, device=dev)
+        if n_blend:
+            img["n_blend"] = torch.empty(V, H, W, dtype=torch.int32, device=dev)
+        return img
+
+    @staticmethod
+    def _images(img: Dict[str, torch.Tensor]) -> Images:
+        return Images(*(_ptr(img.get(k)) for k in ("color", "depth", "t_final", "last", "probs", "id_map",
+                                                   "target", "p_target", "n_blend")))
+
+    def render_forward(self, img: Dict[str, torch.Tensor], stream=None):
+        s = Frame._images(img)
+        self.ctx.check(lib().dqo_render_forward(*self._fr(), _ptr(self.state), ctypes.byref(s), _stream(stream)))
+
+    def object_loss(self, img, tgt: Dict[str, torch.Tensor], grads: Optional[Dict[str, torch.Tensor]], loss: torch.Tensor,
+                    w_rgb=1.0, w_depth=1.0, lam=1.0, ce_eps=1e-6, stream=None):
+        s = Frame._images(img)
+        t = Targets(_ptr(tgt["color"]), _ptr(tgt["depth"]), _ptr(tgt.get("id")))
+        w = LossWeights(w_rgb, w_depth, lam, ce_eps)
+        g = None
+        if grads is not None:
+            g = ctypes.byref(ImageGrads(*(_ptr(grads.get(k)) for k in ("d_color", "d_depth", "d_t_final", "d_probs",
+                                                                      "d_p_target"))))
+        self.ctx.check(lib().dqo_object_loss(*self._fr(), ctypes.byref(s), ctypes.byref(t), ctypes.byref(w),
+                                             _ptr(loss), g, _ptr(self.state), _stream(stream)))
+
+    def render_backward(self, img, grads: Dict[str, torch.Tensor], stream=None):
+        s = Frame._images(img)
+        g = ImageGrads(*(_ptr(grads.get(k)) for k in ("d_color", "d_depth", "d_t_final", "d_probs", "d_p_target")))
+        self.ctx.check(lib().dqo_render_backward(*self._fr(), _ptr(self.state), ctypes.byref(s), ctypes.byref(g),
+                                                 _stream(stream)))
+
+    def project_backward(self, params: torch.Tensor, grads: torch.Tensor, stream=None):
+        self.ctx.check(lib().dqo_project_backward(*self._fr(), _ptr(params), _ptr(self.state), _ptr(grads),
+                                                  _stream(stream)))
+
+
+def adam_step(ctx: Context, params, grads, m, v, lrs, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    hp = AdamParams()
+    for k in range(NUM_PARAMS):
+        hp.lr[k] = float(lrs[k])
+    hp.beta1, hp.beta2, hp.eps = beta1, beta2, eps
+    dt = F64 if params.dtype == torch.float64 else F32
+    ctx.check(lib().dqo_adam_step(ctx.h, dt, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.shape[-1],
+                                  ctypes.byref(hp), int(step), _stream(stream)))
+
+
+def fit_dual_quadric(ctx: Context, boxes, box_obj, box_view, Ps, n_obj, img_wh=None, border=1.0, stream=None):
+    """Device tensors in, device tensors out (see dqo_fit_dual_quadric)."""
+    dev = boxes.device
+    Q = torch.empty(n_obj, 4, 4, dtype=torch.float64, device=dev)
+    mu = torch.empty(n_obj, 3, dtype=torch.float64, device=dev)
+    R = torch.empty(n_obj, 3, 3, dtype=torch.float64, device=dev)
+    axes = torch.empty(n_obj, 3, dtype=torch.float64, device=dev)
+    status = torch.empty(n_obj, dtype=torch.int32, device=dev)
+    ctx.check(lib().dqo_fit_dual_quadric(ctx.h, int(n_obj), int(boxes.shape[0]), _ptr(boxes), _ptr(box_obj),
+                                         _ptr(box_view), int(Ps.shape[0]), _ptr(Ps), _ptr(img_wh), float(border),
+                                         _ptr(Q), _ptr(mu), _ptr(R), _ptr(axes), _ptr(status), _stream(stream)))
+    return dict(Q=Q, mu=mu, R=R, axes=axes, status=status)
+
+
+# ------------------------------------------------------------------ helpers
+def default_lrs(scene_extent: float = 1.0):
+    """Per-row learning rates: mean 1.6e-4 * extent, log-scale 5e-3, quaternion
+    1e-3, opacity logit 5e-2, colour 2.5e-3."""
+    return [1.6e-4 * scene_extent] * 3 + [5e-3] * 3 + [1e-3] * 4 + [5e-2] + [2.5e-3] * 3
+
+
+class Rasterizer:
+    """Frame + image buffers for a fixed camera set, with capacity management."""
+
+    def __init__(self, cams: Sequence[dict], n: int, K: int, capacity: Optional[int] = None,
+                 dtype=torch.float32, ctx: Optional[Context] = None, device="cuda"):
+        self.ctx = ctx if ctx is not None else Context()
+        self.cams, self.n, self.K, self.dtype, self.device = list(cams), int(n), int(K), dtype, device
+        cap = capacity if capacity is not None else max(1024, 4 * n * len(cams))
+        self.frame = Frame(self.ctx, self.cams, n, K, min(cap, 1 << 30), dtype, device)
+
+    def bin(self, params, ids, grow=True, stream=None):
+        """project_cull_bin + sort; when grow is set, checks the pair count (a
+        host synchronisation) and re-runs with a larger pair list on overflow."""
+        f = self.frame
+        f.project_cull_bin(params, ids, stream)
+        if grow:
+            rc, st, npairs = f.read_status(stream)
+            if st & STATUS_OVERFLOW:
+                cap = min(1 << 30, int(math.ceil(npairs * 1.25)) + 1024)
+                self.frame = f = Frame(self.ctx, self.cams, self.n, self.K, cap, self.dtype, self.device)
+                f.project_cull_bin(params, ids, stream)
+                rc, st, npairs = f.read_status(stream)
+            if st & STATUS_TIMEOUT:
+                raise DqoError(EINTERNAL, "device wait bound exceeded")
+        f.sort(stream)
+
+    def forward(self, params, ids, probs=False, id_map=False, target=None, stream=None, grow=True, n_blend=False):
+        self.bin(params, ids, grow=grow, stream=stream)
+        img = self.frame.new_images(probs=probs, id_map=id_map, target=target, n_blend=n_blend)
+        self.frame.render_forward(img, stream)
+        return img
+
+    def backward(self, params, img, grads, stream=None):
+        f = self.frame
+        f.render_backward(img, grads, stream)
+        out = torch.empty_like(params)
+        f.project_backward(params, out, stream)
+        return out
+
+
+class RasterizeFunction(torch.autograd.Function):
+    """Differentiable render of (colour, depth, T_final, instance channels)
+    with respect to the Gaussian parameters [14][n].  Backward recomputes the
+    transmittance per pixel from T_final instead of storing per-pixel lists."""
+
+    @staticmethod
+    def forward(ctx, params, ids, rasterizer: Rasterizer, want_probs: bool = True):
+        p = params.detach().contiguous()
+        img = rasterizer.forward(p, ids, probs=want_probs and rasterizer.K > 0)
+        ctx.rasterizer = rasterizer
+        ctx.img = img
+        ctx.want_probs = want_probs and rasterizer.K > 0
+        ctx.save_for_backward(p)
+        probs = img["probs"] if ctx.want_probs else img["color"].new_zeros(0)
+        return img["color"], img["depth"], img["t_final"], probs
+
+    @staticmethod
+    def backward(ctx, d_color, d_depth, d_t_final, d_probs):
+        (p,) = ctx.saved_tensors
+        r: Rasterizer = ctx.rasterizer
+        z = lambda t, like: (t.contiguous() if t is not None else torch.zeros_like(like))
+        grads = dict(d_color=z(d_color, ctx.img["color"]), d_depth=z(d_depth, ctx.img["depth"]),
+                     d_t_final=z(d_t_final, ctx.img["t_final"]))
+        if ctx.want_probs and d_probs is not None:
+            grads["d_probs"] = d_probs.contiguous()
+        g = r.backward(p, ctx.img, grads)
+        return g, None, None, None
+
+
+def rasterize(params, ids, rasterizer: Rasterizer, want_probs=True):
+    return RasterizeFunction.apply(params, ids, rasterizer, want_probs)
+
+
+class Trainer:
+    """The timed training iteration: project/bin, sort, render forward (loss
+    mode: probability of each pixel's target object), object loss, render
+    backward, project backward and Adam, all as libdqo calls on one stream
+    with preallocated buffers and no host synchronisation."""
+
+    def __init__(self, params: torch.Tensor, ids: torch.Tensor, cams, K, targets: Dict[str, torch.Tensor],
+                 lrs=None, capacity=None, loss_weights=(1.0, 1.0, 1.0), ctx=None):
+        self.params = params.contiguous()
+        self.ids = ids
+        self.n = params.shape[1]
+        self.dtype = params.dtype
+        self.r = Rasterizer(cams, self.n, K, capacity=capacity, dtype=self.dtype, ctx=ctx)
+        self.r.bin(self.params, ids, grow=True)  # sizes the pair list once
+        if self.r.frame.capacity < (1 << 30):   # headroom for pairs added while training
+            cap = min(1 << 30, int(self.r.frame.read_status()[2] * 1.5) + 4096)
+            if cap > self.r.frame.capacity:
+                self.r.frame = Frame(self.r.ctx, self.r.cams, self.n, K, cap, self.dtype, params.device)
+                self.r.bin(self.params, ids, grow=True)
+        f = self.r.frame
+        self.targets = targets
+        self.img = f.new_images(target=targets["id"])
+        dev = params.device
+        V, H, W = f.V, f.H, f.W
+        self.grads_img = dict(d_color=torch.empty(V, 3, H, W, dtype=self.dtype, device=dev),
+                              d_depth=torch.empty(V, H, W, dtype=self.dtype, device=dev),
+                              d_p_target=torch.empty(V, H, W, dtype=self.dtype, device=dev))
+        self.grads = torch.empty_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.loss = torch.zeros(4, dtype=torch.float64, device=dev)
+        self.lrs = lrs if lrs is not None else default_lrs()
+        self.lw = loss_weights
+        self.step_count = 0
+
+    def step(self, stream=None):
+        f = self.r.frame
+        f.project_cull_bin(self.params, self.ids, stream)
+        f.sort(stream)
+        f.render_forward(self.img, stream)
+        f.object_loss(self.img, self.targets, self.grads_img, self.loss, *self.lw, stream=stream)
+        f.render_backward(self.img, self.grads_img, stream)
+        f.project_backward(self.params, self.grads, stream)
+        self.step_count += 1
+        adam_step(self.r.ctx, self.params, self.grads, self.m, self.v, self.lrs, self.step_count, stream=stream)
+
+    def check(self):
+        rc, st, npairs = self.r.frame.read_status()
+        if st & (STATUS_OVERFLOW | STATUS_TIMEOUT):
+            raise DqoError(ECAPACITY if st & STATUS_OVERFLOW else EINTERNAL,
+                           f"status {st}, pairs {npairs}, capacity {self.r.frame.capacity}")
+        return npairs

@@ -1,0 +1,477 @@
+// Host side of the C ABI: argument validation (before any launch), the state
+// buffer layout, and the launch sequence of each call.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "dqo_device.hpp"
+
+struct dqo_ctx {
+    dqo_config cfg;
+    mutable char err[512];
+};
+
+namespace {
+
+using namespace dqo;
+
+int fail(const dqo_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof(c->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+int hip_fail(const dqo_ctx* c, hipError_t e, const char* where) {
+    return fail(c, DQO_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool tile_ok(int tw, int th) {
+    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 32 && th == 8) ||
+           (tw == 8 && th == 32);
+}
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+int key_bits(int64_t tiles_total) {
+    int b = 0;
+    while (b < 32 && (tiles_total - 1) >> b) ++b;
+    return b;
+}
+
+struct Geo {
+    dqo_layout L;
+    int64_t items;
+    int depth_blocks, scan_blocks, pair_blocks, pair_passes, pair_first_buf;
+    int64_t lb_words;
+    // scratch sub-offsets (relative to DQO_BUF_SCRATCH)
+    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_lbd, off_lbs, off_lbp;
+};
+
+int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams) {
+    if (!ctx) return DQO_EINVAL;
+    if (!d || !cams) return fail(ctx, DQO_EINVAL, "frame descriptor and cameras must not be NULL");
+    if (d->dtype != DQO_F32 && d->dtype != DQO_F64) return fail(ctx, DQO_EINVAL, "dtype %d unknown", d->dtype);
+    if (d->n < 0) return fail(ctx, DQO_EINVAL, "n = %lld < 0", (long long)d->n);
+    if (d->n_views < 1 || d->n_views > DQO_MAX_VIEWS)
+        return fail(ctx, DQO_EINVAL, "n_views = %d outside [1, %d]", d->n_views, DQO_MAX_VIEWS);
+    if (d->K < 0 || d->K > DQO_MAX_K) return fail(ctx, DQO_EINVAL, "K = %d outside [0, %d]", d->K, DQO_MAX_K);
+    if (d->pair_capacity < 0 || d->pair_capacity > (int64_t(1) << 30))
+        return fail(ctx, DQO_EINVAL, "pair_capacity = %lld outside [0, 2^30]", (long long)d->pair_capacity);
+    if ((int64_t)d->n * d->n_views > (int64_t(1) << 31) - 1)
+        return fail(ctx, DQO_EINVAL, "n * n_views must be < 2^31");
+    const int W = cams[0].width, H = cams[0].height;
+    if (W < 1 || H < 1 || W > 32767 || H > 32767) return fail(ctx, DQO_EINVAL, "image size %dx%d invalid", W, H);
+    for (int v = 0; v < d->n_views; ++v) {
+        const dqo_camera& c = cams[v];
+        if (c.width != W || c.height != H) return fail(ctx, DQO_EINVAL, "all views must share width and height");
+        bool fin = isfinite(c.fx) && isfinite(c.fy) && isfinite(c.cx) && isfinite(c.cy);
+        for (int k = 0; k < 9; ++k) fin = fin && isfinite(c.R[k]);
+        for (int k = 0; k < 3; ++k) fin = fin && isfinite(c.t[k]);
+        if (!fin) return fail(ctx, DQO_EINVAL, "camera %d has non-finite entries", v);
+    }
+    if (!tile_ok(ctx->cfg.tile_w, ctx->cfg.tile_h))
+        return fail(ctx, DQO_EINVAL, "tile %dx%d not supported", ctx->cfg.tile_w, ctx->cfg.tile_h);
+    return DQO_OK;
+}
+
+Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams) {
+    Geo g;
+    memset(&g, 0, sizeof(g));
+    const int tw = ctx->cfg.tile_w, th = ctx->cfg.tile_h;
+    const int W = cams[0].width, H = cams[0].height;
+    g.L.tiles_x = (W + tw - 1) / tw;
+    g.L.tiles_y = (H + th - 1) / th;
+    const int64_t tiles_total = (int64_t)g.L.tiles_x * g.L.tiles_y * d->n_views;
+    g.L.pair_key_bits = key_bits(tiles_total);
+    g.pair_passes = (g.L.pair_key_bits + kRadixBits - 1) / kRadixBits;
+    g.pair_first_buf = g.pair_passes & 1;
+    g.items = (int64_t)d->n * d->n_views;
+    const int64_t M = g.items, cap = d->pair_capacity;
+    const int64_t ts = d->dtype == DQO_F64 ? 8 : 4;
+    g.depth_blocks = (int)((M + kSortTile - 1) / kSortTile);
+    g.scan_blocks = (int)((M + kScanTile - 1) / kScanTile);
+    g.pair_blocks = (int)((cap + kSortTile - 1) / kSortTile);
+    int64_t sz[DQO_BUF_COUNT];
+    sz[DQO_BUF_SPLATS] = M * kSplatWords * ts;
+    sz[DQO_BUF_RECTS] = M * 8;
+    sz[DQO_BUF_COUNTS] = M * 4;
+    sz[DQO_BUF_OFFSETS] = M * 4;
+    sz[DQO_BUF_DEPTH_KEYS] = M * 4;
+    sz[DQO_BUF_DEPTH_ORDER] = M * 4;
+    sz[DQO_BUF_PAIR_KEYS] = cap * 4;
+    sz[DQO_BUF_PAIR_VALS] = cap * 4;
+    sz[DQO_BUF_RANGES] = tiles_total * 8;
+    sz[DQO_BUF_PARTIALS] = cap * kGradWords * ts;
+    sz[DQO_BUF_CONTROL] = (int64_t)sizeof(Ctrl);
+    int64_t so = 0;
+    g.off_dk1 = so; so = align256(so + M * 4);
+    g.off_dv1 = so; so = align256(so + M * 4);
+    g.off_pk1 = so; so = align256(so + cap * 4);
+    g.off_pv1 = so; so = align256(so + cap * 4);
+    g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * g.depth_blocks * kRadixBins * 8);
+    g.off_lbs = so; so = align256(so + (int64_t)g.scan_blocks * 8);
+    g.off_lbp = so; so = align256(so + (int64_t)kMaxPairPasses * g.pair_blocks * kRadixBins * 8);
+    g.lb_words = (so - g.off_lbd) / 8;
+    sz[DQO_BUF_SCRATCH] = so;
+    int64_t off = 0;
+    for (int b = 0; b < DQO_BUF_COUNT; ++b) {
+        g.L.offset[b] = off;
+        g.L.bytes[b] = sz[b];
+        off = align256(off + sz[b]);
+    }
+    g.L.total = off;
+    return g;
+}
+
+StatePtrs state_ptrs(const Geo& g, void* state) {
+    StatePtrs s;
+    char* b = (char*)state;
+    s.splats = b + g.L.offset[DQO_BUF_SPLATS];
+    s.rects = (short4*)(b + g.L.offset[DQO_BUF_RECTS]);
+    s.counts = (uint32_t*)(b + g.L.offset[DQO_BUF_COUNTS]);
+    s.offsets = (uint32_t*)(b + g.L.offset[DQO_BUF_OFFSETS]);
+    char* sc = b + g.L.offset[DQO_BUF_SCRATCH];
+    s.depth_keys[0] = (uint32_t*)(b + g.L.offset[DQO_BUF_DEPTH_KEYS]);
+    s.depth_vals[0] = (uint32_t*)(b + g.L.offset[DQO_BUF_DEPTH_ORDER]);
+    s.depth_keys[1] = (uint32_t*)(sc + g.off_dk1);
+    s.depth_vals[1] = (uint32_t*)(sc + g.off_dv1);
+    s.pair_keys[0] = (uint32_t*)(b + g.L.offset[DQO_BUF_PAIR_KEYS]);
+    s.pair_vals[0] = (uint32_t*)(b + g.L.offset[DQO_BUF_PAIR_VALS]);
+    s.pair_keys[1] = (uint32_t*)(sc + g.off_pk1);
+    s.pair_vals[1] = (uint32_t*)(sc + g.off_pv1);
+    s.ranges = (uint32_t*)(b + g.L.offset[DQO_BUF_RANGES]);
+    s.partials = b + g.L.offset[DQO_BUF_PARTIALS];
+    s.ctrl = (Ctrl*)(b + g.L.offset[DQO_BUF_CONTROL]);
+    s.lb_depth = (uint64_t*)(sc + g.off_lbd);
+    s.lb_scan = (uint64_t*)(sc + g.off_lbs);
+    s.lb_pair = (uint64_t*)(sc + g.off_lbp);
+    s.items = g.items;
+    s.capacity = g.L.bytes[DQO_BUF_PAIR_KEYS] / 4;
+    s.depth_blocks = g.depth_blocks;
+    s.scan_blocks = g.scan_blocks;
+    s.pair_blocks = g.pair_blocks;
+    s.pair_passes = g.pair_passes;
+    s.pair_first_buf = g.pair_first_buf;
+    return s;
+}
+
+template <typename T>
+Frame<T> make_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const Geo& g, void* state) {
+    Frame<T> f;
+    memset(&f, 0, sizeof(f));
+    const dqo_config& c = ctx->cfg;
+    for (int v = 0; v < d->n_views; ++v) {
+        DevCam<T>& dc = f.views.cam[v];
+        for (int k = 0; k < 9; ++k) dc.R[k] = (T)cams[v].R[k];
+        for (int k = 0; k < 3; ++k) dc.t[k] = (T)cams[v].t[k];
+        dc.fx = (T)cams[v].fx;
+        dc.fy = (T)cams[v].fy;
+        dc.cx = (T)cams[v].cx;
+        dc.cy = (T)cams[v].cy;
+    }
+    f.views.n_views = d->n_views;
+    f.views.W = cams[0].width;
+    f.views.H = cams[0].height;
+    f.views.tile_w = c.tile_w;
+    f.views.tile_h = c.tile_h;
+    f.views.tiles_x = g.L.tiles_x;
+    f.views.tiles_y = g.L.tiles_y;
+    f.views.tiles_per_view = g.L.tiles_x * g.L.tiles_y;
+    f.consts.z_near = (T)c.z_near;
+    f.consts.dilation = (T)c.dilation;
+    f.consts.q_max = (T)c.q_max;
+    f.consts.alpha_min = (T)c.alpha_min;
+    f.consts.alpha_max = (T)c.alpha_max;
+    f.consts.t_min = (T)c.t_min;
+    for (int k = 0; k < 3; ++k) f.consts.bg[k] = (T)c.bg[k];
+    f.n = d->n;
+    f.K = d->K;
+    f.s = state_ptrs(g, state);
+    return f;
+}
+
+int check_images(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_images* img, bool need_probs_ok) {
+    if (!img) return fail(ctx, DQO_EINVAL, "images must not be NULL");
+    if (!img->color || !img->depth || !img->t_final || !img->last)
+        return fail(ctx, DQO_EINVAL, "images: color, depth, t_final and last are required");
+    if (img->probs && d->K < 1) return fail(ctx, DQO_EINVAL, "probs requested with K = 0");
+    if (img->id_map && !img->probs) return fail(ctx, DQO_EINVAL, "id_map needs probs");
+    if (img->p_target && !img->target) return fail(ctx, DQO_EINVAL, "p_target needs target");
+    if (need_probs_ok && img->probs) {
+        const int64_t ts = d->dtype == DQO_F64 ? 8 : 4;
+        if ((int64_t)d->K * ctx->cfg.tile_w * ctx->cfg.tile_h * ts > 65536)
+            return fail(ctx, DQO_EINVAL, "K = %d instance channels do not fit in LDS for this tile and dtype", d->K);
+    }
+    return DQO_OK;
+}
+
+template <typename F>
+int run(const dqo_ctx* ctx, const char* what, F&& fn) {
+    hipError_t e = fn();
+    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    ctx->err[0] = 0;
+    return DQO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dqo_config_default(dqo_config* c) {
+    if (!c) return;
+    c->tile_w = 16;
+    c->tile_h = 16;
+    c->z_near = 0.2;
+    c->dilation = 0.3;
+    c->q_max = 9.0;
+    c->alpha_min = 1.0 / 255.0;
+    c->alpha_max = 0.99;
+    c->t_min = 1e-4;
+    c->bg[0] = c->bg[1] = c->bg[2] = 0.0;
+}
+
+int dqo_ctx_create(dqo_ctx** out, const dqo_config* cfg) {
+    if (!out) return DQO_EINVAL;
+    dqo_config c;
+    dqo_config_default(&c);
+    if (cfg) c = *cfg;
+    if (!tile_ok(c.tile_w, c.tile_h)) return DQO_EINVAL;
+    if (!(c.alpha_min > 0 && c.alpha_max <= 1 && c.alpha_min < c.alpha_max && c.t_min > 0 && c.t_min < 1 &&
+          c.q_max > 0 && c.dilation >= 0 && c.z_near > 0))
+        return DQO_EINVAL;
+    dqo_ctx* x = new dqo_ctx;
+    x->cfg = c;
+    x->err[0] = 0;
+    *out = x;
+    return DQO_OK;
+}
+
+int dqo_ctx_destroy(dqo_ctx* ctx) {
+    delete ctx;
+    return DQO_OK;
+}
+
+const char* dqo_last_error(const dqo_ctx* ctx) { return ctx ? ctx->err : "NULL context"; }
+
+const char* dqo_version(void) { return "dqo 0.1 gfx950"; }
+
+const char* dqo_status_string(int code) {
+    switch (code) {
+        case DQO_OK: return "ok";
+        case DQO_EINVAL: return "invalid argument";
+        case DQO_ECAPACITY: return "pair capacity exceeded";
+        case DQO_ENONFINITE: return "non-finite input";
+        case DQO_EDEGENERATE: return "degenerate input";
+        case DQO_EHIP: return "HIP runtime error";
+        case DQO_EINTERNAL: return "internal device wait bound exceeded";
+        default: return "unknown status";
+    }
+}
+
+int dqo_state_layout(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, dqo_layout* out) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!out) return fail(ctx, DQO_EINVAL, "layout output must not be NULL");
+    *out = geometry(ctx, d, cams).L;
+    return DQO_OK;
+}
+
+int dqo_state_init(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, void* state, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state) return fail(ctx, DQO_EINVAL, "state must not be NULL");
+    Geo g = geometry(ctx, d, cams);
+    StatePtrs s = state_ptrs(g, state);
+    return run(ctx, "state_init", [&] {
+        hipError_t e = launch_clear_ctrl(s.ctrl, s.lb_depth, g.lb_words, (hipStream_t)stream);
+        if (e != hipSuccess) return e;
+        return launch_zero_words(s.ranges, g.L.bytes[DQO_BUF_RANGES] / 4, (hipStream_t)stream);
+    });
+}
+
+int dqo_read_status(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, void* state,
+                    uint32_t* status, int64_t* num_pairs, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state) return fail(ctx, DQO_EINVAL, "state must not be NULL");
+    Geo g = geometry(ctx, d, cams);
+    StatePtrs s = state_ptrs(g, state);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read_status sync");
+    uint32_t h[3];
+    e = hipMemcpy(h, s.ctrl, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read_status copy");
+    if (status) *status = h[0];
+    if (num_pairs) *num_pairs = h[2];
+    if (h[0] & DQO_STATUS_TIMEOUT) return fail(ctx, DQO_EINTERNAL, "a device wait exceeded its bound");
+    if (h[0] & DQO_STATUS_OVERFLOW)
+        return fail(ctx, DQO_ECAPACITY, "pair list needs %u entries, capacity %lld", h[2],
+                    (long long)d->pair_capacity);
+    if (h[0] & DQO_STATUS_NONFINITE) return fail(ctx, DQO_ENONFINITE, "non-finite Gaussian parameters");
+    ctx->err[0] = 0;
+    return DQO_OK;
+}
+
+int dqo_clear_status(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, void* state,
+                     void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state) return fail(ctx, DQO_EINVAL, "state must not be NULL");
+    Geo g = geometry(ctx, d, cams);
+    StatePtrs s = state_ptrs(g, state);
+    return run(ctx, "clear_status", [&] { return launch_clear_status(s.ctrl, (hipStream_t)stream); });
+}
+
+int dqo_project_cull_bin(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const void* params,
+                         const int32_t* ids, void* state, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state || (d->n > 0 && (!params || !ids)))
+        return fail(ctx, DQO_EINVAL, "params, ids and state must not be NULL");
+    Geo g = geometry(ctx, d, cams);
+    if (d->dtype == DQO_F32) {
+        Frame<float> f = make_frame<float>(ctx, d, cams, g, state);
+        return run(ctx, "project_cull_bin", [&] {
+            return launch_project_bin<float>(f, (const float*)params, ids, (hipStream_t)stream);
+        });
+    }
+    Frame<double> f = make_frame<double>(ctx, d, cams, g, state);
+    return run(ctx, "project_cull_bin",
+               [&] { return launch_project_bin<double>(f, (const double*)params, ids, (hipStream_t)stream); });
+}
+
+int dqo_sort(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, void* state, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state) return fail(ctx, DQO_EINVAL, "state must not be NULL");
+    Geo g = geometry(ctx, d, cams);
+    StatePtrs s = state_ptrs(g, state);
+    const int tiles_total = g.L.tiles_x * g.L.tiles_y * d->n_views;
+    return run(ctx, "sort", [&] { return launch_pair_sort(s, tiles_total, (hipStream_t)stream); });
+}
+
+int dqo_render_forward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const void* state,
+                       const dqo_images* img, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state) return fail(ctx, DQO_EINVAL, "state must not be NULL");
+    rc = check_images(ctx, d, img, true);
+    if (rc) return rc;
+    Geo g = geometry(ctx, d, cams);
+    if (d->dtype == DQO_F32) {
+        Frame<float> f = make_frame<float>(ctx, d, cams, g, (void*)state);
+        return run(ctx, "render_forward", [&] { return launch_render_forward<float>(f, *img, (hipStream_t)stream); });
+    }
+    Frame<double> f = make_frame<double>(ctx, d, cams, g, (void*)state);
+    return run(ctx, "render_forward", [&] { return launch_render_forward<double>(f, *img, (hipStream_t)stream); });
+}
+
+int dqo_object_loss(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const dqo_images* img,
+                    const dqo_targets* tgt, const dqo_loss_weights* w, double* loss, const dqo_image_grads* gr,
+                    void* state, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!img || !img->color || !img->depth || !img->p_target)
+        return fail(ctx, DQO_EINVAL, "object_loss needs color, depth and p_target images");
+    if (!tgt || !tgt->color || !tgt->depth) return fail(ctx, DQO_EINVAL, "object_loss needs target color and depth");
+    if (!w || !loss || !state) return fail(ctx, DQO_EINVAL, "weights, loss and state must not be NULL");
+    if (!(w->ce_eps > 0)) return fail(ctx, DQO_EINVAL, "ce_eps must be > 0");
+    if (gr && (!gr->d_color || !gr->d_depth || !gr->d_p_target))
+        return fail(ctx, DQO_EINVAL, "object_loss gradients need d_color, d_depth and d_p_target");
+    dqo_image_grads none;
+    memset(&none, 0, sizeof(none));
+    Geo g = geometry(ctx, d, cams);
+    if (d->dtype == DQO_F32) {
+        Frame<float> f = make_frame<float>(ctx, d, cams, g, state);
+        return run(ctx, "object_loss", [&] {
+            return launch_object_loss<float>(f, *img, *tgt, *w, loss, gr ? *gr : none, (hipStream_t)stream);
+        });
+    }
+    Frame<double> f = make_frame<double>(ctx, d, cams, g, state);
+    return run(ctx, "object_loss", [&] {
+        return launch_object_loss<double>(f, *img, *tgt, *w, loss, gr ? *gr : none, (hipStream_t)stream);
+    });
+}
+
+int dqo_render_backward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, void* state,
+                        const dqo_images* img, const dqo_image_grads* gr, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state) return fail(ctx, DQO_EINVAL, "state must not be NULL");
+    rc = check_images(ctx, d, img, false);
+    if (rc) return rc;
+    if (!gr || !gr->d_color) return fail(ctx, DQO_EINVAL, "render_backward needs d_color");
+    if (gr->d_p_target && !img->target) return fail(ctx, DQO_EINVAL, "d_p_target needs images.target");
+    if (gr->d_probs && d->K < 1) return fail(ctx, DQO_EINVAL, "d_probs with K = 0");
+    Geo g = geometry(ctx, d, cams);
+    if (d->dtype == DQO_F32) {
+        Frame<float> f = make_frame<float>(ctx, d, cams, g, state);
+        return run(ctx, "render_backward",
+                   [&] { return launch_render_backward<float>(f, *img, *gr, (hipStream_t)stream); });
+    }
+    Frame<double> f = make_frame<double>(ctx, d, cams, g, state);
+    return run(ctx, "render_backward",
+               [&] { return launch_render_backward<double>(f, *img, *gr, (hipStream_t)stream); });
+}
+
+int dqo_project_backward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const void* params,
+                         const void* state, void* grads, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state || (d->n > 0 && (!params || !grads)))
+        return fail(ctx, DQO_EINVAL, "params, state and grads must not be NULL");
+    Geo g = geometry(ctx, d, cams);
+    if (d->dtype == DQO_F32) {
+        Frame<float> f = make_frame<float>(ctx, d, cams, g, (void*)state);
+        return run(ctx, "project_backward", [&] {
+            return launch_project_backward<float>(f, (const float*)params, (float*)grads, (hipStream_t)stream);
+        });
+    }
+    Frame<double> f = make_frame<double>(ctx, d, cams, g, (void*)state);
+    return run(ctx, "project_backward", [&] {
+        return launch_project_backward<double>(f, (const double*)params, (double*)grads, (hipStream_t)stream);
+    });
+}
+
+int dqo_adam_step(const dqo_ctx* ctx, int32_t dtype, void* params, const void* grads, void* m, void* v, int64_t n,
+                  const dqo_adam* hp, int64_t step, void* stream) {
+    if (!ctx) return DQO_EINVAL;
+    if (dtype != DQO_F32 && dtype != DQO_F64) return fail(ctx, DQO_EINVAL, "dtype %d unknown", dtype);
+    if (n < 0 || step < 1 || !hp) return fail(ctx, DQO_EINVAL, "need n >= 0, step >= 1 and hyper-parameters");
+    if (n > 0 && (!params || !grads || !m || !v)) return fail(ctx, DQO_EINVAL, "adam buffers must not be NULL");
+    if (!(hp->beta1 >= 0 && hp->beta1 < 1 && hp->beta2 >= 0 && hp->beta2 < 1 && hp->eps >= 0))
+        return fail(ctx, DQO_EINVAL, "adam betas must lie in [0, 1) and eps >= 0");
+    if (dtype == DQO_F32)
+        return run(ctx, "adam", [&] {
+            return launch_adam<float>((float*)params, (const float*)grads, (float*)m, (float*)v, n, *hp, step,
+                                      (hipStream_t)stream);
+        });
+    return run(ctx, "adam", [&] {
+        return launch_adam<double>((double*)params, (const double*)grads, (double*)m, (double*)v, n, *hp, step,
+                                   (hipStream_t)stream);
+    });
+}
+
+int dqo_fit_dual_quadric(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, const double* boxes,
+                         const int32_t* box_obj, const int32_t* box_view, int32_t n_views, const double* P,
+                         const int32_t* img_wh, double border, double* Q, double* mu, double* R, double* axes,
+                         int32_t* status, void* stream) {
+    if (!ctx) return DQO_EINVAL;
+    if (n_obj < 0 || n_boxes < 0 || n_views < 0) return fail(ctx, DQO_EINVAL, "negative size");
+    if (n_boxes > 0 && (!boxes || !box_obj || !box_view || !P || n_views < 1))
+        return fail(ctx, DQO_EINVAL, "boxes, box_obj, box_view and P are required");
+    if (n_obj > 0 && (!Q || !mu || !R || !axes || !status))
+        return fail(ctx, DQO_EINVAL, "quadric outputs must not be NULL");
+    if (n_obj > 65535) return fail(ctx, DQO_EINVAL, "n_obj too large");
+    return run(ctx, "fit_dual_quadric", [&] {
+        return launch_fit_quadric(n_obj, n_boxes, boxes, box_obj, box_view, n_views, P, img_wh, border, Q, mu, R,
+                                  axes, status, (hipStream_t)stream);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,227 @@
+// Device-side helpers and launch interfaces shared by the libdqo translation
+// units.  gfx950 (CDNA4) only: wave64, 160 KiB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dqo.h"
+
+namespace dqo {
+
+constexpr int kWave = 64;
+constexpr int kParams = DQO_NUM_PARAMS;
+constexpr int kSplatWords = 12;   // mx,my,A,B,C,o,z,id,r,g,b,pad
+constexpr int kGradWords = 10;    // dmx,dmy,dA,dB,dC,do,dr,dg,db,dz
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortIpt = 8;                             // items per thread in a radix pass
+constexpr int kSortTile = kSortThreads * kSortIpt;      // 2048 items per block
+constexpr int kScanThreads = 256;
+constexpr int kScanIpt = 4;
+constexpr int kScanTile = kScanThreads * kScanIpt;      // 1024 items per block
+constexpr int kMaxDepthPasses = 4;
+constexpr int kMaxPairPasses = 4;
+constexpr int kLossBlocks = 512;
+
+// Counter slots in the control block (dynamic block index per look-back chain).
+constexpr int kCounterDepth = 0;   // + pass
+constexpr int kCounterScan = 4;
+constexpr int kCounterPair = 5;    // + pass
+constexpr int kNumCounters = 16;
+
+// Control block at the start of DQO_BUF_CONTROL.
+struct Ctrl {
+    uint32_t status;
+    uint32_t epoch;
+    uint32_t num_pairs;   // total pairs requested (may exceed the capacity)
+    uint32_t n_valid;     // valid-depth pixel count of the last loss
+    uint32_t counters[kNumCounters];
+    uint32_t hist_depth[kMaxDepthPasses][kRadixBins];
+    uint32_t hist_pair[kMaxPairPasses][kRadixBins];
+    double loss_partials[kLossBlocks][4];
+};
+
+template <typename T>
+struct DevCam {
+    T R[9];
+    T t[3];
+    T fx, fy, cx, cy;
+};
+
+// Everything a kernel needs to know about the views (passed by value).
+template <typename T>
+struct Views {
+    DevCam<T> cam[DQO_MAX_VIEWS];
+    int n_views;
+    int W, H;
+    int tile_w, tile_h;
+    int tiles_x, tiles_y;
+    int tiles_per_view;
+};
+
+template <typename T>
+struct Consts {
+    T z_near, dilation, q_max, alpha_min, alpha_max, t_min;
+    T bg[3];
+};
+
+// Look-back words: [flag:2 | epoch:30 | value:32].
+constexpr uint64_t kFlagAggregate = 1ull;
+constexpr uint64_t kFlagInclusive = 2ull;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ uint64_t lb_pack(uint64_t flag, uint32_t epoch, uint32_t value) {
+    return (flag << 62) | ((uint64_t)(epoch & 0x3fffffffu) << 32) | value;
+}
+__device__ __forceinline__ uint32_t lb_flag(uint64_t w, uint32_t epoch) {
+    return ((uint32_t)(w >> 32) & 0x3fffffffu) == (epoch & 0x3fffffffu) ? (uint32_t)(w >> 62) : 0u;
+}
+__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of `slot` over the chain 0..slot-1 (decoupled look-back).
+// Publishes the aggregate first, then the inclusive value.  Every wait is
+// bounded: on timeout the status bit is set and the partial sum is used.
+__device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* words, int stride, int slot, uint32_t agg,
+                                                       uint32_t epoch, uint32_t* status) {
+    if (slot == 0) {
+        lb_store(words, lb_pack(kFlagInclusive, epoch, agg));
+        return 0u;
+    }
+    lb_store(words + (size_t)slot * stride, lb_pack(kFlagAggregate, epoch, agg));
+    uint32_t excl = 0;
+    int j = slot - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        uint64_t w = lb_load(words + (size_t)j * stride);
+        uint32_t f = lb_flag(w, epoch);
+        if (f == 0) {
+            if (++spins > kSpinLimit) {
+                atomicOr(status, (uint32_t)DQO_STATUS_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += (uint32_t)w;
+        if (f == kFlagInclusive) break;
+        --j;
+    }
+    lb_store(words + (size_t)slot * stride, lb_pack(kFlagInclusive, epoch, excl + agg));
+    return excl;
+}
+
+// Tile index of this block, remapped so that each of the 8 XCDs (which take
+// blocks round-robin) works on one contiguous run of tiles and keeps their
+// shared splat records in its own L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int xcd = b & 7, k = b >> 3;
+    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
+}
+
+template <typename T>
+__device__ __forceinline__ T fast_exp(T x);
+template <>
+__device__ __forceinline__ float fast_exp<float>(float x) { return __expf(x); }
+template <>
+__device__ __forceinline__ double fast_exp<double>(double x) { return exp(x); }
+
+template <typename T>
+__device__ __forceinline__ T id_to_word(int id);
+template <>
+__device__ __forceinline__ float id_to_word<float>(int id) { return __int_as_float(id); }
+template <>
+__device__ __forceinline__ double id_to_word<double>(int id) { return (double)id; }
+
+template <typename T>
+__device__ __forceinline__ int word_to_id(T w);
+template <>
+__device__ __forceinline__ int word_to_id<float>(float w) { return __float_as_int(w); }
+template <>
+__device__ __forceinline__ int word_to_id<double>(double w) { return (int)w; }
+
+// Quaternion (normalised, w,x,y,z) to rotation matrix, row-major.
+template <typename T>
+__device__ __forceinline__ void quat_rot(T w, T x, T y, T z, T R[9]) {
+    R[0] = T(1) - T(2) * (y * y + z * z);
+    R[1] = T(2) * (x * y - w * z);
+    R[2] = T(2) * (x * z + w * y);
+    R[3] = T(2) * (x * y + w * z);
+    R[4] = T(1) - T(2) * (x * x + z * z);
+    R[5] = T(2) * (y * z - w * x);
+    R[6] = T(2) * (x * z - w * y);
+    R[7] = T(2) * (y * z + w * x);
+    R[8] = T(1) - T(2) * (x * x + y * y);
+}
+
+}  // namespace dqo
+
+// ---- launchers (host functions defined in the .hip files) -------------------
+namespace dqo {
+
+struct StatePtrs {
+    void* splats;
+    short4* rects;
+    uint32_t* counts;
+    uint32_t* offsets;
+    uint32_t* depth_keys[2];
+    uint32_t* depth_vals[2];
+    uint32_t* pair_keys[2];
+    uint32_t* pair_vals[2];
+    uint32_t* ranges;
+    void* partials;
+    Ctrl* ctrl;
+    uint64_t* lb_depth;   // [kMaxDepthPasses][blocks][256]
+    uint64_t* lb_scan;    // [blocks]
+    uint64_t* lb_pair;    // [kMaxPairPasses][blocks][256]
+    int64_t items;        // V * n
+    int64_t capacity;
+    int depth_blocks;     // radix blocks over items
+    int scan_blocks;
+    int pair_blocks;      // radix blocks over capacity
+    int pair_passes;
+    int pair_first_buf;   // buffer emission writes into so the sort ends in buffer 0
+};
+
+template <typename T>
+struct Frame {
+    Views<T> views;
+    Consts<T> consts;
+    int64_t n;
+    int K;
+    StatePtrs s;
+};
+
+template <typename T>
+hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t* ids, hipStream_t st);
+hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st);
+template <typename T>
+hipError_t launch_render_forward(const Frame<T>& f, const dqo_images& img, hipStream_t st);
+template <typename T>
+hipError_t launch_render_backward(const Frame<T>& f, const dqo_images& img, const dqo_image_grads& g,
+                                  hipStream_t st);
+template <typename T>
+hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads, hipStream_t st);
+template <typename T>
+hipError_t launch_object_loss(const Frame<T>& f, const dqo_images& img, const dqo_targets& tgt,
+                              const dqo_loss_weights& w, double* loss, const dqo_image_grads& g,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, const dqo_adam& hp, int64_t step,
+                       hipStream_t st);
+hipError_t launch_fit_quadric(int n_obj, int64_t n_boxes, const double* boxes, const int32_t* box_obj,
+                              const int32_t* box_view, int n_views, const double* P, const int32_t* img_wh,
+                              double border, double* Q, double* mu, double* R, double* axes,
+                              int32_t* status, hipStream_t st);
+hipError_t launch_clear_ctrl(Ctrl* ctrl, uint64_t* lb, int64_t lb_words, hipStream_t st);
+hipError_t launch_clear_status(Ctrl* ctrl, hipStream_t st);
+hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t st);
+
+}  // namespace dqo

@@ -1,0 +1,447 @@
+// Projection, culling and binning of Gaussians into pixel tiles, and the chain
+// rule back through the projection.
+//
+// Each (view, Gaussian) item is projected with the EWA splatting model the
+// method inherits from 3D Gaussian Splatting: the 3D covariance
+// R diag(s^2) R^T of the Gaussian (the quadric shape of Eq. (2)) is pushed
+// through the perspective Jacobian, a 0.3 px^2 dilation is added, and its
+// inverse (the conic) is stored with the 2D mean, opacity, depth and colour in
+// one 12-word record so that the render kernels gather one record per pair.
+//
+// Binning is factorised: items are first sorted by depth (4 radix passes over
+// the float bits of z), then each item's tile pairs are emitted in depth order
+// by a scan over the sorted items; a later stable sort by tile id then yields
+// the (tile, depth, index) order with far fewer bytes than sorting 64-bit
+// (tile, depth) keys over all pairs.
+#include "dqo_device.hpp"
+#include "sort_common.hpp"
+
+namespace dqo {
+
+__global__ void prep_kernel(Ctrl* ctrl) {
+    const int t = threadIdx.x;
+    if (t == 0) ctrl->epoch = ctrl->epoch + 1u;
+    if (t < kNumCounters) ctrl->counters[t] = 0u;
+    for (int p = 0; p < kMaxDepthPasses; ++p) ctrl->hist_depth[p][t] = 0u;
+    for (int p = 0; p < kMaxPairPasses; ++p) ctrl->hist_pair[p][t] = 0u;
+    if (t == 0) ctrl->num_pairs = 0u;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_splat(T* dst, const T (&w)[kSplatWords]) {
+#pragma unroll
+    for (int k = 0; k < kSplatWords; ++k) dst[k] = w[k];
+}
+template <>
+__device__ __forceinline__ void store_splat<float>(float* dst, const float (&w)[kSplatWords]) {
+    float4* d = reinterpret_cast<float4*>(dst);
+    d[0] = make_float4(w[0], w[1], w[2], w[3]);
+    d[1] = make_float4(w[4], w[5], w[6], w[7]);
+    d[2] = make_float4(w[8], w[9], w[10], w[11]);
+}
+
+template <typename T>
+struct Proj {
+    T x, y, z;        // camera-frame mean
+    T R[9];           // rotation of the normalised quaternion
+    T qn[4], qnorm;
+    T s[3];           // scales
+    T U[6];           // J W R diag(s) (2x3)
+    T s00, s01, s11;  // 2D covariance incl. dilation
+    T det;
+    T A, B, C;        // conic
+    T mx, my;
+    T o;
+    bool visible;
+};
+
+template <typename T>
+__device__ __forceinline__ void project_item(const DevCam<T>& c, const Consts<T>& cs, const T (&p)[kParams],
+                                             Proj<T>& r) {
+    const T* W = c.R;
+    r.x = W[0] * p[0] + W[1] * p[1] + W[2] * p[2] + c.t[0];
+    r.y = W[3] * p[0] + W[4] * p[1] + W[5] * p[2] + c.t[1];
+    r.z = W[6] * p[0] + W[7] * p[1] + W[8] * p[2] + c.t[2];
+    r.o = T(1) / (T(1) + exp(-p[10]));
+    r.qnorm = sqrt(p[6] * p[6] + p[7] * p[7] + p[8] * p[8] + p[9] * p[9]);
+    const T inv = T(1) / r.qnorm;
+    r.qn[0] = p[6] * inv; r.qn[1] = p[7] * inv; r.qn[2] = p[8] * inv; r.qn[3] = p[9] * inv;
+    quat_rot(r.qn[0], r.qn[1], r.qn[2], r.qn[3], r.R);
+    r.s[0] = exp(p[3]); r.s[1] = exp(p[4]); r.s[2] = exp(p[5]);
+    r.visible = r.z > cs.z_near;
+    if (!r.visible) return;
+    const T iz = T(1) / r.z;
+    const T j00 = c.fx * iz, j02 = -c.fx * r.x * iz * iz;
+    const T j11 = c.fy * iz, j12 = -c.fy * r.y * iz * iz;
+    T T2[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T2[k] = j00 * W[k] + j02 * W[6 + k];
+        T2[3 + k] = j11 * W[3 + k] + j12 * W[6 + k];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            r.U[a * 3 + b] = (T2[a * 3 + 0] * r.R[0 + b] + T2[a * 3 + 1] * r.R[3 + b] + T2[a * 3 + 2] * r.R[6 + b]) * r.s[b];
+    r.s00 = r.U[0] * r.U[0] + r.U[1] * r.U[1] + r.U[2] * r.U[2] + cs.dilation;
+    r.s01 = r.U[0] * r.U[3] + r.U[1] * r.U[4] + r.U[2] * r.U[5];
+    r.s11 = r.U[3] * r.U[3] + r.U[4] * r.U[4] + r.U[5] * r.U[5] + cs.dilation;
+    r.det = r.s00 * r.s11 - r.s01 * r.s01;
+    if (!(r.det > T(0))) { r.visible = false; return; }
+    const T idet = T(1) / r.det;
+    r.A = r.s11 * idet;
+    r.B = -r.s01 * idet;
+    r.C = r.s00 * idet;
+    r.mx = c.fx * r.x * iz + c.cx;
+    r.my = c.fy * r.y * iz + c.cy;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, int64_t n, int64_t M,
+                                                      const T* __restrict__ params, const int32_t* __restrict__ ids,
+                                                      T* __restrict__ splats, short4* __restrict__ rects,
+                                                      uint32_t* __restrict__ counts, uint32_t* __restrict__ dkeys,
+                                                      uint32_t* __restrict__ dvals, Ctrl* ctrl) {
+    __shared__ uint32_t s_hist[kMaxDepthPasses][kRadixBins];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < kMaxDepthPasses; ++p) s_hist[p][tid] = 0u;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    if (i < M) {
+        const int v = (int)(i / n);
+        const int64_t g = i - (int64_t)v * n;
+        T p[kParams];
+        bool finite = true;
+#pragma unroll
+        for (int r = 0; r < kParams; ++r) {
+            p[r] = params[(int64_t)r * n + g];
+            finite = finite && isfinite(p[r]);
+        }
+        if (!finite) atomicOr(&ctrl->status, (uint32_t)DQO_STATUS_NONFINITE);
+        Proj<T> pr;
+        pr.visible = false;
+        if (finite) project_item(V.cam[v], cs, p, pr);
+        uint32_t cnt = 0;
+        short4 rc = make_short4(0, 0, -1, -1);
+        T w[kSplatWords];
+#pragma unroll
+        for (int k = 0; k < kSplatWords; ++k) w[k] = T(0);
+        if (pr.visible) {
+            const T ex = T(3) * sqrt(pr.s00), ey = T(3) * sqrt(pr.s11);
+            T x0 = floor((pr.mx - ex) / T(V.tile_w)), x1 = floor((pr.mx + ex) / T(V.tile_w));
+            T y0 = floor((pr.my - ey) / T(V.tile_h)), y1 = floor((pr.my + ey) / T(V.tile_h));
+            x0 = max(x0, T(0));
+            y0 = max(y0, T(0));
+            x1 = min(x1, T(V.tiles_x - 1));
+            y1 = min(y1, T(V.tiles_y - 1));
+            if (x0 <= x1 && y0 <= y1) {
+                rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
+                cnt = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
+            }
+            w[0] = pr.mx; w[1] = pr.my; w[2] = pr.A; w[3] = pr.B; w[4] = pr.C; w[5] = pr.o; w[6] = pr.z;
+            w[7] = id_to_word<T>(ids[g]);
+            w[8] = p[11]; w[9] = p[12]; w[10] = p[13];
+        }
+        store_splat<T>(splats + i * kSplatWords, w);
+        rects[i] = rc;
+        counts[i] = cnt;
+        const uint32_t key = pr.visible ? __float_as_uint((float)pr.z) : 0xffffffffu;
+        dkeys[i] = key;
+        dvals[i] = (uint32_t)i;
+#pragma unroll
+        for (int ps = 0; ps < kMaxDepthPasses; ++ps) atomicAdd(&s_hist[ps][(key >> (8 * ps)) & 255u], 1u);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ps = 0; ps < kMaxDepthPasses; ++ps) {
+        const uint32_t c = s_hist[ps][tid];
+        if (c) atomicAdd(&ctrl->hist_depth[ps][tid], c);
+    }
+}
+
+// Scan of the tile counts in depth order and emission of (tile, item) pairs.
+__global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts, const short4* __restrict__ rects,
+    uint32_t* __restrict__ offsets, uint32_t* __restrict__ pkeys, uint32_t* __restrict__ pvals, uint32_t M,
+    uint32_t cap, int64_t n, int tiles_x, int tiles_per_view, int pair_passes, uint64_t* lb, Ctrl* ctrl) {
+    __shared__ uint32_t s_incl[kScanTile];
+    __shared__ uint32_t s_rec[kScanTile];
+    __shared__ uint32_t s_hist[kMaxPairPasses][kRadixBins];
+    __shared__ uint32_t s_tmp[kScanThreads / kWave];
+    __shared__ uint32_t s_base, s_bid, s_agg;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_bid = atomicAdd(&ctrl->counters[kCounterScan], 1u);
+#pragma unroll
+    for (int p = 0; p < kMaxPairPasses; ++p) s_hist[p][tid] = 0u;
+    __syncthreads();
+    const uint32_t bid = s_bid;
+    const uint32_t base = bid * (uint32_t)kScanTile;
+    if (base >= M) return;
+    const uint32_t epoch = ctrl->epoch;
+    uint32_t c[kScanIpt], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        const uint32_t q = tid * kScanIpt + k;
+        uint32_t rec = 0xffffffffu, cnt = 0;
+        if (base + q < M) {
+            rec = min(order[base + q], M - 1);  // order is a permutation of [0, M)
+            cnt = counts[rec];
+        }
+        s_rec[q] = rec;
+        c[k] = cnt;
+        sum += cnt;
+    }
+    const uint32_t texcl = block_exclusive_scan_256(sum, s_tmp);
+    uint32_t run = texcl;
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        run += c[k];
+        s_incl[tid * kScanIpt + k] = run;
+    }
+    if (tid == kScanThreads - 1) s_agg = run;
+    __syncthreads();
+    const uint32_t agg = s_agg;
+    if (tid == 0) {
+        const uint32_t excl = lookback_exclusive(lb, 1, (int)bid, agg, epoch, &ctrl->status);
+        s_base = excl;
+        if (base + kScanTile >= M) {
+            const uint32_t total = excl + agg;
+            ctrl->num_pairs = total;
+            if (total > cap) atomicOr(&ctrl->status, (uint32_t)DQO_STATUS_OVERFLOW);
+        }
+    }
+    __syncthreads();
+    const uint32_t gbase = s_base;
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        const uint32_t q = tid * kScanIpt + k;
+        if (base + q < M) offsets[s_rec[q]] = gbase + s_incl[q] - c[k];
+    }
+    // Cooperative emission: consecutive threads write consecutive pair slots.
+    for (uint32_t e = tid; e < agg; e += kScanThreads) {
+        uint32_t lo = 0, hi = kScanTile - 1;
+        while (lo < hi) {  // first q with s_incl[q] > e
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_incl[mid] > e) hi = mid; else lo = mid + 1;
+        }
+        const uint32_t q = lo;
+        const uint32_t start = q ? s_incl[q - 1] : 0u;
+        const uint32_t j = e - start;
+        const uint32_t rec = s_rec[q];
+        const short4 rc = rects[rec];
+        const uint32_t w = (uint32_t)(rc.z - rc.x + 1);
+        const uint32_t tx = rc.x + j % w, ty = rc.y + j / w;
+        const uint32_t v = (uint32_t)(rec / n);
+        const uint32_t tile = v * (uint32_t)tiles_per_view + ty * (uint32_t)tiles_x + tx;
+        const uint32_t gpos = gbase + e;
+        if (gpos < cap) {
+            pkeys[gpos] = tile;
+            pvals[gpos] = rec;
+            for (int p = 0; p < pair_passes; ++p) atomicAdd(&s_hist[p][(tile >> (8 * p)) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < pair_passes; ++p) {
+        const uint32_t h = s_hist[p][tid];
+        if (h) atomicAdd(&ctrl->hist_pair[p][tid], h);
+    }
+}
+
+template <typename T>
+hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t* ids, hipStream_t st) {
+    const StatePtrs& s = f.s;
+    hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(256), 0, st, s.ctrl);
+    const int64_t M = s.items;
+    if (M == 0) return hipGetLastError();
+    hipLaunchKernelGGL(project_kernel<T>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, f.views, f.consts,
+                       f.n, M, params, ids, (T*)s.splats, s.rects, s.counts, s.depth_keys[0], s.depth_vals[0],
+                       s.ctrl);
+    int src = 0;
+    for (int p = 0; p < kMaxDepthPasses; ++p) {
+        hipError_t e = launch_radix_pass(s.depth_keys[src], s.depth_vals[src], s.depth_keys[src ^ 1],
+                                         s.depth_vals[src ^ 1], nullptr, (uint32_t)M, p * kRadixBits,
+                                         s.ctrl->hist_depth[p],
+                                         s.lb_depth + (size_t)p * s.depth_blocks * kRadixBins,
+                                         &s.ctrl->counters[kCounterDepth + p], s.ctrl, st);
+        if (e != hipSuccess) return e;
+        src ^= 1;
+    }
+    const int pf = s.pair_first_buf;
+    hipLaunchKernelGGL(scan_emit_kernel, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st, s.depth_vals[0],
+                       s.counts, s.rects, s.offsets, s.pair_keys[pf], s.pair_vals[pf], (uint32_t)M,
+                       (uint32_t)s.capacity, f.n, f.views.tiles_x, f.views.tiles_per_view, s.pair_passes,
+                       s.lb_scan, s.ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- backward
+template <typename T>
+__global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Consts<T> cs, int64_t n,
+                                                               const T* __restrict__ params,
+                                                               const uint32_t* __restrict__ counts,
+                                                               const uint32_t* __restrict__ offsets,
+                                                               const T* __restrict__ partials, uint32_t cap,
+                                                               T* __restrict__ grads) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n) return;
+    T p[kParams];
+#pragma unroll
+    for (int r = 0; r < kParams; ++r) p[r] = params[(int64_t)r * n + g];
+    T acc[kParams];
+#pragma unroll
+    for (int r = 0; r < kParams; ++r) acc[r] = T(0);
+    for (int v = 0; v < V.n_views; ++v) {
+        const int64_t item = (int64_t)v * n + g;
+        const uint32_t cnt = counts[item];
+        if (cnt == 0) continue;
+        const uint32_t off = offsets[item];
+        if ((uint64_t)off + cnt > cap) continue;
+        T d[kGradWords];
+#pragma unroll
+        for (int k = 0; k < kGradWords; ++k) d[k] = T(0);
+        for (uint32_t j = 0; j < cnt; ++j) {
+            const T* src = partials + (size_t)(off + j) * kGradWords;
+#pragma unroll
+            for (int k = 0; k < kGradWords; ++k) d[k] += src[k];
+        }
+        const DevCam<T>& c = V.cam[v];
+        Proj<T> pr;
+        project_item(c, cs, p, pr);
+        if (!pr.visible) continue;
+        const T* W = c.R;
+        // conic -> 2D covariance: G_S = -Ci Gc Ci with Gc = [[dA, dB/2], [dB/2, dC]]
+        const T hB = T(0.5) * d[3];
+        const T a00 = pr.A * d[2] + pr.B * hB, a01 = pr.A * hB + pr.B * d[4];
+        const T a10 = pr.B * d[2] + pr.C * hB, a11 = pr.B * hB + pr.C * d[4];
+        const T gs00 = -(a00 * pr.A + a01 * pr.B);
+        const T gs01 = -(a00 * pr.B + a01 * pr.C);
+        const T gs11 = -(a10 * pr.B + a11 * pr.C);
+        // Sigma2 = U U^T + dil I: dU = 2 G_S U
+        T dU[6];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            dU[b] = T(2) * (gs00 * pr.U[b] + gs01 * pr.U[3 + b]);
+            dU[3 + b] = T(2) * (gs01 * pr.U[b] + gs11 * pr.U[3 + b]);
+        }
+        // U = T2 M with T2 = J W, M = R diag(s)
+        const T iz = T(1) / pr.z;
+        const T j00 = c.fx * iz, j02 = -c.fx * pr.x * iz * iz;
+        const T j11 = c.fy * iz, j12 = -c.fy * pr.y * iz * iz;
+        T T2[6], Mm[9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            T2[k] = j00 * W[k] + j02 * W[6 + k];
+            T2[3 + k] = j11 * W[3 + k] + j12 * W[6 + k];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Mm[a * 3 + b] = pr.R[a * 3 + b] * pr.s[b];
+        T dT2[6], dM[9];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                dT2[a * 3 + k] = dU[a * 3 + 0] * Mm[k * 3 + 0] + dU[a * 3 + 1] * Mm[k * 3 + 1] +
+                                 dU[a * 3 + 2] * Mm[k * 3 + 2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) dM[k * 3 + b] = T2[k] * dU[b] + T2[3 + k] * dU[3 + b];
+        // dJ = dT2 W^T (only the four nonzero entries of J matter)
+        const T dj00 = dT2[0] * W[0] + dT2[1] * W[1] + dT2[2] * W[2];
+        const T dj02 = dT2[0] * W[6] + dT2[1] * W[7] + dT2[2] * W[8];
+        const T dj11 = dT2[3] * W[3] + dT2[4] * W[4] + dT2[5] * W[5];
+        const T dj12 = dT2[3] * W[6] + dT2[4] * W[7] + dT2[5] * W[8];
+        const T iz2 = iz * iz, iz3 = iz2 * iz;
+        T dpx = dj02 * (-c.fx * iz2) + d[0] * c.fx * iz;
+        T dpy = dj12 * (-c.fy * iz2) + d[1] * c.fy * iz;
+        T dpz = dj00 * (-c.fx * iz2) + dj02 * (T(2) * c.fx * pr.x * iz3) + dj11 * (-c.fy * iz2) +
+                dj12 * (T(2) * c.fy * pr.y * iz3) + d[0] * (-c.fx * pr.x * iz2) + d[1] * (-c.fy * pr.y * iz2) +
+                d[9];
+        acc[0] += W[0] * dpx + W[3] * dpy + W[6] * dpz;
+        acc[1] += W[1] * dpx + W[4] * dpy + W[7] * dpz;
+        acc[2] += W[2] * dpx + W[5] * dpy + W[8] * dpz;
+        // M = R diag(s)
+        T dR[9];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            T ds = T(0);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ds += dM[a * 3 + b] * pr.R[a * 3 + b];
+                dR[a * 3 + b] = dM[a * 3 + b] * pr.s[b];
+            }
+            acc[3 + b] += ds * pr.s[b];
+        }
+        // R(q) with q normalised
+        const T w = pr.qn[0], x = pr.qn[1], y = pr.qn[2], z = pr.qn[3];
+        T dq[4];
+        dq[0] = T(2) * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+        dq[1] = T(2) * (y * dR[1] + z * dR[2] + y * dR[3] - w * dR[5] + z * dR[6] + w * dR[7]) -
+                T(4) * x * (dR[4] + dR[8]);
+        dq[2] = T(2) * (x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7]) -
+                T(4) * y * (dR[0] + dR[8]);
+        dq[3] = T(2) * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] + x * dR[6] + y * dR[7]) -
+                T(4) * z * (dR[0] + dR[4]);
+        const T dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+        const T iq = T(1) / pr.qnorm;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[6 + k] += (dq[k] - pr.qn[k] * dot) * iq;
+        acc[10] += d[5] * pr.o * (T(1) - pr.o);
+        acc[11] += d[6];
+        acc[12] += d[7];
+        acc[13] += d[8];
+    }
+#pragma unroll
+    for (int r = 0; r < kParams; ++r) grads[(int64_t)r * n + g] = acc[r];
+}
+
+template <typename T>
+hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads, hipStream_t st) {
+    if (f.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(project_backward_kernel<T>, dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st, f.views,
+                       f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.partials,
+                       (uint32_t)f.s.capacity, grads);
+    return hipGetLastError();
+}
+
+__global__ void clear_ctrl_kernel(Ctrl* ctrl, uint64_t* lb, int64_t lb_words) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t* c = reinterpret_cast<uint32_t*>(ctrl);
+    const int64_t cw = (int64_t)(sizeof(Ctrl) / 4);
+    for (int64_t k = i; k < cw; k += (int64_t)gridDim.x * blockDim.x) c[k] = 0u;
+    for (int64_t k = i; k < lb_words; k += (int64_t)gridDim.x * blockDim.x) lb[k] = 0ull;
+}
+
+__global__ void clear_status_kernel(Ctrl* ctrl) { ctrl->status = 0u; }
+
+__global__ void zero_words_kernel(uint32_t* p, int64_t n) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = 0u;
+}
+
+hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_ctrl(Ctrl* ctrl, uint64_t* lb, int64_t lb_words, hipStream_t st) {
+    hipLaunchKernelGGL(clear_ctrl_kernel, dim3(256), dim3(256), 0, st, ctrl, lb, lb_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_status(Ctrl* ctrl, hipStream_t st) {
+    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, st, ctrl);
+    return hipGetLastError();
+}
+
+template hipError_t launch_project_bin<float>(const Frame<float>&, const float*, const int32_t*, hipStream_t);
+template hipError_t launch_project_bin<double>(const Frame<double>&, const double*, const int32_t*, hipStream_t);
+template hipError_t launch_project_backward<float>(const Frame<float>&, const float*, float*, hipStream_t);
+template hipError_t launch_project_backward<double>(const Frame<double>&, const double*, double*, hipStream_t);
+
+}  // namespace dqo

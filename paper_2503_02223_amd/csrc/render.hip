@@ -1,0 +1,391 @@
+// Tile rasterization: forward alpha blending and its adjoint.
+//
+// One workgroup per (view, pixel tile), one thread per pixel; the tile's sorted
+// pair range is streamed through LDS in batches of one record per thread, and
+// every thread then walks the batch from LDS (broadcast reads).  Blending is a
+// per-pixel recurrence, not a dense contraction, so this path is VALU and
+// transcendental bound and uses no matrix cores.
+//
+// The inner loops are written without divergent branches: every lane computes
+// the contribution test, non-contributing lanes carry a zero weight, and whole
+// steps are skipped only when the entire wavefront agrees (ballots), so the
+// per-pair cost is a straight line of VALU work instead of exec-mask juggling.
+//
+// The forward keeps only T_final and the position of the last blended
+// Gaussian per pixel.  The backward walks each pixel from that position back to
+// the front of its tile's range, recomputing alpha exactly as the forward did
+// and the transmittance by division (T_i = T_{i+1} / (1 - alpha_i)), and
+// reduces the per-pixel gradients of each Gaussian over the workgroup: six
+// Gaussians x ten values are transposed-and-summed across the 64 lanes of a
+// wave (each lane ends up owning one value), then summed over the waves in
+// LDS, and written once per (tile, Gaussian) pair to its own slot; the
+// per-Gaussian totals are formed later in a fixed order, so no atomics are
+// needed and the result is deterministic.
+#include "dqo_device.hpp"
+
+namespace dqo {
+
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) { return fma(a, b, c); }
+
+// Mahalanobis form of the pixel sample against a splat record (shared by the
+// forward and the backward so that both take bitwise identical decisions).
+template <typename T>
+__device__ __forceinline__ T quad_form(const T* sp, T sx, T sy, T& dx, T& dy) {
+    dx = sx - sp[0];
+    dy = sy - sp[1];
+    return fmadd(sp[2] * dx, dx, fmadd(T(2) * sp[3] * dx, dy, sp[4] * dy * dy));
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+template <typename T>
+__device__ __forceinline__ void copy_splat(T* dst, const T* src) {
+#pragma unroll
+    for (int k = 0; k < kSplatWords; ++k) dst[k] = src[k];
+}
+template <>
+__device__ __forceinline__ void copy_splat<float>(float* dst, const float* src) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+    float4* d4 = reinterpret_cast<float4*>(dst);
+    const float4 a = s4[0], b = s4[1], c = s4[2];
+    d4[0] = a;
+    d4[1] = b;
+    d4[2] = c;
+}
+
+template <typename T, int TW, int TH, bool PROBS>
+__global__ __launch_bounds__(TW* TH) void render_forward_kernel(
+    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const uint32_t* __restrict__ pvals,
+    const uint32_t* __restrict__ ranges, T* __restrict__ color, T* __restrict__ depth, T* __restrict__ tfinal,
+    int32_t* __restrict__ last, T* __restrict__ probs, int32_t* __restrict__ idmap,
+    const int32_t* __restrict__ target, T* __restrict__ ptarget, int32_t* __restrict__ nblend, uint32_t cap,
+    uint32_t M) {
+    constexpr int BLOCK = TW * TH;
+    __shared__ __align__(16) T s_sp[BLOCK * kSplatWords];
+    extern __shared__ unsigned char s_dyn[];
+    T* s_P = reinterpret_cast<T*>(s_dyn);  // [K][BLOCK] when PROBS
+
+    const int tid = threadIdx.x;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int view = tile / V.tiles_per_view;
+    const int t = tile - view * V.tiles_per_view;
+    const int ty = t / V.tiles_x, tx = t - ty * V.tiles_x;
+    const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
+    const bool inside = px < V.W && py < V.H;
+    const int64_t HW = (int64_t)V.W * V.H;
+    const int64_t pix = (int64_t)py * V.W + px;
+    const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
+    const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
+    int tgt = -2;
+    if (target && inside) tgt = target[view * HW + pix];
+    if (PROBS)
+        for (int k = 0; k < K; ++k) s_P[k * BLOCK + tid] = T(0);
+
+    T Tt = T(1), c0 = T(0), c1 = T(0), c2 = T(0), dd = T(0), pt = T(0);
+    int lastpos = -1, nb_count = 0;
+    bool done = !inside;
+    for (uint32_t b0 = rs; b0 < re; b0 += BLOCK) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t pos = b0 + tid;
+        if (pos < re) copy_splat<T>(s_sp + tid * kSplatWords, splats + (size_t)min(pvals[pos], M - 1) * kSplatWords);
+        __syncthreads();
+        const int nb = (int)min((uint32_t)BLOCK, re - b0);
+        if (!wave_any(!done)) continue;
+        for (int j = 0; j < nb; ++j) {
+            const T* sp = s_sp + j * kSplatWords;
+            T dx, dy;
+            const T Q = quad_form(sp, sx, sy, dx, dy);
+            const bool in = (Q <= cs.q_max) && !done;
+            if (!wave_any(in)) continue;
+            const T a0 = min(sp[5] * fast_exp<T>(T(-0.5) * Q), cs.alpha_max);
+            const bool contrib = in && (a0 >= cs.alpha_min);
+            const T a = contrib ? a0 : T(0);
+            const T Tn = Tt * (T(1) - a);
+            const bool stop = contrib && (Tn < cs.t_min);
+            const T w = stop ? T(0) : a * Tt;
+            if (wave_any(w != T(0))) {
+                c0 = fmadd(w, sp[8], c0);
+                c1 = fmadd(w, sp[9], c1);
+                c2 = fmadd(w, sp[10], c2);
+                dd = fmadd(w, sp[6], dd);
+                const int id = word_to_id<T>(sp[7]);
+                pt += (id == tgt) ? w : T(0);
+                if (w != T(0)) {
+                    lastpos = (int)(b0 + j);
+                    ++nb_count;
+                    if (PROBS && id >= 0 && id < K) s_P[id * BLOCK + tid] += w;
+                }
+                Tt = stop ? Tt : Tn;
+            }
+            if (stop) done = true;
+            if (!wave_any(!done)) break;
+        }
+    }
+    if (!inside) return;
+    const int64_t o = view * HW + pix;
+    color[(view * 3 + 0) * HW + pix] = c0 + Tt * cs.bg[0];
+    color[(view * 3 + 1) * HW + pix] = c1 + Tt * cs.bg[1];
+    color[(view * 3 + 2) * HW + pix] = c2 + Tt * cs.bg[2];
+    depth[o] = dd;
+    tfinal[o] = Tt;
+    last[o] = lastpos;
+    if (nblend) nblend[o] = nb_count;
+    if (ptarget && target) ptarget[o] = (tgt == -1) ? Tt : pt;
+    if (PROBS) {
+        int best = K;
+        T bv = Tt;
+        for (int k = K - 1; k >= 0; --k) {
+            const T pk = s_P[k * BLOCK + tid];
+            probs[((int64_t)view * K + k) * HW + pix] = pk;
+            if (pk >= bv) {
+                bv = pk;
+                best = k;
+            }
+        }
+        if (idmap) idmap[o] = (best == K) ? -1 : best;
+    }
+}
+
+// ---------------------------------------------------------------- backward
+constexpr int kChunk = 6;  // Gaussians per transposed reduction (6 x 10 = 60 of 64 lanes)
+
+template <typename T, int D, int M>
+__device__ __forceinline__ void butterfly_step(T (&v)[64], int lane) {
+    const bool up = (lane & D) != 0;
+#pragma unroll
+    for (int i = 0; i < M / 2; ++i) {
+        const T send = up ? v[i] : v[i + M / 2];
+        const T keep = up ? v[i + M / 2] : v[i];
+        v[i] = keep + __shfl_xor(send, D);
+    }
+}
+
+// After the call, v[0] of lane L holds the sum over the wave of value L.
+template <typename T>
+__device__ __forceinline__ void wave_transpose_sum(T (&v)[64], int lane) {
+    butterfly_step<T, 32, 64>(v, lane);
+    butterfly_step<T, 16, 32>(v, lane);
+    butterfly_step<T, 8, 16>(v, lane);
+    butterfly_step<T, 4, 8>(v, lane);
+    butterfly_step<T, 2, 4>(v, lane);
+    butterfly_step<T, 1, 2>(v, lane);
+}
+
+__device__ __forceinline__ uint32_t pair_slot(const short4* rects, const uint32_t* offsets, uint32_t rec, int tx,
+                                              int ty) {
+    const short4 rc = rects[rec];
+    return offsets[rec] + (uint32_t)(ty - rc.y) * (uint32_t)(rc.z - rc.x + 1) + (uint32_t)(tx - rc.x);
+}
+
+template <typename T, int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void render_backward_kernel(
+    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges,
+    const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
+    const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
+    const T* __restrict__ dPt, T* __restrict__ partials, uint32_t cap, uint32_t M) {
+    constexpr int BLOCK = TW * TH;
+    constexpr int NW = BLOCK / kWave;
+    __shared__ __align__(16) T s_sp[BLOCK * kSplatWords];
+    __shared__ uint32_t s_slot[BLOCK];
+    __shared__ T s_red[2][NW][kWave];
+    __shared__ int s_maxlast;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid >> 6;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int view = tile / V.tiles_per_view;
+    const int t = tile - view * V.tiles_per_view;
+    const int ty = t / V.tiles_x, tx = t - ty * V.tiles_x;
+    const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
+    const bool inside = px < V.W && py < V.H;
+    const int64_t HW = (int64_t)V.W * V.H;
+    const int64_t pix = (int64_t)py * V.W + px;
+    const int64_t o = view * HW + pix;
+    const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
+    const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
+
+    int lastp = -1;
+    T Tcur = T(1), gc0 = T(0), gc1 = T(0), gc2 = T(0), gd = T(0), gt = T(0), gpt = T(0);
+    int tgt = -2;
+    if (inside) {
+        lastp = last[o];
+        Tcur = tfinal[o];
+        gc0 = dC[(view * 3 + 0) * HW + pix];
+        gc1 = dC[(view * 3 + 1) * HW + pix];
+        gc2 = dC[(view * 3 + 2) * HW + pix];
+        gd = dD ? dD[o] : T(0);
+        gt = dT ? dT[o] : T(0);
+        if (dPt && target) {
+            tgt = target[o];
+            gpt = dPt[o];
+            if (tgt == -1) gt += gpt;
+        }
+    }
+    if (tid == 0) s_maxlast = -1;
+    __syncthreads();
+    if (lastp >= 0) atomicMax(&s_maxlast, lastp);
+    __syncthreads();
+    const int maxlast = s_maxlast;
+    // Pairs behind every pixel's last blended Gaussian get zero partials.
+    const uint32_t hi = (maxlast >= (int)rs) ? (uint32_t)(maxlast + 1) : rs;
+    for (uint32_t pos = hi + tid; pos < re; pos += BLOCK) {
+        const uint32_t slot = pair_slot(rects, offsets, min(pvals[pos], M - 1), tx, ty);
+        if (slot < cap) {
+#pragma unroll
+            for (int k = 0; k < kGradWords; ++k) partials[(size_t)slot * kGradWords + k] = T(0);
+        }
+    }
+    T S = Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
+    int buf = 0;
+    for (uint32_t bend = hi; bend > rs;) {
+        const uint32_t bstart = (bend - rs > (uint32_t)BLOCK) ? bend - BLOCK : rs;
+        const int nb = (int)(bend - bstart);
+        __syncthreads();
+        if (tid < nb) {
+            const uint32_t rec = min(pvals[bstart + tid], M - 1);
+            copy_splat<T>(s_sp + tid * kSplatWords, splats + (size_t)rec * kSplatWords);
+            s_slot[tid] = pair_slot(rects, offsets, rec, tx, ty);
+        }
+        __syncthreads();
+        for (int c0 = nb - 1; c0 >= 0; c0 -= kChunk) {
+            T v[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) v[k] = T(0);
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c) {
+                const int jl = c0 - c;
+                if (jl < 0) break;
+                const T* sp = s_sp + jl * kSplatWords;
+                T dx, dy;
+                const T Q = quad_form(sp, sx, sy, dx, dy);
+                const bool in = (Q <= cs.q_max) && ((int)(bstart + jl) <= lastp);
+                if (!wave_any(in)) continue;
+                const T G = fast_exp<T>(T(-0.5) * Q);
+                const T araw = sp[5] * G;
+                const bool clamped = !(araw < cs.alpha_max);
+                const T a0 = min(araw, cs.alpha_max);
+                const bool contrib = in && (a0 >= cs.alpha_min);
+                if (!wave_any(contrib)) continue;
+                any = true;
+                const T a = contrib ? a0 : T(0);
+                const T oma = T(1) - a;
+                const T Ti = Tcur / oma;
+                const T w = a * Ti;
+                const int id = word_to_id<T>(sp[7]);
+                T vv = fmadd(gc0, sp[8], fmadd(gc1, sp[9], fmadd(gc2, sp[10], gd * sp[6])));
+                vv += (tgt >= 0 && id == tgt) ? gpt : T(0);
+                if (dP && contrib && id >= 0 && id < K) vv += dP[((int64_t)view * K + id) * HW + pix];
+                const T dalpha = contrib ? (Ti * vv - S / oma) : T(0);
+                S = fmadd(w, vv, S);
+                Tcur = Ti;
+                v[c * kGradWords + 6] = gc0 * w;
+                v[c * kGradWords + 7] = gc1 * w;
+                v[c * kGradWords + 8] = gc2 * w;
+                v[c * kGradWords + 9] = gd * w;
+                const T dQ = clamped ? T(0) : dalpha * (T(-0.5) * a);
+                v[c * kGradWords + 5] = clamped ? T(0) : dalpha * G;
+                v[c * kGradWords + 0] = dQ * (T(-2) * (sp[2] * dx + sp[3] * dy));
+                v[c * kGradWords + 1] = dQ * (T(-2) * (sp[3] * dx + sp[4] * dy));
+                v[c * kGradWords + 2] = dQ * dx * dx;
+                v[c * kGradWords + 3] = dQ * T(2) * dx * dy;
+                v[c * kGradWords + 4] = dQ * dy * dy;
+            }
+            if (wave_any(any)) wave_transpose_sum<T>(v, lane);
+            if constexpr (NW == 1) {
+                // one wavefront per tile: the transposed sums are the block sums
+                const int c = lane / kGradWords;
+                const int jl = c0 - c;
+                if (lane < kChunk * kGradWords && jl >= 0) {
+                    const uint32_t slot = s_slot[jl];
+                    if (slot < cap) partials[(size_t)slot * kGradWords + (lane - c * kGradWords)] = v[0];
+                }
+                continue;
+            }
+            s_red[buf][wave][lane] = v[0];
+            __syncthreads();
+            if (tid < kChunk * kGradWords) {
+                const int c = tid / kGradWords;
+                const int jl = c0 - c;
+                if (jl >= 0) {
+                    T sum = T(0);
+#pragma unroll
+                    for (int w2 = 0; w2 < NW; ++w2) sum += s_red[buf][w2][tid];
+                    const uint32_t slot = s_slot[jl];
+                    if (slot < cap) partials[(size_t)slot * kGradWords + (tid - c * kGradWords)] = sum;
+                }
+            }
+            buf ^= 1;
+        }
+        bend = bstart;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename T, int TW, int TH>
+static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t st) {
+    const int blocks = f.views.n_views * f.views.tiles_per_view;
+    if (blocks == 0) return hipSuccess;
+    const StatePtrs& s = f.s;
+    if (img.probs && f.K > 0) {
+        const size_t dyn = (size_t)f.K * TW * TH * sizeof(T);
+        hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, true>), dim3(blocks), dim3(TW * TH), dyn, st, f.views,
+                           f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, (T*)img.color,
+                           (T*)img.depth, (T*)img.t_final, img.last, (T*)img.probs, img.id_map, img.target,
+                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items);
+    } else {
+        hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, false>), dim3(blocks), dim3(TW * TH), 0, st, f.views,
+                           f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, (T*)img.color,
+                           (T*)img.depth, (T*)img.t_final, img.last, (T*)nullptr, (int32_t*)nullptr, img.target,
+                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int TW, int TH>
+static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_image_grads& g, hipStream_t st) {
+    const int blocks = f.views.n_views * f.views.tiles_per_view;
+    if (blocks == 0) return hipSuccess;
+    const StatePtrs& s = f.s;
+    hipLaunchKernelGGL((render_backward_kernel<T, TW, TH>), dim3(blocks), dim3(TW * TH), 0, st, f.views, f.consts,
+                       f.K, (const T*)s.splats, s.rects, s.offsets, s.pair_vals[0], s.ranges,
+                       (const T*)img.t_final, img.last, img.target, (const T*)g.d_color, (const T*)g.d_depth,
+                       (const T*)g.d_t_final, (const T*)g.d_probs, (const T*)g.d_p_target, (T*)s.partials,
+                       (uint32_t)s.capacity, (uint32_t)s.items);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_render_forward(const Frame<T>& f, const dqo_images& img, hipStream_t st) {
+    const int tw = f.views.tile_w, th = f.views.tile_h;
+    if (tw == 16 && th == 16) return fwd_tile<T, 16, 16>(f, img, st);
+    if (tw == 8 && th == 8) return fwd_tile<T, 8, 8>(f, img, st);
+    if (tw == 16 && th == 8) return fwd_tile<T, 16, 8>(f, img, st);
+    if (tw == 32 && th == 8) return fwd_tile<T, 32, 8>(f, img, st);
+    if (tw == 8 && th == 32) return fwd_tile<T, 8, 32>(f, img, st);
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_render_backward(const Frame<T>& f, const dqo_images& img, const dqo_image_grads& g,
+                                  hipStream_t st) {
+    const int tw = f.views.tile_w, th = f.views.tile_h;
+    if (tw == 16 && th == 16) return bwd_tile<T, 16, 16>(f, img, g, st);
+    if (tw == 8 && th == 8) return bwd_tile<T, 8, 8>(f, img, g, st);
+    if (tw == 16 && th == 8) return bwd_tile<T, 16, 8>(f, img, g, st);
+    if (tw == 32 && th == 8) return bwd_tile<T, 32, 8>(f, img, g, st);
+    if (tw == 8 && th == 32) return bwd_tile<T, 8, 32>(f, img, g, st);
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_render_forward<float>(const Frame<float>&, const dqo_images&, hipStream_t);
+template hipError_t launch_render_forward<double>(const Frame<double>&, const dqo_images&, hipStream_t);
+template hipError_t launch_render_backward<float>(const Frame<float>&, const dqo_images&, const dqo_image_grads&,
+                                                  hipStream_t);
+template hipError_t launch_render_backward<double>(const Frame<double>&, const dqo_images&,
+                                                   const dqo_image_grads&, hipStream_t);
+
+}  // namespace dqo

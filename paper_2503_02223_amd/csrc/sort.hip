@@ -1,0 +1,154 @@
+// Stable LSD radix sort passes (8-bit digits, one kernel per pass) and tile ranges.
+//
+// A pass reads 2048 (key, value) items per block, ranks them stably inside the
+// block with wave-wide match ballots, obtains the block's global offset per
+// digit by decoupled look-back over the preceding blocks (block order is taken
+// from an atomic ticket, so every block it waits on is already running), then
+// writes the items out digit-sorted through LDS so stores are coalesced.
+// Digit histograms of every pass are accumulated before the first pass by the
+// kernel that produced the keys.
+#include "dqo_device.hpp"
+#include "sort_common.hpp"
+
+namespace dqo {
+
+__global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
+    const uint32_t* __restrict__ ghist, uint64_t* lb, uint32_t* counter, Ctrl* ctrl) {
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wcnt[kSortThreads / kWave][kRadixBins];
+    __shared__ uint32_t s_dstart[kRadixBins];
+    __shared__ uint32_t s_gbase[kRadixBins];
+    __shared__ uint32_t s_tmp[kSortThreads / kWave];
+    __shared__ uint32_t s_bid;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid >> 6;
+    if (tid == 0) s_bid = atomicAdd(counter, 1u);
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; ++w) s_wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint32_t bid = s_bid;
+    uint32_t n = n_host;
+    if (n_dev) n = min(*n_dev, n_host);
+    const uint32_t base = bid * (uint32_t)kSortTile;
+    if (base >= n) return;  // uniform over the block; no later block waits on this one
+    const uint32_t epoch = ctrl->epoch;
+
+    uint32_t key[kSortIpt], val[kSortIpt], rank[kSortIpt];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int i = 0; i < kSortIpt; ++i) {
+        const uint32_t pos = base + wave * (kWave * kSortIpt) + i * kWave + lane;
+        const bool valid = pos < n;
+        key[i] = valid ? kin[pos] : 0u;
+        val[i] = valid ? vin[pos] : 0u;
+        const uint32_t d = (key[i] >> shift) & (kRadixBins - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+        uint32_t old = 0;
+        if (valid) old = s_wcnt[wave][d];
+        const bool leader = valid && ((peers >> lane) == 1ull);
+        if (leader) s_wcnt[wave][d] = old + (uint32_t)__popcll(peers);
+        rank[i] = old + below;
+    }
+    __syncthreads();
+
+    // Thread t owns digit t: per-wave exclusive offsets and the block total.
+    const int t = tid;
+    uint32_t total = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; ++w) {
+        const uint32_t c = s_wcnt[w][t];
+        s_wcnt[w][t] = total;
+        total += c;
+    }
+    const uint32_t dstart = block_exclusive_scan_256(total, s_tmp);
+    const uint32_t gdig = block_exclusive_scan_256(ghist[t], s_tmp);
+    s_dstart[t] = dstart;
+    const uint32_t excl = lookback_exclusive(lb + t, kRadixBins, (int)bid, total, epoch, &ctrl->status);
+    s_gbase[t] = gdig + excl;
+    __syncthreads();
+
+#pragma unroll
+    for (int i = 0; i < kSortIpt; ++i) {
+        const uint32_t pos = base + wave * (kWave * kSortIpt) + i * kWave + lane;
+        if (pos < n) {
+            const uint32_t d = (key[i] >> shift) & (kRadixBins - 1);
+            const uint32_t p = s_dstart[d] + s_wcnt[wave][d] + rank[i];
+            if (p < (uint32_t)kSortTile) {
+                s_keys[p] = key[i];
+                s_vals[p] = val[i];
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = min((uint32_t)kSortTile, n - base);
+    for (uint32_t q = tid; q < cnt; q += kSortThreads) {
+        const uint32_t k = s_keys[q];
+        const uint32_t d = (k >> shift) & (kRadixBins - 1);
+        const uint32_t o = s_gbase[d] + (q - s_dstart[d]);
+        if (o < n) {  // always true unless a bounded wait gave up (status bit set)
+            kout[o] = k;
+            vout[o] = s_vals[q];
+        }
+    }
+}
+
+// [start, end) of every global tile id in the sorted pair keys, by binary search.
+__global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+                                   uint32_t n_host, uint32_t* __restrict__ ranges, int tiles_total) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles_total) return;
+    const uint32_t n = min(*n_dev, n_host);
+    auto lower = [&](uint32_t v) {
+        uint32_t lo = 0, hi = n;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (keys[mid] < v) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    ranges[2 * t] = lower((uint32_t)t);
+    ranges[2 * t + 1] = lower((uint32_t)t + 1u);
+}
+
+hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                             const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
+                             uint64_t* lb, uint32_t* counter, Ctrl* ctrl, hipStream_t st) {
+    if (n_host == 0) return hipSuccess;
+    const int blocks = (int)((n_host + kSortTile - 1) / kSortTile);
+    hipLaunchKernelGGL(radix_pass_kernel, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev,
+                       n_host, shift, ghist, lb, counter, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st) {
+    const uint32_t cap = (uint32_t)s.capacity;
+    const uint32_t* n_dev = &s.ctrl->num_pairs;
+    int src = s.pair_first_buf;
+    for (int p = 0; p < s.pair_passes; ++p) {
+        hipError_t e = launch_radix_pass(s.pair_keys[src], s.pair_vals[src], s.pair_keys[src ^ 1],
+                                         s.pair_vals[src ^ 1], n_dev, cap, p * kRadixBits,
+                                         s.ctrl->hist_pair[p], s.lb_pair + (size_t)p * s.pair_blocks * kRadixBins,
+                                         &s.ctrl->counters[kCounterPair + p], s.ctrl, st);
+        if (e != hipSuccess) return e;
+        src ^= 1;
+    }
+    if (tiles_total > 0) {
+        hipLaunchKernelGGL(tile_ranges_kernel, dim3((tiles_total + 255) / 256), dim3(256), 0, st, s.pair_keys[0],
+                           n_dev, cap, s.ranges, tiles_total);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dqo

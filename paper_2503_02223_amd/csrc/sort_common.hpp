@@ -1,0 +1,34 @@
+// Wave- and block-level scans used by the radix passes and the pair emission.
+#pragma once
+#include "dqo_device.hpp"
+
+namespace dqo {
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over a 256-thread block (4 waves); s_tmp holds 4 words.
+// Contains two barriers: every thread of the block must call it.
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* s_tmp) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    const uint32_t incl = wave_inclusive_scan(v, lane);
+    if (lane == kWave - 1) s_tmp[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int w = 0; w < wave; ++w) off += s_tmp[w];
+    __syncthreads();
+    return off + incl - v;
+}
+
+hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                             const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
+                             uint64_t* lb, uint32_t* counter, Ctrl* ctrl, hipStream_t st);
+
+}  // namespace dqo

@@ -1,0 +1,85 @@
+"""The C-ABI library loads, exports every symbol include/dqo.h declares, and
+validates arguments on the host (no GPU needed: nothing is launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2503_02223_amd import binding as B
+from paper_2503_02223_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dqo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dqo_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_version_and_status_strings():
+    L = B.lib()
+    assert b"gfx950" in L.dqo_version()
+    assert L.dqo_status_string(B.ECAPACITY) == b"pair capacity exceeded"
+
+
+def test_layout_and_validation_on_host():
+    ctx = B.Context()
+    sc = scenes.single_view_scene(n=100)
+    cams = B.make_cameras(sc["cams"])
+    d = B.FrameDesc(n=100, n_views=1, K=3, pair_capacity=5000, dtype=B.F32)
+    L = B.Layout()
+    assert B.lib().dqo_state_layout(ctx.h, ctypes.byref(d), cams, ctypes.byref(L)) == 0
+    assert (L.tiles_x, L.tiles_y) == (8, 6)
+    assert L.pair_key_bits == 6
+    assert all(L.offset[i] % 256 == 0 for i in range(12))
+    assert L.total >= L.offset[11] + L.bytes[11]
+    assert L.bytes[0] == 100 * 12 * 4 and L.bytes[9] == 5000 * 10 * 4
+    for bad in (dict(n_views=0), dict(n_views=17), dict(K=65), dict(dtype=7), dict(n=-1),
+                dict(pair_capacity=(1 << 30) + 1)):
+        kw = dict(n=100, n_views=1, K=3, pair_capacity=5000, dtype=B.F32)
+        kw.update(bad)
+        d2 = B.FrameDesc(**kw)
+        nv = max(1, min(kw["n_views"], 16))
+        cams2 = B.make_cameras(sc["cams"] * nv)
+        rc = B.lib().dqo_state_layout(ctx.h, ctypes.byref(d2), cams2, ctypes.byref(L))
+        assert rc == B.EINVAL, bad
+        assert B.lib().dqo_last_error(ctx.h)
+    # mismatched view sizes
+    c2 = dict(sc["cams"][0])
+    c2["width"] = 64
+    d3 = B.FrameDesc(n=100, n_views=2, K=3, pair_capacity=5000, dtype=B.F32)
+    assert B.lib().dqo_state_layout(ctx.h, ctypes.byref(d3), B.make_cameras([sc["cams"][0], c2]),
+                                    ctypes.byref(L)) == B.EINVAL
+
+
+def test_bad_tile_config_rejected():
+    cfg = B.default_config(tile_w=12, tile_h=12)
+    with pytest.raises(B.DqoError):
+        B.Context(cfg)
+
+
+def test_null_pointers_rejected_before_launch():
+    ctx = B.Context()
+    sc = scenes.single_view_scene(n=10)
+    cams = B.make_cameras(sc["cams"])
+    d = B.FrameDesc(n=10, n_views=1, K=3, pair_capacity=100, dtype=B.F32)
+    L = B.lib()
+    assert L.dqo_project_cull_bin(ctx.h, ctypes.byref(d), cams, None, None, None, None) == B.EINVAL
+    img = B.Images()
+    assert L.dqo_render_forward(ctx.h, ctypes.byref(d), cams, ctypes.c_void_p(1), ctypes.byref(img), None) == B.EINVAL
+    hp = B.AdamParams()
+    assert L.dqo_adam_step(ctx.h, B.F32, None, None, None, None, 10, ctypes.byref(hp), 1, None) == B.EINVAL
+    assert L.dqo_adam_step(ctx.h, B.F32, None, None, None, None, 0, ctypes.byref(hp), 0, None) == B.EINVAL
+    assert L.dqo_fit_dual_quadric(ctx.h, 2, 4, None, None, None, 1, None, None, 1.0, None, None, None, None,
+                                  None, None) == B.EINVAL

@@ -21,7 +21,7 @@ def test_adjoint_matches_central_differences(oracle, seed):
     cam = sc["cams"][0]
     base = oracle.render(sc["params"], sc["ids"], cam, K=sc["K"])
     w = scenes.random_image_grads(100 + seed, (3, cam["height"], cam["width"]), K=sc["K"])
-    keep = (base["margin"] > 1e-4) & (base["margin_clamp"] > 1e-4)
+    keep = (base["margin"] > 1e-4) & (base["margin_clamp"] > 1e-4) & (base["depth_gap"] > 1e-5)
     for k in w:
         w[k] = w[k] * keep
     grads, _ = oracle.render_backward(sc["params"], sc["ids"], cam, K=sc["K"], **w)
@@ -48,7 +48,7 @@ def test_adjoint_with_background_colour(oracle):
     cfg = dict(bg=(0.3, 0.6, 0.9))
     base = oracle.render(sc["params"], sc["ids"], cam, cfg=cfg, K=sc["K"])
     w = scenes.random_image_grads(9, (3, 16, 16), K=sc["K"])
-    keep = (base["margin"] > 1e-4) & (base["margin_clamp"] > 1e-4)
+    keep = (base["margin"] > 1e-4) & (base["margin_clamp"] > 1e-4) & (base["depth_gap"] > 1e-5)
     for k in w:
         w[k] = w[k] * keep
     grads, _ = oracle.render_backward(sc["params"], sc["ids"], cam, cfg=cfg, K=sc["K"], **w)
