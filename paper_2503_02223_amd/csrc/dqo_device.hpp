@@ -16,8 +16,8 @@ constexpr int kGradWords = 10;    // dmx,dmy,dA,dB,dC,do,dr,dg,db,dz
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
-constexpr int kSortIpt = 8;                             // items per thread in a radix pass
-constexpr int kSortTile = kSortThreads * kSortIpt;      // 2048 items per block
+constexpr int kSortIpt = 16;                            // items per thread in a radix pass
+constexpr int kSortTile = kSortThreads * kSortIpt;      // 4096 items per block
 constexpr int kScanThreads = 256;
 constexpr int kScanIpt = 4;
 constexpr int kScanTile = kScanThreads * kScanIpt;      // 1024 items per block
@@ -98,20 +98,37 @@ __device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* words, int stri
     uint32_t excl = 0;
     int j = slot - 1;
     uint32_t spins = 0;
+    // Look back over a window of predecessors per round trip: the loads are
+    // independent, so the walk costs one memory latency per kLbWindow blocks.
+    constexpr int kLbWindow = 8;
     while (j >= 0) {
-        uint64_t w = lb_load(words + (size_t)j * stride);
-        uint32_t f = lb_flag(w, epoch);
-        if (f == 0) {
+        uint64_t w[kLbWindow];
+#pragma unroll
+        for (int k = 0; k < kLbWindow; ++k)
+            w[k] = (j - k >= 0) ? lb_load(words + (size_t)(j - k) * stride) : lb_pack(kFlagInclusive, epoch, 0u);
+        bool finished = false, stalled = false;
+        int used = 0;
+#pragma unroll
+        for (int k = 0; k < kLbWindow; ++k) {
+            if (finished || stalled) continue;
+            const uint32_t f = lb_flag(w[k], epoch);
+            if (f == 0) {
+                stalled = true;
+                continue;
+            }
+            excl += (uint32_t)w[k];
+            ++used;
+            if (f == kFlagInclusive) finished = true;
+        }
+        if (finished) break;
+        j -= used;
+        if (stalled) {
             if (++spins > kSpinLimit) {
                 atomicOr(status, (uint32_t)DQO_STATUS_TIMEOUT);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
-            continue;
         }
-        excl += (uint32_t)w;
-        if (f == kFlagInclusive) break;
-        --j;
     }
     lb_store(words + (size_t)slot * stride, lb_pack(kFlagInclusive, epoch, excl + agg));
     return excl;
@@ -132,6 +149,14 @@ template <>
 __device__ __forceinline__ float fast_exp<float>(float x) { return __expf(x); }
 template <>
 __device__ __forceinline__ double fast_exp<double>(double x) { return exp(x); }
+
+// Reciprocal: the hardware v_rcp_f32 (1 ulp) in FP32, exact division in FP64.
+template <typename T>
+__device__ __forceinline__ T fast_rcp(T x);
+template <>
+__device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
 
 template <typename T>
 __device__ __forceinline__ T id_to_word(int id);
@@ -176,7 +201,9 @@ struct StatePtrs {
     uint32_t* pair_keys[2];
     uint32_t* pair_vals[2];
     uint32_t* ranges;
+    uint32_t* schedule;   // [V*tiles] launch order of the render workgroups
     void* partials;
+    void* g2d;            // [V*n][10] per-item sums of the pair partials
     Ctrl* ctrl;
     uint64_t* lb_depth;   // [kMaxDepthPasses][blocks][256]
     uint64_t* lb_scan;    // [blocks]
@@ -223,5 +250,7 @@ hipError_t launch_fit_quadric(int n_obj, int64_t n_boxes, const double* boxes, c
 hipError_t launch_clear_ctrl(Ctrl* ctrl, uint64_t* lb, int64_t lb_words, hipStream_t st);
 hipError_t launch_clear_status(Ctrl* ctrl, hipStream_t st);
 hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_zero_partials(const StatePtrs& s, hipStream_t st);
 
 }  // namespace dqo

@@ -277,12 +277,94 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
 }
 
 // ---------------------------------------------------------------- backward
+// Per (view, Gaussian) item, in depth order so that neighbouring threads read
+// neighbouring pair slots: sum the item's per-tile partials in slot order into
+// g2d[item] (zero for items without pairs).
+template <typename T>
+__global__ __launch_bounds__(256) void pair_sum_kernel(const uint32_t* __restrict__ order,
+                                                       const uint32_t* __restrict__ counts,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const T* __restrict__ partials, T* __restrict__ g2d,
+                                                       uint32_t cap, uint32_t M) {
+    // The 256 items of a block own one contiguous run of slots (offsets are an
+    // exclusive scan in depth order); the run is staged through LDS in chunks
+    // with coalesced loads and every thread sums its own slots from LDS.
+    constexpr int kChunkSlots = 512;
+    __shared__ T s_p[kChunkSlots * kGradWords];
+    __shared__ uint32_t s_lo, s_hi;
+    const int tid = threadIdx.x;
+    const uint32_t r = blockIdx.x * 256 + tid;
+    const bool valid = r < M;
+    const uint32_t item = valid ? min(order[r], M - 1) : 0u;
+    uint32_t cnt = valid ? counts[item] : 0u;
+    const uint32_t off = valid ? offsets[item] : 0u;
+    if ((uint64_t)off + cnt > cap) cnt = 0;
+    if (tid == 0) {
+        s_lo = 0xffffffffu;
+        s_hi = 0u;
+    }
+    __syncthreads();
+    if (cnt) {
+        atomicMin(&s_lo, off);
+        atomicMax(&s_hi, off + cnt);
+    }
+    __syncthreads();
+    const uint32_t lo = s_lo, hi = s_hi;
+    T d[kGradWords];
+#pragma unroll
+    for (int k = 0; k < kGradWords; ++k) d[k] = T(0);
+    for (uint32_t c0 = lo; c0 < hi; c0 += kChunkSlots) {
+        const uint32_t nsl = min((uint32_t)kChunkSlots, hi - c0);
+        __syncthreads();
+        for (uint32_t k = tid; k < nsl * kGradWords; k += 256) s_p[k] = partials[(size_t)c0 * kGradWords + k];
+        __syncthreads();
+        const uint32_t j0 = max(off, c0), j1 = min(off + cnt, c0 + nsl);
+        for (uint32_t j = j0; j < j1; ++j) {
+#pragma unroll
+            for (int k = 0; k < kGradWords; ++k) d[k] += s_p[(j - c0) * kGradWords + k];
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < kGradWords; ++k) g2d[(size_t)item * kGradWords + k] = d[k];
+    }
+}
+
+// Zeroes the partials of the pairs of this frame (the render backward writes
+// only the pairs that contribute somewhere in their tile).
+template <typename T>
+__global__ __launch_bounds__(256) void zero_partials_kernel(T* __restrict__ partials, const Ctrl* __restrict__ ctrl,
+                                                            uint32_t cap) {
+    const uint64_t n = (uint64_t)min(ctrl->num_pairs, cap) * kGradWords;
+    const uint64_t stride = (uint64_t)gridDim.x * 256 * 4;
+    for (uint64_t i = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 4; i < n; i += stride) {
+        if (i + 4 <= n) {
+            partials[i] = T(0);
+            partials[i + 1] = T(0);
+            partials[i + 2] = T(0);
+            partials[i + 3] = T(0);
+        } else {
+            for (uint64_t k = i; k < n; ++k) partials[k] = T(0);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_zero_partials(const StatePtrs& s, hipStream_t st) {
+    if (s.capacity == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_partials_kernel<T>, dim3(1024), dim3(256), 0, st, (T*)s.partials, s.ctrl,
+                       (uint32_t)s.capacity);
+    return hipGetLastError();
+}
+template hipError_t launch_zero_partials<float>(const StatePtrs&, hipStream_t);
+template hipError_t launch_zero_partials<double>(const StatePtrs&, hipStream_t);
+
 template <typename T>
 __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Consts<T> cs, int64_t n,
                                                                const T* __restrict__ params,
                                                                const uint32_t* __restrict__ counts,
                                                                const uint32_t* __restrict__ offsets,
-                                                               const T* __restrict__ partials, uint32_t cap,
+                                                               const T* __restrict__ g2d, uint32_t cap,
                                                                T* __restrict__ grads) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= n) return;
@@ -298,14 +380,9 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
         if (cnt == 0) continue;
         const uint32_t off = offsets[item];
         if ((uint64_t)off + cnt > cap) continue;
-        T d[kGradWords];
+        T d[kGradWords];  // summed over the item's tiles by pair_sum_kernel
 #pragma unroll
-        for (int k = 0; k < kGradWords; ++k) d[k] = T(0);
-        for (uint32_t j = 0; j < cnt; ++j) {
-            const T* src = partials + (size_t)(off + j) * kGradWords;
-#pragma unroll
-            for (int k = 0; k < kGradWords; ++k) d[k] += src[k];
-        }
+        for (int k = 0; k < kGradWords; ++k) d[k] = g2d[(size_t)item * kGradWords + k];
         const DevCam<T>& c = V.cam[v];
         Proj<T> pr;
         project_item(c, cs, p, pr);
@@ -402,8 +479,11 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
 template <typename T>
 hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads, hipStream_t st) {
     if (f.n == 0) return hipSuccess;
+    const uint32_t M = (uint32_t)f.s.items;
+    hipLaunchKernelGGL(pair_sum_kernel<T>, dim3((M + 255) / 256), dim3(256), 0, st, f.s.depth_vals[0], f.s.counts,
+                       f.s.offsets, (const T*)f.s.partials, (T*)f.s.g2d, (uint32_t)f.s.capacity, M);
     hipLaunchKernelGGL(project_backward_kernel<T>, dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st, f.views,
-                       f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.partials,
+                       f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.g2d,
                        (uint32_t)f.s.capacity, grads);
     return hipGetLastError();
 }

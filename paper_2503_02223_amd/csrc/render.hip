@@ -54,10 +54,40 @@ __device__ __forceinline__ void copy_splat<float>(float* dst, const float* src) 
     d4[2] = c;
 }
 
+// Splat record into registers (prefetch) and from registers into LDS.
+template <typename T>
+__device__ __forceinline__ void load_splat(T (&r)[kSplatWords], const T* src) {
+#pragma unroll
+    for (int k = 0; k < kSplatWords; ++k) r[k] = src[k];
+}
+template <>
+__device__ __forceinline__ void load_splat<float>(float (&r)[kSplatWords], const float* src) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const float4 a = s4[q];
+        r[4 * q] = a.x;
+        r[4 * q + 1] = a.y;
+        r[4 * q + 2] = a.z;
+        r[4 * q + 3] = a.w;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store_splat_lds(T* dst, const T (&r)[kSplatWords]) {
+#pragma unroll
+    for (int k = 0; k < kSplatWords; ++k) dst[k] = r[k];
+}
+template <>
+__device__ __forceinline__ void store_splat_lds<float>(float* dst, const float (&r)[kSplatWords]) {
+    float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) d4[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+}
+
 template <typename T, int TW, int TH, bool PROBS>
 __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const uint32_t* __restrict__ pvals,
-    const uint32_t* __restrict__ ranges, T* __restrict__ color, T* __restrict__ depth, T* __restrict__ tfinal,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule, T* __restrict__ color, T* __restrict__ depth, T* __restrict__ tfinal,
     int32_t* __restrict__ last, T* __restrict__ probs, int32_t* __restrict__ idmap,
     const int32_t* __restrict__ target, T* __restrict__ ptarget, int32_t* __restrict__ nblend, uint32_t cap,
     uint32_t M) {
@@ -67,7 +97,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     T* s_P = reinterpret_cast<T*>(s_dyn);  // [K][BLOCK] when PROBS
 
     const int tid = threadIdx.x;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = (int)min(schedule[blockIdx.x], (uint32_t)(gridDim.x - 1));
     const int view = tile / V.tiles_per_view;
     const int t = tile - view * V.tiles_per_view;
     const int ty = t / V.tiles_x, tx = t - ty * V.tiles_x;
@@ -85,11 +115,19 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     T Tt = T(1), c0 = T(0), c1 = T(0), c2 = T(0), dd = T(0), pt = T(0);
     int lastpos = -1, nb_count = 0;
     bool done = !inside;
+    // Software prefetch: this lane's record of the next batch is loaded into
+    // registers while the current batch is walked; the pair index one batch
+    // further ahead is loaded one step earlier still.
+    T pf[kSplatWords];
+    uint32_t rec2 = 0u;
+    if (rs + tid < re) load_splat<T>(pf, splats + (size_t)min(pvals[rs + tid], M - 1) * kSplatWords);
+    if (rs + BLOCK + tid < re) rec2 = min(pvals[rs + BLOCK + tid], M - 1);
     for (uint32_t b0 = rs; b0 < re; b0 += BLOCK) {
         if (__syncthreads_count(!done) == 0) break;
-        const uint32_t pos = b0 + tid;
-        if (pos < re) copy_splat<T>(s_sp + tid * kSplatWords, splats + (size_t)min(pvals[pos], M - 1) * kSplatWords);
+        if (b0 + tid < re) store_splat_lds<T>(s_sp + tid * kSplatWords, pf);
         __syncthreads();
+        if (b0 + BLOCK + tid < re) load_splat<T>(pf, splats + (size_t)rec2 * kSplatWords);
+        if (b0 + 2 * BLOCK + tid < re) rec2 = min(pvals[b0 + 2 * BLOCK + tid], M - 1);
         const int nb = (int)min((uint32_t)BLOCK, re - b0);
         if (!wave_any(!done)) continue;
         for (int j = 0; j < nb; ++j) {
@@ -172,6 +210,50 @@ __device__ __forceinline__ void wave_transpose_sum(T (&v)[64], int lane) {
     butterfly_step<T, 1, 2>(v, lane);
 }
 
+// FP32 on gfx950.  The two cross-row levels use v_permlane32_swap /
+// v_permlane16_swap: swapping the upper half of x = v[i] with the lower half of
+// y = v[i + M/2] and adding the two results leaves, in every lane, the pair sum
+// of exactly the value that lane keeps (one swap and one add per value pair).
+// The in-row levels pair lanes with DPP row_mirror (lane ^ 15), row_half_mirror
+// (lane ^ 7) and quad_perm (lane ^ 2, lane ^ 1); with 32 and 16 these masks are
+// linearly independent, so each lane still sums all 64 lanes once, and the lane
+// bit that selects the kept half is the same as in the XOR butterfly.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL, int D, int M>
+__device__ __forceinline__ void dpp_step(float (&v)[64], int lane) {
+    const bool up = (lane & D) != 0;
+#pragma unroll
+    for (int i = 0; i < M / 2; ++i) {
+        const float send = up ? v[i] : v[i + M / 2];
+        const float keep = up ? v[i + M / 2] : v[i];
+        v[i] = keep + dpp_mov<CTRL>(send);
+    }
+}
+
+template <>
+__device__ __forceinline__ void wave_transpose_sum<float>(float (&v)[64], int lane) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 32]), false,
+                                                        false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 16]), false,
+                                                        false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    dpp_step<0x140, 8, 16>(v, lane);  // row_mirror: lane ^ 15
+    dpp_step<0x141, 4, 8>(v, lane);   // row_half_mirror: lane ^ 7
+    dpp_step<0x4E, 2, 4>(v, lane);    // quad_perm [2,3,0,1]: lane ^ 2
+    dpp_step<0xB1, 1, 2>(v, lane);    // quad_perm [1,0,3,2]: lane ^ 1
+}
+
 __device__ __forceinline__ uint32_t pair_slot(const short4* rects, const uint32_t* offsets, uint32_t rec, int tx,
                                               int ty) {
     const short4 rc = rects[rec];
@@ -181,7 +263,7 @@ __device__ __forceinline__ uint32_t pair_slot(const short4* rects, const uint32_
 template <typename T, int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
-    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
     const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
     const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
     const T* __restrict__ dPt, T* __restrict__ partials, uint32_t cap, uint32_t M) {
@@ -195,7 +277,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = (int)min(schedule[blockIdx.x], (uint32_t)(gridDim.x - 1));
     const int view = tile / V.tiles_per_view;
     const int t = tile - view * V.tiles_per_view;
     const int ty = t / V.tiles_x, tx = t - ty * V.tiles_x;
@@ -212,6 +294,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     int tgt = -2;
     if (inside) {
         lastp = last[o];
+        if (lastp < (int)rs || lastp >= (int)re) lastp = -1;  // not from this frame's forward: no work
         Tcur = tfinal[o];
         gc0 = dC[(view * 3 + 0) * HW + pix];
         gc1 = dC[(view * 3 + 1) * HW + pix];
@@ -229,15 +312,9 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     if (lastp >= 0) atomicMax(&s_maxlast, lastp);
     __syncthreads();
     const int maxlast = s_maxlast;
-    // Pairs behind every pixel's last blended Gaussian get zero partials.
+    // Pairs behind every pixel's last blended Gaussian keep the zero partials
+    // written before this kernel.
     const uint32_t hi = (maxlast >= (int)rs) ? (uint32_t)(maxlast + 1) : rs;
-    for (uint32_t pos = hi + tid; pos < re; pos += BLOCK) {
-        const uint32_t slot = pair_slot(rects, offsets, min(pvals[pos], M - 1), tx, ty);
-        if (slot < cap) {
-#pragma unroll
-            for (int k = 0; k < kGradWords; ++k) partials[(size_t)slot * kGradWords + k] = T(0);
-        }
-    }
     T S = Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
     int buf = 0;
     for (uint32_t bend = hi; bend > rs;) {
@@ -272,14 +349,14 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
                 if (!wave_any(contrib)) continue;
                 any = true;
                 const T a = contrib ? a0 : T(0);
-                const T oma = T(1) - a;
-                const T Ti = Tcur / oma;
+                const T roma = fast_rcp<T>(T(1) - a);
+                const T Ti = Tcur * roma;
                 const T w = a * Ti;
                 const int id = word_to_id<T>(sp[7]);
                 T vv = fmadd(gc0, sp[8], fmadd(gc1, sp[9], fmadd(gc2, sp[10], gd * sp[6])));
                 vv += (tgt >= 0 && id == tgt) ? gpt : T(0);
                 if (dP && contrib && id >= 0 && id < K) vv += dP[((int64_t)view * K + id) * HW + pix];
-                const T dalpha = contrib ? (Ti * vv - S / oma) : T(0);
+                const T dalpha = contrib ? (Ti * vv - S * roma) : T(0);
                 S = fmadd(w, vv, S);
                 Tcur = Ti;
                 v[c * kGradWords + 6] = gc0 * w;
@@ -324,6 +401,199 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     }
 }
 
+// Backward for 64-pixel tiles: the workgroup is one wavefront, so the
+// transposed wave sums are already the tile sums and no barrier is needed
+// between chunks.  Only Gaussians that contribute somewhere in the tile take a
+// reduction slot: the walk finds the next contributing Gaussian, fills slot c
+// (c = 0..5, a separate statically indexed code section each, so the slot
+// values stay in fixed registers), and after six slots the wave transposes and
+// sums them.  Pairs that take no slot get zero partials.
+template <typename T>
+__device__ __forceinline__ void flush_slots(T (&v)[64], int nslot, int lane, const uint32_t* s_chunk,
+                                            T* __restrict__ partials, uint32_t cap) {
+    wave_transpose_sum<T>(v, lane);
+    if (lane < nslot * kGradWords) {
+        const int c = lane / kGradWords;
+        const uint32_t slot = s_chunk[c];
+        if (slot < cap) partials[(size_t)slot * kGradWords + (lane - c * kGradWords)] = v[0];
+    }
+#pragma unroll
+    for (int k = 0; k < 64; ++k) v[k] = T(0);
+}
+
+template <int C>
+struct SlotIdx {
+    static constexpr int value = C;
+};
+
+template <typename T, int TW, int TH>
+__global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
+    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
+    const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
+    const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
+    const T* __restrict__ dPt, T* __restrict__ partials, uint32_t cap, uint32_t M) {
+    static_assert(TW * TH == kWave, "one wavefront per tile");
+    __shared__ __align__(16) T s_sp[kWave * kSplatWords];
+    __shared__ uint32_t s_slot[kWave];
+    __shared__ uint32_t s_chunk[kChunk];
+
+    const int lane = threadIdx.x;
+    const int tile = (int)min(schedule[blockIdx.x], (uint32_t)(gridDim.x - 1));
+    const int view = tile / V.tiles_per_view;
+    const int t = tile - view * V.tiles_per_view;
+    const int ty = t / V.tiles_x, tx = t - ty * V.tiles_x;
+    const int px = tx * TW + (lane % TW), py = ty * TH + (lane / TW);
+    const bool inside = px < V.W && py < V.H;
+    const int64_t HW = (int64_t)V.W * V.H;
+    const int64_t pix = (int64_t)py * V.W + px;
+    const int64_t o = view * HW + pix;
+    const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
+    const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
+
+    int lastp = -1;
+    T Tcur = T(1), gc0 = T(0), gc1 = T(0), gc2 = T(0), gd = T(0), gt = T(0), gpt = T(0);
+    int tgt = -2;
+    if (inside) {
+        lastp = last[o];
+        if (lastp < (int)rs || lastp >= (int)re) lastp = -1;  // not from this frame's forward: no work
+        Tcur = tfinal[o];
+        gc0 = dC[(view * 3 + 0) * HW + pix];
+        gc1 = dC[(view * 3 + 1) * HW + pix];
+        gc2 = dC[(view * 3 + 2) * HW + pix];
+        gd = dD ? dD[o] : T(0);
+        gt = dT ? dT[o] : T(0);
+        if (dPt && target) {
+            tgt = target[o];
+            gpt = dPt[o];
+            if (tgt == -1) gt += gpt;
+        }
+    }
+    int maxlast = lastp;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d));
+    // Pairs behind every pixel's last blended Gaussian, and pairs that
+    // contribute nowhere in the tile, keep the zero partials written before
+    // this kernel.
+    const uint32_t hi = (maxlast >= (int)rs) ? (uint32_t)(maxlast + 1) : rs;
+    T S = Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
+    T v[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) v[k] = T(0);
+
+    // walk state (wave-uniform): the LDS batch holds positions [bstart, bend)
+    uint32_t bend = hi, bstart = hi;
+    int jl = -1;
+    // contribution state of the Gaussian found by `next`
+    const T* sp = s_sp;
+    T dx = T(0), dy = T(0), G = T(0), a0 = T(0);
+    bool clamped = false, contrib = false;
+
+    // Software prefetch: batch A = [a_s, a_e) is held in registers (record and
+    // slot) while the current batch is walked; the pair indices of the batch
+    // after it (B) are loaded one step earlier still.
+    auto batch_lo = [&](uint32_t e) { return (e - rs > (uint32_t)kWave) ? e - kWave : rs; };
+    uint32_t a_e = hi, a_s = batch_lo(hi);
+    T pf[kSplatWords];
+    uint32_t pf_slot = 0u;
+    if (lane < (int)(a_e - a_s)) {
+        const uint32_t rec = min(pvals[a_s + lane], M - 1);
+        load_splat<T>(pf, splats + (size_t)rec * kSplatWords);
+        pf_slot = pair_slot(rects, offsets, rec, tx, ty);
+    }
+    uint32_t b_e = a_s, b_s = batch_lo(a_s);
+    uint32_t rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
+
+    // Advances to the next Gaussian (descending) that contributes at some pixel
+    // of the tile; false at the end of the range.
+    auto next = [&]() -> bool {
+        for (;;) {
+            if (jl < 0) {
+                if (a_e <= a_s) return false;
+                bend = a_e;
+                bstart = a_s;
+                const int nb = (int)(bend - bstart);
+                __syncthreads();
+                if (lane < nb) {
+                    store_splat_lds<T>(s_sp + lane * kSplatWords, pf);
+                    s_slot[lane] = pf_slot;
+                }
+                __syncthreads();
+                jl = nb - 1;
+                a_e = b_e;
+                a_s = b_s;
+                if (lane < (int)(a_e - a_s)) {
+                    load_splat<T>(pf, splats + (size_t)rec_b * kSplatWords);
+                    pf_slot = pair_slot(rects, offsets, rec_b, tx, ty);
+                }
+                b_e = a_s;
+                b_s = batch_lo(a_s);
+                rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
+            }
+            sp = s_sp + jl * kSplatWords;
+            const T Q = quad_form(sp, sx, sy, dx, dy);
+            const bool in = (Q <= cs.q_max) && ((int)(bstart + jl) <= lastp);
+            if (!wave_any(in)) {
+                --jl;
+                continue;
+            }
+            G = fast_exp<T>(T(-0.5) * Q);
+            const T araw = sp[5] * G;
+            clamped = !(araw < cs.alpha_max);
+            a0 = min(araw, cs.alpha_max);
+            contrib = in && (a0 >= cs.alpha_min);
+            if (!wave_any(contrib)) {
+                --jl;
+                continue;
+            }
+            return true;
+        }
+    };
+    // Gradient of the found Gaussian into slot C; advances the walk.
+    auto take = [&](auto cidx) {
+        constexpr int C = decltype(cidx)::value;
+        const T a = contrib ? a0 : T(0);
+        const T roma = fast_rcp<T>(T(1) - a);
+        const T Ti = Tcur * roma;
+        const T w = a * Ti;
+        const int id = word_to_id<T>(sp[7]);
+        T vv = fmadd(gc0, sp[8], fmadd(gc1, sp[9], fmadd(gc2, sp[10], gd * sp[6])));
+        vv += (tgt >= 0 && id == tgt) ? gpt : T(0);
+        if (dP && contrib && id >= 0 && id < K) vv += dP[((int64_t)view * K + id) * HW + pix];
+        const T dalpha = contrib ? (Ti * vv - S * roma) : T(0);
+        S = fmadd(w, vv, S);
+        Tcur = Ti;
+        const T dQ = clamped ? T(0) : dalpha * (T(-0.5) * a);
+        v[C * kGradWords + 0] = dQ * (T(-2) * (sp[2] * dx + sp[3] * dy));
+        v[C * kGradWords + 1] = dQ * (T(-2) * (sp[3] * dx + sp[4] * dy));
+        v[C * kGradWords + 2] = dQ * dx * dx;
+        v[C * kGradWords + 3] = dQ * T(2) * dx * dy;
+        v[C * kGradWords + 4] = dQ * dy * dy;
+        v[C * kGradWords + 5] = clamped ? T(0) : dalpha * G;
+        v[C * kGradWords + 6] = gc0 * w;
+        v[C * kGradWords + 7] = gc1 * w;
+        v[C * kGradWords + 8] = gc2 * w;
+        v[C * kGradWords + 9] = gd * w;
+        if (lane == 0) s_chunk[C] = s_slot[jl];
+        --jl;
+    };
+    for (;;) {
+        if (!next()) break;
+        take(SlotIdx<0>{});
+        if (!next()) { flush_slots<T>(v, 1, lane, s_chunk, partials, cap); break; }
+        take(SlotIdx<1>{});
+        if (!next()) { flush_slots<T>(v, 2, lane, s_chunk, partials, cap); break; }
+        take(SlotIdx<2>{});
+        if (!next()) { flush_slots<T>(v, 3, lane, s_chunk, partials, cap); break; }
+        take(SlotIdx<3>{});
+        if (!next()) { flush_slots<T>(v, 4, lane, s_chunk, partials, cap); break; }
+        take(SlotIdx<4>{});
+        if (!next()) { flush_slots<T>(v, 5, lane, s_chunk, partials, cap); break; }
+        take(SlotIdx<5>{});
+        flush_slots<T>(v, 6, lane, s_chunk, partials, cap);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename T, int TW, int TH>
 static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t st) {
@@ -333,12 +603,12 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
     if (img.probs && f.K > 0) {
         const size_t dyn = (size_t)f.K * TW * TH * sizeof(T);
         hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, true>), dim3(blocks), dim3(TW * TH), dyn, st, f.views,
-                           f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, (T*)img.color,
+                           f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)img.probs, img.id_map, img.target,
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items);
     } else {
         hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, false>), dim3(blocks), dim3(TW * TH), 0, st, f.views,
-                           f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, (T*)img.color,
+                           f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)nullptr, (int32_t*)nullptr, img.target,
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items);
     }
@@ -350,8 +620,16 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
     const int blocks = f.views.n_views * f.views.tiles_per_view;
     if (blocks == 0) return hipSuccess;
     const StatePtrs& s = f.s;
+    if constexpr (TW * TH == kWave) {
+        hipLaunchKernelGGL((render_backward_wave_kernel<T, TW, TH>), dim3(blocks), dim3(kWave), 0, st, f.views,
+                           f.consts, f.K, (const T*)s.splats, s.rects, s.offsets, s.pair_vals[0], s.ranges, s.schedule,
+                           (const T*)img.t_final, img.last, img.target, (const T*)g.d_color, (const T*)g.d_depth,
+                           (const T*)g.d_t_final, (const T*)g.d_probs, (const T*)g.d_p_target, (T*)s.partials,
+                           (uint32_t)s.capacity, (uint32_t)s.items);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((render_backward_kernel<T, TW, TH>), dim3(blocks), dim3(TW * TH), 0, st, f.views, f.consts,
-                       f.K, (const T*)s.splats, s.rects, s.offsets, s.pair_vals[0], s.ranges,
+                       f.K, (const T*)s.splats, s.rects, s.offsets, s.pair_vals[0], s.ranges, s.schedule,
                        (const T*)img.t_final, img.last, img.target, (const T*)g.d_color, (const T*)g.d_depth,
                        (const T*)g.d_t_final, (const T*)g.d_probs, (const T*)g.d_p_target, (T*)s.partials,
                        (uint32_t)s.capacity, (uint32_t)s.items);
@@ -372,6 +650,8 @@ hipError_t launch_render_forward(const Frame<T>& f, const dqo_images& img, hipSt
 template <typename T>
 hipError_t launch_render_backward(const Frame<T>& f, const dqo_images& img, const dqo_image_grads& g,
                                   hipStream_t st) {
+    const hipError_t z = launch_zero_partials<T>(f.s, st);
+    if (z != hipSuccess) return z;
     const int tw = f.views.tile_w, th = f.views.tile_h;
     if (tw == 16 && th == 16) return bwd_tile<T, 16, 16>(f, img, g, st);
     if (tw == 8 && th == 8) return bwd_tile<T, 8, 8>(f, img, g, st);

@@ -122,6 +122,42 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint
     ranges[2 * t + 1] = lower((uint32_t)t + 1u);
 }
 
+// Launch order of the render workgroups: tiles by decreasing pair count (in
+// power-of-two classes).  Workgroups are dispatched in index order and spread
+// round-robin over the XCDs and CUs, so the heaviest tiles, which are
+// spatially clustered, start first and on different compute units instead of
+// queueing on the same ones.  Order inside a class is arbitrary; results do
+// not depend on it (every tile writes only its own pixels and pair slots).
+constexpr int kSchedThreads = 1024;
+constexpr int kSchedClasses = 33;
+
+__global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint32_t* __restrict__ ranges,
+                                                                     int tiles, uint32_t* __restrict__ schedule) {
+    __shared__ uint32_t s_cnt[kSchedClasses];
+    __shared__ uint32_t s_off[kSchedClasses];
+    const int tid = threadIdx.x;
+    if (tid < kSchedClasses) s_cnt[tid] = 0u;
+    __syncthreads();
+    for (int t = tid; t < tiles; t += kSchedThreads) {
+        const uint32_t w = ranges[2 * t + 1] - ranges[2 * t];
+        atomicAdd(&s_cnt[w ? 32 - __clz(w) : 0], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t off = 0;
+        for (int c = kSchedClasses - 1; c >= 0; --c) {
+            s_off[c] = off;
+            off += s_cnt[c];
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < tiles; t += kSchedThreads) {
+        const uint32_t w = ranges[2 * t + 1] - ranges[2 * t];
+        const uint32_t pos = atomicAdd(&s_off[w ? 32 - __clz(w) : 0], 1u);
+        schedule[pos] = (uint32_t)t;
+    }
+}
+
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
                              uint64_t* lb, uint32_t* counter, Ctrl* ctrl, hipStream_t st) {
@@ -147,6 +183,8 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
     if (tiles_total > 0) {
         hipLaunchKernelGGL(tile_ranges_kernel, dim3((tiles_total + 255) / 256), dim3(256), 0, st, s.pair_keys[0],
                            n_dev, cap, s.ranges, tiles_total);
+        hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
+                           s.schedule);
     }
     return hipGetLastError();
 }
