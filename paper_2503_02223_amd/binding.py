@@ -333,10 +333,12 @@ class Rasterizer:
         self.cams, self.n, self.K, self.dtype, self.device = list(cams), int(n), int(K), dtype, device
         cap = capacity if capacity is not None else max(1024, 4 * n * len(cams))
         self.frame = Frame(self.ctx, self.cams, n, K, min(cap, 1 << 30), dtype, device)
+        self.generation = 0   # bumped by every bin(): identifies the pair list in the state
 
     def bin(self, params, ids, grow=True, stream=None):
         """project_cull_bin + sort; when grow is set, checks the pair count (a
         host synchronisation) and re-runs with a larger pair list on overflow."""
+        self.generation += 1
         f = self.frame
         f.project_cull_bin(params, ids, stream)
         if grow:
@@ -374,6 +376,8 @@ class RasterizeFunction(torch.autograd.Function):
         p = params.detach().contiguous()
         img = rasterizer.forward(p, ids, probs=want_probs and rasterizer.K > 0)
         ctx.rasterizer = rasterizer
+        ctx.generation = rasterizer.generation
+        ctx.ids = ids
         ctx.img = img
         ctx.want_probs = want_probs and rasterizer.K > 0
         ctx.save_for_backward(p)
@@ -384,6 +388,12 @@ class RasterizeFunction(torch.autograd.Function):
     def backward(ctx, d_color, d_depth, d_t_final, d_probs):
         (p,) = ctx.saved_tensors
         r: Rasterizer = ctx.rasterizer
+        if r.generation != ctx.generation:
+            # Another forward reused the pair list since: rebuild it from the saved
+            # parameters (binning and sorting are deterministic, so the positions
+            # stored in `last` refer to the same list again).
+            r.bin(p, ctx.ids)
+            ctx.generation = r.generation
         z = lambda t, like: (t.contiguous() if t is not None else torch.zeros_like(like))
         grads = dict(d_color=z(d_color, ctx.img["color"]), d_depth=z(d_depth, ctx.img["depth"]),
                      d_t_final=z(d_t_final, ctx.img["t_final"]))

@@ -1,0 +1,181 @@
+"""GPU: the autograd Function in FP64 (gradcheck against central differences
+and the oracle's adjoint), multi-view frames, and edge cases of the C ABI
+(empty input, everything culled, ragged image sizes, pair-list overflow,
+non-finite parameters)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2503_02223_amd import binding as B
+from paper_2503_02223_amd import scenes
+from tests.gpu_util import FWD_RTOL, GRAD_RTOL, close, to_dev, unambiguous
+
+pytestmark = pytest.mark.gpu
+
+
+def _tiny(seed):
+    return scenes.tiny_scene(seed=seed, n=64, width=32, height=32, f=40.0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradcheck_fp64_central_differences(oracle, seed):
+    sc = _tiny(seed)
+    cam = sc["cams"][0]
+    ref = oracle.render(sc["params"], sc["ids"], cam, K=sc["K"])
+    # outputs at pixels where a discrete decision is within the band of its
+    # threshold are masked out (a constant mask, so the masked map is smooth)
+    ok = unambiguous(ref, grads=True) & (ref["depth_gap"] > 1e-5)
+    assert ok.mean() > 0.9
+    mask = torch.tensor(ok, dtype=torch.float64, device="cuda")
+    r = B.Rasterizer(sc["cams"], 64, sc["K"], dtype=torch.float64)
+    ids = torch.tensor(sc["ids"], device="cuda")
+
+    def f(p):
+        C, D, T, P = B.rasterize(p, ids, r)
+        return C * mask, D * mask, T * mask, P * mask
+
+    p = to_dev(sc["params"], torch.float64).requires_grad_(True)
+    assert torch.autograd.gradcheck(f, (p,), eps=1e-6, atol=1e-6, rtol=1e-4, fast_mode=False)
+
+
+def test_fp64_autograd_matches_oracle_adjoint(oracle):
+    sc = _tiny(3)
+    cam = sc["cams"][0]
+    ref = oracle.render(sc["params"], sc["ids"], cam, K=sc["K"])
+    keep = unambiguous(ref, grads=True)
+    up = scenes.random_image_grads(5, (3, 32, 32), K=sc["K"])
+    for k in up:
+        up[k] = up[k] * keep
+    r = B.Rasterizer(sc["cams"], 64, sc["K"], dtype=torch.float64)
+    p = to_dev(sc["params"], torch.float64).requires_grad_(True)
+    C, D, T, P = B.rasterize(p, torch.tensor(sc["ids"], device="cuda"), r)
+    # FP64 forward agrees with the oracle to rounding
+    close(C[0].detach().cpu().numpy(), ref["C"], 1e-10, keep, "colour fp64")
+    L = ((C[0] * to_dev(up["gC"], torch.float64)).sum() + (D[0] * to_dev(up["gD"], torch.float64)).sum()
+         + (T[0] * to_dev(up["gT"], torch.float64)).sum() + (P[0] * to_dev(up["gP"], torch.float64)).sum())
+    L.backward()
+    go, _ = oracle.render_backward(sc["params"], sc["ids"], cam, K=sc["K"], **up)
+    close(p.grad.cpu().numpy(), go, 1e-9, what="fp64 grads")
+
+
+def test_fp32_autograd_matches_fp64():
+    sc = scenes.single_view_scene(seed=2, n=2000)
+    ids = torch.tensor(sc["ids"], device="cuda")
+    outs = []
+    for dt in (torch.float32, torch.float64):
+        r = B.Rasterizer(sc["cams"], 2000, 3, dtype=dt)
+        p = to_dev(sc["params"], dt).requires_grad_(True)
+        C, D, T, P = B.rasterize(p, ids, r)
+        w = torch.linspace(-1, 1, C.numel(), device="cuda", dtype=dt).view_as(C)
+        ((C * w).sum() + D.sum() * 0.1).backward()
+        outs.append((C.detach().double().cpu().numpy(), p.grad.double().cpu().numpy()))
+    close(outs[0][0], outs[1][0], FWD_RTOL, what="colour f32 vs f64")
+    # gradients agree up to the few pixels whose decisions differ between precisions
+    g32, g64 = outs[0][1], outs[1][1]
+    rel = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
+    assert rel < 1e-3, rel
+
+
+def test_multiview_forward_matches_single_views(oracle):
+    sc = scenes.room_scene(seed=4, n=3000, n_objects=5)
+    cams = scenes.ring_cameras(3, radius=4.0, width=96, height=72, f=80.0)
+    r = B.Rasterizer(cams, 3000, sc["K"])
+    p = to_dev(sc["params"])
+    ids = torch.tensor(sc["ids"], device="cuda")
+    img = r.forward(p, ids, probs=True)
+    torch.cuda.synchronize()
+    for v, cam in enumerate(cams):
+        ref = oracle.render(sc["params"], sc["ids"], cam, K=sc["K"])
+        ok = unambiguous(ref)
+        close(img["color"][v].cpu().numpy(), ref["C"], FWD_RTOL, ok, f"colour view {v}")
+        close(img["depth"][v].cpu().numpy(), ref["D"], FWD_RTOL, ok, f"depth view {v}")
+        close(img["probs"][v].cpu().numpy(), ref["P"], FWD_RTOL, ok, f"instance view {v}")
+
+
+def test_multiview_backward_sums_views(oracle):
+    sc = scenes.room_scene(seed=5, n=1500, n_objects=3)
+    cams = scenes.ring_cameras(2, radius=4.0, width=64, height=48, f=60.0)
+    r = B.Rasterizer(cams, 1500, sc["K"])
+    p = to_dev(sc["params"])
+    ids = torch.tensor(sc["ids"], device="cuda")
+    img = r.forward(p, ids)
+    go = np.zeros((14, 1500))
+    grads = {k: [] for k in ("d_color", "d_depth", "d_t_final")}
+    for v, cam in enumerate(cams):
+        ref = oracle.render(sc["params"], sc["ids"], cam, K=sc["K"])
+        keep = unambiguous(ref, grads=True)
+        up = scenes.random_image_grads(20 + v, (3, 48, 64))
+        for k in up:
+            up[k] = up[k] * keep
+        g, _ = oracle.render_backward(sc["params"], sc["ids"], cam, K=sc["K"], gC=up["gC"], gD=up["gD"], gT=up["gT"])
+        go += g
+        grads["d_color"].append(up["gC"])
+        grads["d_depth"].append(up["gD"])
+        grads["d_t_final"].append(up["gT"])
+    gd = {k: to_dev(np.stack(v)) for k, v in grads.items()}
+    g = r.backward(p, img, gd)
+    torch.cuda.synchronize()
+    close(g.cpu().numpy(), go, GRAD_RTOL, what="two-view grads")
+
+
+@pytest.mark.parametrize("W,H", [(100, 75), (7, 5), (16, 16), (129, 33)])
+def test_ragged_image_sizes(oracle, W, H):
+    sc = scenes.tiny_scene(seed=W, n=200, width=W, height=H, f=0.6 * W)
+    r = B.Rasterizer(sc["cams"], 200, sc["K"], ctx=B.Context(tile_w=8, tile_h=8))
+    img = r.forward(to_dev(sc["params"]), torch.tensor(sc["ids"], device="cuda"), probs=True)
+    torch.cuda.synchronize()
+    ref = oracle.render(sc["params"], sc["ids"], sc["cams"][0], K=sc["K"])
+    ok = unambiguous(ref)
+    close(img["color"][0].cpu().numpy(), ref["C"], FWD_RTOL, ok, "colour")
+    close(img["t_final"][0].cpu().numpy(), ref["Tf"], FWD_RTOL, ok, "T_final")
+
+
+def test_empty_and_all_culled():
+    cam = scenes.camera(width=40, height=30, cx=20, cy=15)
+    # n = 0
+    r = B.Rasterizer([cam], 0, 2)
+    img = r.forward(torch.zeros(14, 0, device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"), probs=True)
+    torch.cuda.synchronize()
+    assert (img["t_final"] == 1).all() and (img["color"] == 0).all() and (img["last"] == -1).all()
+    # every Gaussian behind the camera
+    sc = scenes.single_view_scene(seed=1, n=500)
+    p = sc["params"].copy()
+    p[2] = -np.abs(p[2])
+    r = B.Rasterizer([cam], 500, 3)
+    img = r.forward(to_dev(p), torch.tensor(sc["ids"], device="cuda"), probs=True)
+    rc, st, npairs = r.frame.read_status()
+    assert rc == 0 and npairs == 0
+    assert (img["t_final"] == 1).all() and (img["probs"] == 0).all()
+    grads = dict(d_color=torch.ones_like(img["color"]), d_depth=torch.ones_like(img["depth"]))
+    g = r.backward(to_dev(p), img, grads)
+    torch.cuda.synchronize()
+    assert (g == 0).all()
+
+
+def test_pair_overflow_is_reported():
+    sc = scenes.single_view_scene(seed=0, n=2000)
+    r = B.Rasterizer(sc["cams"], 2000, 3, capacity=1000)
+    r.frame.project_cull_bin(to_dev(sc["params"]), torch.tensor(sc["ids"], device="cuda"))
+    rc, st, npairs = r.frame.read_status()
+    assert rc == B.ECAPACITY and st & B.STATUS_OVERFLOW and npairs > 1000
+    # the grow path recovers
+    img = r.forward(to_dev(sc["params"]), torch.tensor(sc["ids"], device="cuda"))
+    rc, st, npairs2 = r.frame.read_status()
+    assert rc == 0 and npairs2 == npairs and r.frame.capacity >= npairs
+
+
+def test_nonfinite_parameters_are_flagged_and_culled(oracle):
+    sc = scenes.single_view_scene(seed=3, n=300)
+    p = sc["params"].copy()
+    p[0, 5] = np.nan
+    p[4, 17] = np.inf
+    r = B.Rasterizer(sc["cams"], 300, 3)
+    img = r.forward(to_dev(p), torch.tensor(sc["ids"], device="cuda"))
+    rc, st, _ = r.frame.read_status()
+    assert rc == B.ENONFINITE and st & B.STATUS_NONFINITE
+    assert torch.isfinite(img["color"]).all()
+    q = sc["params"].copy()
+    q[0, 5] = q[2, 5] = q[0, 17] = 0.0
+    q[2, 5] = q[2, 17] = -5.0  # behind the camera: culled like the non-finite ones
+    ref = oracle.render(q, sc["ids"], sc["cams"][0], K=3)
+    close(img["color"][0].cpu().numpy(), ref["C"], FWD_RTOL, unambiguous(ref), "colour without the bad Gaussians")
