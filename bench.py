@@ -27,6 +27,18 @@ MI355X_FP32_VECTOR_TFLOPS = 157.3   # published fp32 vector peak (256 CUs, 2.4 G
 # Algorithmic FLOPs of the render backward (see the design notes):
 FLOP_PER_EXAMINED = 11.0   # contribution test of one (pixel, pair) at or before the pixel's last blend
 FLOP_PER_BLENDED = 46.0    # gradient of one blended (pixel, Gaussian) incl. its share of the reduction
+# HBM bytes per launch of the render backward from rocprofv3 FETCH_SIZE + WRITE_SIZE
+# (scaled by a 256 MiB copy: x2.000 and x1.000), valid only for the kernel source
+# they were taken with (see profiles/); reported as null otherwise.
+MEASURED_TRAFFIC = {"render_src_sha256_16": "9810c6e35d9130d2", "bytes_per_launch": 182090729}
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2503_02223_amd", "csrc", "render.hip")
+    with open(src, "rb") as fh:
+        h = hashlib.sha256(fh.read()).hexdigest()[:16]
+    return MEASURED_TRAFFIC["bytes_per_launch"] if h == MEASURED_TRAFFIC["render_src_sha256_16"] else None
 
 
 def log(*a):
@@ -113,8 +125,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-pixels", type=int, default=49152)
     ap.add_argument("--tile", default="8x8", help="pixel tile WxH (8x8, 16x8, 16x16, 32x8, 8x32)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device-to-device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     tw, th = (int(x) for x in args.tile.split("x"))
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the multi-GPU (view-sharded) path is designed but not built; "
               "run with --gpus 1", file=sys.stderr)
@@ -158,7 +180,7 @@ def main():
     achieved = flops / (bwd_ms * 1e-3) / 1e12
     roof = dict(bound="alu", kernel=f"render_backward_kernel<float,{tw},{th}>", achieved=round(achieved, 3),
                 peak=MI355X_FP32_VECTOR_TFLOPS, unit="TFLOP/s", frac=round(achieved / MI355X_FP32_VECTOR_TFLOPS, 4),
-                traffic=None, avg_ms=round(bwd_ms, 4), examined_pairs=E, blended_pairs=Bn,
+                traffic=measured_traffic(), avg_ms=round(bwd_ms, 4), examined_pairs=E, blended_pairs=Bn,
                 flop_per_examined=FLOP_PER_EXAMINED, flop_per_blended=FLOP_PER_BLENDED)
     cpu = None
     if not args.no_cpu:

@@ -217,7 +217,9 @@ int dqo_project_cull_bin(const dqo_ctx* ctx, const dqo_frame_desc* desc, const d
 
 /* Stable radix sort of the pair list by global tile id (the list is already in
  * depth order, so the result is ordered by (tile, depth, item index)), then the
- * [start, end) range of every tile. */
+ * [start, end) range of every tile, the launch order of the render workgroups
+ * (heaviest tiles first), and zeroed per-pair gradient partials for
+ * dqo_render_backward. */
 int dqo_sort(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams, void* state,
              void* stream);
 

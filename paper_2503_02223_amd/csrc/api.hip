@@ -356,7 +356,13 @@ int dqo_sort(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     Geo g = geometry(ctx, d, cams);
     StatePtrs s = state_ptrs(g, state);
     const int tiles_total = g.L.tiles_x * g.L.tiles_y * d->n_views;
-    return run(ctx, "sort", [&] { return launch_pair_sort(s, tiles_total, (hipStream_t)stream); });
+    return run(ctx, "sort", [&] {
+        hipError_t e = launch_pair_sort(s, tiles_total, (hipStream_t)stream);
+        if (e != hipSuccess) return e;
+        // the render backward writes only the pairs that contribute in their tile
+        return d->dtype == DQO_F64 ? launch_zero_partials<double>(s, (hipStream_t)stream)
+                                   : launch_zero_partials<float>(s, (hipStream_t)stream);
+    });
 }
 
 int dqo_render_forward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const void* state,

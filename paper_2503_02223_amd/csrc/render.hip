@@ -650,8 +650,6 @@ hipError_t launch_render_forward(const Frame<T>& f, const dqo_images& img, hipSt
 template <typename T>
 hipError_t launch_render_backward(const Frame<T>& f, const dqo_images& img, const dqo_image_grads& g,
                                   hipStream_t st) {
-    const hipError_t z = launch_zero_partials<T>(f.s, st);
-    if (z != hipSuccess) return z;
     const int tw = f.views.tile_w, th = f.views.tile_h;
     if (tw == 16 && th == 16) return bwd_tile<T, 16, 16>(f, img, g, st);
     if (tw == 8 && th == 8) return bwd_tile<T, 8, 8>(f, img, g, st);
