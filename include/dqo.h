@@ -265,7 +265,23 @@ int dqo_project_backward(const dqo_ctx* ctx, const dqo_frame_desc* desc, const d
 int dqo_adam_step(const dqo_ctx* ctx, int32_t dtype, void* params, const void* grads, void* m, void* v,
                   int64_t n, const dqo_adam* hp /* host */, int64_t step, void* stream);
 
+/* Same update as dqo_adam_step, with the step count kept in device memory so
+ * that the call can be captured once in a HIP graph and replayed: the update
+ * uses step = *d_step + 1 and then stores it back into *d_step (int64, device,
+ * caller-owned, start at 0). */
+int dqo_adam_step_counted(const dqo_ctx* ctx, int32_t dtype, void* params, const void* grads, void* m, void* v,
+                          int64_t n, const dqo_adam* hp /* host */, int64_t* d_step, void* stream);
+
 /* ---- quadric -------------------------------------------------------------- */
+
+/* 2D boxes of every object in rendered id maps (the observed boxes from which
+ * the quadric of Eq. (1) is fitted): for view v and object k, the pixel-edge
+ * box (x0, y0, x1, y1) = (min u, min v, max u + 1, max v + 1) over pixels with
+ * id_map == k.  Outputs (device): boxes[V*K][4] double, box_obj[V*K] (k, or -1
+ * when the object covers no pixel of the view) and box_view[V*K] (v), in the
+ * input format of dqo_fit_dual_quadric.  id_map: [V][H][W] int32. */
+int dqo_id_boxes(const dqo_ctx* ctx, const int32_t* id_map, int32_t n_views, int32_t width, int32_t height,
+                 int32_t K, double* boxes, int32_t* box_obj, int32_t* box_view, void* stream);
 enum dqo_quadric_status { DQO_QUADRIC_OK = 0, DQO_QUADRIC_DEGENERATE = 1, DQO_QUADRIC_NOT_ELLIPSOID = 2 };
 
 /* Per-object dual quadric from 2D boxes (Eq. (1)): every box edge line l of

@@ -29,7 +29,8 @@ BUF_NAMES = ["splats", "rects", "counts", "offsets", "depth_keys", "depth_order"
 EXPORTED = ["dqo_config_default", "dqo_ctx_create", "dqo_ctx_destroy", "dqo_last_error", "dqo_status_string",
             "dqo_version", "dqo_state_layout", "dqo_state_init", "dqo_read_status", "dqo_clear_status",
             "dqo_project_cull_bin", "dqo_sort", "dqo_render_forward", "dqo_object_loss", "dqo_render_backward",
-            "dqo_project_backward", "dqo_adam_step", "dqo_fit_dual_quadric"]
+            "dqo_project_backward", "dqo_adam_step", "dqo_adam_step_counted", "dqo_fit_dual_quadric",
+            "dqo_id_boxes"]
 
 
 class Config(ctypes.Structure):
@@ -121,7 +122,9 @@ def lib():
     L.dqo_render_backward.argtypes = fr + [vp, P(Images), P(ImageGrads), vp]
     L.dqo_project_backward.argtypes = fr + [vp, vp, vp, vp]
     L.dqo_adam_step.argtypes = [ctx, i32, vp, vp, vp, vp, i64, P(AdamParams), i64, vp]
+    L.dqo_adam_step_counted.argtypes = [ctx, i32, vp, vp, vp, vp, i64, P(AdamParams), vp, vp]
     L.dqo_fit_dual_quadric.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp]
+    L.dqo_id_boxes.argtypes = [ctx, vp, i32, i32, i32, i32, vp, vp, vp, vp]
     for f in EXPORTED:
         if f not in ("dqo_config_default", "dqo_last_error", "dqo_status_string", "dqo_version"):
             getattr(L, f).restype = ctypes.c_int
@@ -303,6 +306,43 @@ def adam_step(ctx: Context, params, grads, m, v, lrs, step, beta1=0.9, beta2=0.9
                                   ctypes.byref(hp), int(step), _stream(stream)))
 
 
+def _adam_hp(lrs, beta1, beta2, eps):
+    hp = AdamParams()
+    for k in range(NUM_PARAMS):
+        hp.lr[k] = float(lrs[k])
+    hp.beta1, hp.beta2, hp.eps = beta1, beta2, eps
+    return hp
+
+
+def adam_step_counted(ctx: Context, params, grads, m, v, lrs, d_step, beta1=0.9, beta2=0.999, eps=1e-15,
+                      stream=None):
+    """Adam with the step count in device memory (graph-capturable)."""
+    hp = _adam_hp(lrs, beta1, beta2, eps)
+    dt = F64 if params.dtype == torch.float64 else F32
+    assert d_step.dtype == torch.int64 and d_step.numel() == 1
+    ctx.check(lib().dqo_adam_step_counted(ctx.h, dt, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.shape[-1],
+                                          ctypes.byref(hp), _ptr(d_step), _stream(stream)))
+
+
+def camera_matrix(cam) -> np.ndarray:
+    """3x4 projection P = K [R | t] of a camera dict (the P of the quadric fit)."""
+    Kc = np.array([[cam["fx"], 0.0, cam["cx"]], [0.0, cam["fy"], cam["cy"]], [0.0, 0.0, 1.0]])
+    Rt = np.concatenate([np.asarray(cam["R"], np.float64).reshape(3, 3),
+                         np.asarray(cam["t"], np.float64).reshape(3, 1)], axis=1)
+    return Kc @ Rt
+
+
+def id_boxes(ctx: Context, id_map: torch.Tensor, K: int, stream=None):
+    """Per (view, object) pixel-edge boxes of the rendered id maps [V][H][W]."""
+    V, H, W = id_map.shape
+    boxes = torch.empty(V * K, 4, dtype=torch.float64, device=id_map.device)
+    box_obj = torch.empty(V * K, dtype=torch.int32, device=id_map.device)
+    box_view = torch.empty(V * K, dtype=torch.int32, device=id_map.device)
+    ctx.check(lib().dqo_id_boxes(ctx.h, _ptr(id_map), V, W, H, K, _ptr(boxes), _ptr(box_obj), _ptr(box_view),
+                                 _stream(stream)))
+    return boxes, box_obj, box_view
+
+
 def fit_dual_quadric(ctx: Context, boxes, box_obj, box_view, Ps, n_obj, img_wh=None, border=1.0, stream=None):
     """Device tensors in, device tensors out (see dqo_fit_dual_quadric)."""
     dev = boxes.device
@@ -441,6 +481,7 @@ class Trainer:
         self.lrs = lrs if lrs is not None else default_lrs()
         self.lw = loss_weights
         self.step_count = 0
+        self.d_step = torch.zeros(1, dtype=torch.int64, device=dev)  # Adam step count on the device
 
     def step(self, stream=None):
         f = self.r.frame
@@ -451,7 +492,22 @@ class Trainer:
         f.render_backward(self.img, self.grads_img, stream)
         f.project_backward(self.params, self.grads, stream)
         self.step_count += 1
-        adam_step(self.r.ctx, self.params, self.grads, self.m, self.v, self.lrs, self.step_count, stream=stream)
+        adam_step_counted(self.r.ctx, self.params, self.grads, self.m, self.v, self.lrs, self.d_step, stream=stream)
+
+    def capture(self):
+        """Records one training step (every kernel of it, on one stream) in a
+        HIP graph; replaying the graph performs one more step."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.step()  # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.step_count -= 1  # the capture itself does not run
+        return g
 
     def check(self):
         rc, st, npairs = self.r.frame.read_status()

@@ -1,35 +1,64 @@
 // Adam over the structure-of-arrays parameter block [14][n] with one learning
-// rate per row (the optimizer the training loop uses; the paper trains with
-// PyTorch's optimizers).  The update follows PyTorch's order of operations:
+// rate per row.  The update follows PyTorch's order of operations:
 // m <- m + (1 - b1)(g - m); v <- b2 v + (1 - b2) g^2;
 // p <- p - (lr / bc1) * m / (sqrt(v) / sqrt(bc2) + eps).
+// The bias corrections come either from the host (step known at launch) or
+// from a step counter in device memory (graph-capturable: the same launch
+// replays every iteration).
 #include "dqo_device.hpp"
 
 namespace dqo {
 
 template <typename T>
 struct AdamArgs {
-    T step_size[kParams];  // lr / bc1 per row
-    T b1c, b2, b2c, inv_sqrt_bc2, eps;
+    double lr[kParams];
+    double beta1, beta2;
+    T b1c, b2, b2c, eps;
+    T step_size[kParams];  // lr / bc1 per row (host step)
+    T inv_sqrt_bc2;        // (host step)
 };
 
 template <typename T>
-__device__ __forceinline__ void adam_one(T& p, T g, T& m, T& v, T ss, const AdamArgs<T>& a) {
+__device__ __forceinline__ void adam_one(T& p, T g, T& m, T& v, T ss, T isb, const AdamArgs<T>& a) {
     m = m + a.b1c * (g - m);
     v = v * a.b2 + a.b2c * g * g;
-    const T denom = sqrt(v) * a.inv_sqrt_bc2 + a.eps;
+    const T denom = sqrt(v) * isb + a.eps;
     p = p - ss * (m / denom);
+}
+
+// Step size and 1/sqrt(bc2) of this row: from the host, or from the device
+// step counter (computed once per workgroup).
+template <typename T>
+__device__ __forceinline__ void step_factors(const AdamArgs<T>& a, const int64_t* d_step, int row, T& ss, T& isb) {
+    if (!d_step) {
+        ss = a.step_size[row];
+        isb = a.inv_sqrt_bc2;
+        return;
+    }
+    __shared__ T s_f[2];
+    if (threadIdx.x == 0) {
+        const double t = (double)(*d_step + 1);
+        const double bc1 = 1.0 - pow(a.beta1, t);
+        const double bc2 = 1.0 - pow(a.beta2, t);
+        s_f[0] = (T)(a.lr[row] / bc1);
+        s_f[1] = (T)(1.0 / sqrt(bc2));
+    }
+    __syncthreads();
+    ss = s_f[0];
+    isb = s_f[1];
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void adam_kernel(T* __restrict__ p, const T* __restrict__ g, T* __restrict__ m,
-                                                   T* __restrict__ v, int64_t n, AdamArgs<T> a) {
+                                                   T* __restrict__ v, int64_t n, AdamArgs<T> a,
+                                                   const int64_t* __restrict__ d_step) {
     const int row = blockIdx.y;
-    const T ss = a.step_size[row];
+    T ss, isb;
+    step_factors(a, d_step, row, ss, isb);
     const int64_t base = (int64_t)row * n;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         T pp = p[base + i], mm = m[base + i], vv = v[base + i];
-        adam_one(pp, g[base + i], mm, vv, ss, a);
+        adam_one(pp, g[base + i], mm, vv, ss, isb, a);
         p[base + i] = pp;
         m[base + i] = mm;
         v[base + i] = vv;
@@ -39,56 +68,68 @@ __global__ __launch_bounds__(256) void adam_kernel(T* __restrict__ p, const T* _
 // float4 path when rows are 16-byte aligned (n % 4 == 0).
 __global__ __launch_bounds__(256) void adam_kernel_vec4(float4* __restrict__ p, const float4* __restrict__ g,
                                                         float4* __restrict__ m, float4* __restrict__ v, int64_t n4,
-                                                        AdamArgs<float> a) {
+                                                        AdamArgs<float> a, const int64_t* __restrict__ d_step) {
     const int row = blockIdx.y;
-    const float ss = a.step_size[row];
+    float ss, isb;
+    step_factors(a, d_step, row, ss, isb);
     const int64_t base = (int64_t)row * n4;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256) {
         float4 pp = p[base + i], mm = m[base + i], vv = v[base + i];
         const float4 gg = g[base + i];
-        adam_one(pp.x, gg.x, mm.x, vv.x, ss, a);
-        adam_one(pp.y, gg.y, mm.y, vv.y, ss, a);
-        adam_one(pp.z, gg.z, mm.z, vv.z, ss, a);
-        adam_one(pp.w, gg.w, mm.w, vv.w, ss, a);
+        adam_one(pp.x, gg.x, mm.x, vv.x, ss, isb, a);
+        adam_one(pp.y, gg.y, mm.y, vv.y, ss, isb, a);
+        adam_one(pp.z, gg.z, mm.z, vv.z, ss, isb, a);
+        adam_one(pp.w, gg.w, mm.w, vv.w, ss, isb, a);
         p[base + i] = pp;
         m[base + i] = mm;
         v[base + i] = vv;
     }
 }
 
+__global__ void step_increment_kernel(int64_t* d_step) { *d_step += 1; }
+
 template <typename T>
-hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, const dqo_adam& hp, int64_t step, hipStream_t st) {
-    if (n == 0) return hipSuccess;
+hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, const dqo_adam& hp, int64_t step, int64_t* d_step,
+                       hipStream_t st) {
+    if (n == 0) {
+        if (d_step) hipLaunchKernelGGL(step_increment_kernel, dim3(1), dim3(1), 0, st, d_step);
+        return hipGetLastError();
+    }
     AdamArgs<T> a;
-    const double bc1 = 1.0 - pow(hp.beta1, (double)step);
-    const double bc2 = 1.0 - pow(hp.beta2, (double)step);
-    for (int r = 0; r < kParams; ++r) a.step_size[r] = (T)(hp.lr[r] / bc1);
+    for (int r = 0; r < kParams; ++r) a.lr[r] = hp.lr[r];
+    a.beta1 = hp.beta1;
+    a.beta2 = hp.beta2;
     a.b1c = (T)(1.0 - hp.beta1);
     a.b2 = (T)hp.beta2;
     a.b2c = (T)(1.0 - hp.beta2);
-    a.inv_sqrt_bc2 = (T)(1.0 / sqrt(bc2));
     a.eps = (T)hp.eps;
+    const double bc1 = 1.0 - pow(hp.beta1, (double)(step > 0 ? step : 1));
+    const double bc2 = 1.0 - pow(hp.beta2, (double)(step > 0 ? step : 1));
+    for (int r = 0; r < kParams; ++r) a.step_size[r] = (T)(hp.lr[r] / bc1);
+    a.inv_sqrt_bc2 = (T)(1.0 / sqrt(bc2));
     bool vec = sizeof(T) == 4 && (n % 4) == 0 && ((uintptr_t)p % 16) == 0 && ((uintptr_t)g % 16) == 0 &&
-                     ((uintptr_t)m % 16) == 0 && ((uintptr_t)v % 16) == 0;
+               ((uintptr_t)m % 16) == 0 && ((uintptr_t)v % 16) == 0;
     const int64_t len = vec ? n / 4 : n;
     int gx = (int)((len + 255) / 256);
     if (gx > 4096) gx = 4096;
+    bool done = false;
     if constexpr (sizeof(T) == 4) {
         if (vec) {
             hipLaunchKernelGGL(adam_kernel_vec4, dim3(gx, kParams), dim3(256), 0, st, (float4*)p, (const float4*)g,
-                               (float4*)m, (float4*)v, len, a);
-            return hipGetLastError();
+                               (float4*)m, (float4*)v, len, a, (const int64_t*)d_step);
+            done = true;
         }
     }
-    {
-        hipLaunchKernelGGL(adam_kernel<T>, dim3(gx, kParams), dim3(256), 0, st, p, g, m, v, n, a);
-    }
+    if (!done)
+        hipLaunchKernelGGL(adam_kernel<T>, dim3(gx, kParams), dim3(256), 0, st, p, g, m, v, n, a,
+                           (const int64_t*)d_step);
+    if (d_step) hipLaunchKernelGGL(step_increment_kernel, dim3(1), dim3(1), 0, st, d_step);
     return hipGetLastError();
 }
 
 template hipError_t launch_adam<float>(float*, const float*, float*, float*, int64_t, const dqo_adam&, int64_t,
-                                       hipStream_t);
-template hipError_t launch_adam<double>(double*, const double*, double*, double*, int64_t, const dqo_adam&,
-                                        int64_t, hipStream_t);
+                                       int64_t*, hipStream_t);
+template hipError_t launch_adam<double>(double*, const double*, double*, double*, int64_t, const dqo_adam&, int64_t,
+                                        int64_t*, hipStream_t);
 
 }  // namespace dqo

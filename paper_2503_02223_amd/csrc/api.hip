@@ -459,11 +459,41 @@ int dqo_adam_step(const dqo_ctx* ctx, int32_t dtype, void* params, const void* g
     if (dtype == DQO_F32)
         return run(ctx, "adam", [&] {
             return launch_adam<float>((float*)params, (const float*)grads, (float*)m, (float*)v, n, *hp, step,
-                                      (hipStream_t)stream);
+                                      nullptr, (hipStream_t)stream);
         });
     return run(ctx, "adam", [&] {
         return launch_adam<double>((double*)params, (const double*)grads, (double*)m, (double*)v, n, *hp, step,
+                                   nullptr, (hipStream_t)stream);
+    });
+}
+
+int dqo_adam_step_counted(const dqo_ctx* ctx, int32_t dtype, void* params, const void* grads, void* m, void* v,
+                          int64_t n, const dqo_adam* hp, int64_t* d_step, void* stream) {
+    if (!ctx) return DQO_EINVAL;
+    if (dtype != DQO_F32 && dtype != DQO_F64) return fail(ctx, DQO_EINVAL, "dtype %d unknown", dtype);
+    if (n < 0 || !hp || !d_step) return fail(ctx, DQO_EINVAL, "need n >= 0, hyper-parameters and a step counter");
+    if (n > 0 && (!params || !grads || !m || !v)) return fail(ctx, DQO_EINVAL, "adam buffers must not be NULL");
+    if (!(hp->beta1 >= 0 && hp->beta1 < 1 && hp->beta2 >= 0 && hp->beta2 < 1 && hp->eps >= 0))
+        return fail(ctx, DQO_EINVAL, "adam betas must lie in [0, 1) and eps >= 0");
+    if (dtype == DQO_F32)
+        return run(ctx, "adam", [&] {
+            return launch_adam<float>((float*)params, (const float*)grads, (float*)m, (float*)v, n, *hp, 1, d_step,
+                                      (hipStream_t)stream);
+        });
+    return run(ctx, "adam", [&] {
+        return launch_adam<double>((double*)params, (const double*)grads, (double*)m, (double*)v, n, *hp, 1, d_step,
                                    (hipStream_t)stream);
+    });
+}
+
+int dqo_id_boxes(const dqo_ctx* ctx, const int32_t* id_map, int32_t n_views, int32_t width, int32_t height,
+                 int32_t K, double* boxes, int32_t* box_obj, int32_t* box_view, void* stream) {
+    if (!ctx) return DQO_EINVAL;
+    if (n_views < 1 || n_views > DQO_MAX_VIEWS || width < 1 || height < 1 || K < 1 || K > DQO_MAX_K)
+        return fail(ctx, DQO_EINVAL, "id_boxes: bad sizes");
+    if (!id_map || !boxes || !box_obj || !box_view) return fail(ctx, DQO_EINVAL, "id_boxes: NULL buffer");
+    return run(ctx, "id_boxes", [&] {
+        return launch_id_boxes(id_map, n_views, width, height, K, boxes, box_obj, box_view, (hipStream_t)stream);
     });
 }
 

@@ -230,6 +230,49 @@ __global__ __launch_bounds__(64) void fit_quadric_kernel(int n_obj, int n_views,
     status[k] = st;
 }
 
+// Boxes of the objects in rendered id maps: one workgroup per view reduces the
+// per-object min/max pixel coordinates in LDS, then writes its K boxes.
+__global__ __launch_bounds__(256) void id_boxes_kernel(const int32_t* __restrict__ id_map, int W, int H, int K,
+                                                       double* __restrict__ boxes, int32_t* __restrict__ box_obj,
+                                                       int32_t* __restrict__ box_view) {
+    __shared__ int s_box[DQO_MAX_K][4];
+    const int v = blockIdx.x;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        s_box[k][0] = W;
+        s_box[k][1] = H;
+        s_box[k][2] = -1;
+        s_box[k][3] = -1;
+    }
+    __syncthreads();
+    const int32_t* im = id_map + (int64_t)v * W * H;
+    for (int64_t i = threadIdx.x; i < (int64_t)W * H; i += blockDim.x) {
+        const int k = im[i];
+        if (k < 0 || k >= K) continue;
+        const int u = (int)(i % W), y = (int)(i / W);
+        atomicMin(&s_box[k][0], u);
+        atomicMin(&s_box[k][1], y);
+        atomicMax(&s_box[k][2], u);
+        atomicMax(&s_box[k][3], y);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const int64_t b = (int64_t)v * K + k;
+        const bool seen = s_box[k][2] >= 0;
+        boxes[4 * b + 0] = seen ? (double)s_box[k][0] : 0.0;
+        boxes[4 * b + 1] = seen ? (double)s_box[k][1] : 0.0;
+        boxes[4 * b + 2] = seen ? (double)(s_box[k][2] + 1) : 0.0;
+        boxes[4 * b + 3] = seen ? (double)(s_box[k][3] + 1) : 0.0;
+        box_obj[b] = seen ? k : -1;
+        box_view[b] = v;
+    }
+}
+
+hipError_t launch_id_boxes(const int32_t* id_map, int n_views, int W, int H, int K, double* boxes, int32_t* box_obj,
+                           int32_t* box_view, hipStream_t st) {
+    hipLaunchKernelGGL(id_boxes_kernel, dim3(n_views), dim3(256), 0, st, id_map, W, H, K, boxes, box_obj, box_view);
+    return hipGetLastError();
+}
+
 hipError_t launch_fit_quadric(int n_obj, int64_t n_boxes, const double* boxes, const int32_t* box_obj,
                               const int32_t* box_view, int n_views, const double* P, const int32_t* img_wh,
                               double border, double* Q, double* mu, double* R, double* axes, int32_t* status,
