@@ -68,7 +68,16 @@ typedef struct {
     double qn[4];            /* normalised quaternion */
     double qnorm;
     double S3[9];            /* world covariance */
+    double ux, uy;           /* x/z, y/z as used in the Jacobian (limited) */
+    int ux_clamped, uy_clamped;
 } oproj;
+
+static void clamp_ratio(double u, double lim, double* out, int* clamped) {
+    *clamped = 0;
+    *out = u;
+    if (u > lim) { *out = lim; *clamped = 1; }
+    if (u < -lim) { *out = -lim; *clamped = 1; }
+}
 
 #define NPAR 14
 
@@ -109,9 +118,13 @@ static void project_one(const double* params, int64_t n, int64_t i, const ocam* 
     double z = p->z;
     p->mx = cam->fx * p->x / z + cam->cx;
     p->my = cam->fy * p->y / z + cam->cy;
-    /* J = d(pixel)/d(camera point); T2 = J W */
-    double J[6] = {cam->fx / z, 0, -cam->fx * p->x / (z * z),
-                   0, cam->fy / z, -cam->fy * p->y / (z * z)};
+    /* J = d(pixel)/d(camera point), evaluated with x/z and y/z limited to 1.3
+     * times the half field of view (the linearisation is meaningless far
+     * outside the view); T2 = J W */
+    clamp_ratio(p->x / z, 1.3 * 0.5 * cam->width / cam->fx, &p->ux, &p->ux_clamped);
+    clamp_ratio(p->y / z, 1.3 * 0.5 * cam->height / cam->fy, &p->uy, &p->uy_clamped);
+    double J[6] = {cam->fx / z, 0, -cam->fx * p->ux / z,
+                   0, cam->fy / z, -cam->fy * p->uy / z};
     double T2[6];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 3; ++b) {
@@ -284,7 +297,7 @@ static void project_backward_one(const double* params, int64_t n, int64_t i, con
     double dc = dA * (1.0 / det - a * c / det2) + dB * (a * b / det2) + dC * (-a * a / det2);
     /* symmetric gradient of Sigma2 (b appears in both off-diagonal slots) */
     double G2[4] = {da, 0.5 * db, 0.5 * db, dc};
-    double J[6] = {fx / z, 0, -fx * x / (z * z), 0, fy / z, -fy * y / (z * z)};
+    double J[6] = {fx / z, 0, -fx * p->ux / z, 0, fy / z, -fy * p->uy / z};
     double T2[6];
     for (int r = 0; r < 2; ++r)
         for (int s = 0; s < 3; ++s) {
@@ -323,11 +336,21 @@ static void project_backward_one(const double* params, int64_t n, int64_t i, con
             dJ[r * 3 + s] = acc;
         }
     double dpx = 0, dpy = 0, dpz = 0;
-    /* J entries: J00 = fx/z, J02 = -fx x/z^2, J11 = fy/z, J12 = -fy y/z^2 */
-    dpx += dJ[2] * (-fx / (z * z));
-    dpy += dJ[5] * (-fy / (z * z));
-    dpz += dJ[0] * (-fx / (z * z)) + dJ[2] * (2 * fx * x / (z * z * z)) + dJ[4] * (-fy / (z * z)) +
-           dJ[5] * (2 * fy * y / (z * z * z));
+    /* J entries: J00 = fx/z, J02 = -fx ux/z, J11 = fy/z, J12 = -fy uy/z with
+     * ux = x/z (or the constant limit when clamped), likewise uy */
+    dpz += dJ[0] * (-fx / (z * z)) + dJ[4] * (-fy / (z * z));
+    if (p->ux_clamped) {
+        dpz += dJ[2] * (fx * p->ux / (z * z));
+    } else {
+        dpx += dJ[2] * (-fx / (z * z));
+        dpz += dJ[2] * (2 * fx * x / (z * z * z));
+    }
+    if (p->uy_clamped) {
+        dpz += dJ[5] * (fy * p->uy / (z * z));
+    } else {
+        dpy += dJ[5] * (-fy / (z * z));
+        dpz += dJ[5] * (2 * fy * y / (z * z * z));
+    }
     /* 2D mean */
     dpx += g2d[0] * fx / z;
     dpz += g2d[0] * (-fx * x / (z * z));

@@ -177,6 +177,8 @@ Frame<T> make_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camer
         dc.fy = (T)cams[v].fy;
         dc.cx = (T)cams[v].cx;
         dc.cy = (T)cams[v].cy;
+        dc.limx = (T)(1.3 * 0.5 * cams[v].width / cams[v].fx);
+        dc.limy = (T)(1.3 * 0.5 * cams[v].height / cams[v].fy);
     }
     f.views.n_views = d->n_views;
     f.views.W = cams[0].width;

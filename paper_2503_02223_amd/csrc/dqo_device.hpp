@@ -48,6 +48,7 @@ struct DevCam {
     T R[9];
     T t[3];
     T fx, fy, cx, cy;
+    T limx, limy;  // |x/z|, |y/z| limits of the projection Jacobian (1.3 x half field of view)
 };
 
 // Everything a kernel needs to know about the views (passed by value).
@@ -132,15 +133,6 @@ __device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* words, int stri
     }
     lb_store(words + (size_t)slot * stride, lb_pack(kFlagInclusive, epoch, excl + agg));
     return excl;
-}
-
-// Tile index of this block, remapped so that each of the 8 XCDs (which take
-// blocks round-robin) works on one contiguous run of tiles and keeps their
-// shared splat records in its own L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7;
-    const int xcd = b & 7, k = b >> 3;
-    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
 }
 
 template <typename T>

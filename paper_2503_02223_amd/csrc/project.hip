@@ -52,6 +52,8 @@ struct Proj {
     T A, B, C;        // conic
     T mx, my;
     T o;
+    T ux, uy;  // x/z and y/z as used in the Jacobian (after the frustum limit)
+    bool ux_clamped, uy_clamped;
     bool visible;
 };
 
@@ -71,8 +73,14 @@ __device__ __forceinline__ void project_item(const DevCam<T>& c, const Consts<T>
     r.visible = r.z > cs.z_near;
     if (!r.visible) return;
     const T iz = T(1) / r.z;
-    const T j00 = c.fx * iz, j02 = -c.fx * r.x * iz * iz;
-    const T j11 = c.fy * iz, j12 = -c.fy * r.y * iz * iz;
+    // The Jacobian is evaluated at x/z, y/z limited to the frustum widened by 30%.
+    const T ux = r.x * iz, uy = r.y * iz;
+    r.ux = fmin(fmax(ux, -c.limx), c.limx);
+    r.uy = fmin(fmax(uy, -c.limy), c.limy);
+    r.ux_clamped = ux > c.limx || ux < -c.limx;
+    r.uy_clamped = uy > c.limy || uy < -c.limy;
+    const T j00 = c.fx * iz, j02 = -c.fx * r.ux * iz;
+    const T j11 = c.fy * iz, j12 = -c.fy * r.uy * iz;
     T T2[6];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -404,8 +412,8 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
         }
         // U = T2 M with T2 = J W, M = R diag(s)
         const T iz = T(1) / pr.z;
-        const T j00 = c.fx * iz, j02 = -c.fx * pr.x * iz * iz;
-        const T j11 = c.fy * iz, j12 = -c.fy * pr.y * iz * iz;
+        const T j00 = c.fx * iz, j02 = -c.fx * pr.ux * iz;
+        const T j11 = c.fy * iz, j12 = -c.fy * pr.uy * iz;
         T T2[6], Mm[9];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -433,11 +441,23 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
         const T dj11 = dT2[3] * W[3] + dT2[4] * W[4] + dT2[5] * W[5];
         const T dj12 = dT2[3] * W[6] + dT2[4] * W[7] + dT2[5] * W[8];
         const T iz2 = iz * iz, iz3 = iz2 * iz;
-        T dpx = dj02 * (-c.fx * iz2) + d[0] * c.fx * iz;
-        T dpy = dj12 * (-c.fy * iz2) + d[1] * c.fy * iz;
-        T dpz = dj00 * (-c.fx * iz2) + dj02 * (T(2) * c.fx * pr.x * iz3) + dj11 * (-c.fy * iz2) +
-                dj12 * (T(2) * c.fy * pr.y * iz3) + d[0] * (-c.fx * pr.x * iz2) + d[1] * (-c.fy * pr.y * iz2) +
-                d[9];
+        // A clamped ratio is a constant: J02 = -fx lim / z then depends on z alone.
+        T dpx = d[0] * c.fx * iz;
+        T dpy = d[1] * c.fy * iz;
+        T dpz = dj00 * (-c.fx * iz2) + dj11 * (-c.fy * iz2) + d[0] * (-c.fx * pr.x * iz2) +
+                d[1] * (-c.fy * pr.y * iz2) + d[9];
+        if (pr.ux_clamped) {
+            dpz += dj02 * (c.fx * pr.ux * iz2);
+        } else {
+            dpx += dj02 * (-c.fx * iz2);
+            dpz += dj02 * (T(2) * c.fx * pr.x * iz3);
+        }
+        if (pr.uy_clamped) {
+            dpz += dj12 * (c.fy * pr.uy * iz2);
+        } else {
+            dpy += dj12 * (-c.fy * iz2);
+            dpz += dj12 * (T(2) * c.fy * pr.y * iz3);
+        }
         acc[0] += W[0] * dpx + W[3] * dpy + W[6] * dpz;
         acc[1] += W[1] * dpx + W[4] * dpy + W[7] * dpz;
         acc[2] += W[2] * dpx + W[5] * dpy + W[8] * dpz;

@@ -41,11 +41,13 @@ def look_at(position, target, **intr):
     return camera(R=R, t=-R @ c, **intr)
 
 
-def ring_cameras(n_views=8, radius=2.0, width=640, height=480, f=600.0):
-    """Keyframes on a horizontal ring around the room centre, facing it."""
+def ring_cameras(n_views=8, radius=2.0, width=640, height=480, f=600.0, angles=None):
+    """Keyframes on a horizontal ring around the room centre, facing it, at
+    the given angles (default: evenly spaced)."""
     cams = []
-    for j in range(n_views):
-        a = 2 * np.pi * j / n_views
+    if angles is None:
+        angles = 2 * np.pi * np.arange(n_views) / n_views
+    for a in angles:
         pos = np.array([radius * np.sin(a), 0.0, -radius * np.cos(a)])
         cams.append(look_at(pos, np.zeros(3), fx=f, fy=f, cx=width / 2, cy=height / 2,
                             width=width, height=height))
@@ -77,11 +79,25 @@ def single_view_scene(seed=0, n=2000):
     return dict(params=pack(mu, ls, q, eta, rgb), ids=ids, cams=[cam], K=3)
 
 
+def _surface_points(rng, m):
+    """Points uniform (by area) on the six faces of the room box."""
+    lo, hi = ROOM_LO, ROOM_HI
+    ext = hi - lo
+    areas = np.array([ext[1] * ext[2], ext[1] * ext[2], ext[0] * ext[2], ext[0] * ext[2],
+                      ext[0] * ext[1], ext[0] * ext[1]])
+    face = rng.choice(6, size=m, p=areas / areas.sum())
+    pts = rng.uniform(lo, hi, size=(m, 3))
+    axis = face // 2
+    pts[np.arange(m), axis] = np.where(face % 2 == 0, lo[axis], hi[axis])
+    return pts
+
+
 def room_scene(seed=0, n=200_000, n_objects=20, background_frac=0.3, blob_sigma=0.3,
-               object_counts=None, logscale=(-4.0, 0.7), eta_sigma=1.5):
+               object_counts=None, logscale=(-4.0, 0.7), eta_sigma=1.5, background="volume", centres=None):
     """Gaussians clustered into object blobs (means N(centre, blob_sigma^2),
-    centres uniform in the 6x4x3 m room) plus uniformly placed background
-    Gaussians with id 0; objects have ids 1..n_objects."""
+    centres uniform in the 6x4x3 m room unless given) plus background
+    Gaussians with id 0, uniform in the room's volume or on its walls, floor
+    and ceiling (background="surface"); objects have ids 1..n_objects."""
     rng = np.random.default_rng(seed)
     if object_counts is None:
         n_bg = int(round(background_frac * n))
@@ -92,8 +108,10 @@ def room_scene(seed=0, n=200_000, n_objects=20, background_frac=0.3, blob_sigma=
         counts = np.asarray(object_counts, dtype=np.int64)
         n_bg = n - counts.sum()
         assert n_bg >= 0
-    centres = rng.uniform(ROOM_LO, ROOM_HI, size=(n_objects, 3))
-    mus, ids = [rng.uniform(ROOM_LO, ROOM_HI, size=(n_bg, 3))], [np.zeros(n_bg, np.int32)]
+    drawn = rng.uniform(ROOM_LO, ROOM_HI, size=(n_objects, 3))
+    centres = drawn if centres is None else np.asarray(centres, np.float64)
+    bg = rng.uniform(ROOM_LO, ROOM_HI, size=(n_bg, 3)) if background == "volume" else _surface_points(rng, n_bg)
+    mus, ids = [bg], [np.zeros(n_bg, np.int32)]
     for k in range(n_objects):
         mus.append(rng.normal(centres[k], blob_sigma, size=(counts[k], 3)))
         ids.append(np.full(counts[k], k + 1, np.int32))
@@ -116,12 +134,23 @@ def slam_view_scene(seed=0, n=200_000):
 
 
 def keyframe_scene(seed=0, n_total=1_200_000, n_objects=40, n_views=8):
-    """40 objects with Gaussian counts log-uniform in [1k, 80k], topped up with
-    background Gaussians to n_total; 8 ring keyframes at 640x480."""
+    """40 objects with Gaussian counts log-uniform in [1k, 80k] (blob sigma
+    0.06 m, log-scales N(-4.5, 0.4), so that objects mostly stay apart),
+    topped up with background Gaussians on the room's walls, floor and ceiling
+    to n_total (a volume-filling background would hide every object from
+    cameras inside the room).  The 8 keyframes sit at seeded random angles on
+    a 2 m ring at 640x480, facing the room centre; object centres are uniform
+    in the upright cylinder of radius 1.2 m and height 1.6 m inside the ring,
+    so that each object lies in front of the cameras."""
     rng = np.random.default_rng(seed + 1000)
     counts = np.exp(rng.uniform(np.log(1e3), np.log(8e4), size=n_objects)).astype(np.int64)
-    sc = room_scene(seed=seed, n=n_total, n_objects=n_objects, object_counts=counts)
-    sc["cams"] = ring_cameras(n_views)
+    r = 1.2 * np.sqrt(rng.uniform(0, 1, n_objects))
+    phi = rng.uniform(0, 2 * np.pi, n_objects)
+    centres = np.stack([r * np.cos(phi), rng.uniform(-0.8, 0.8, n_objects), r * np.sin(phi)], axis=1)
+    angles = np.sort(rng.uniform(0, 2 * np.pi, n_views))
+    sc = room_scene(seed=seed, n=n_total, n_objects=n_objects, object_counts=counts, background="surface",
+                    blob_sigma=0.06, logscale=(-4.5, 0.4), centres=centres)
+    sc["cams"] = ring_cameras(n_views, angles=angles)
     return sc
 
 

@@ -296,3 +296,41 @@ def test_quadric_fit_parity(oracle):
         R0 = objs[k][1]
         np.testing.assert_allclose(M, R0 @ np.diag(objs[k][2] ** 2) @ R0.T, atol=1e-9)
         assert abs(np.linalg.det(Rg) - 1) < 1e-9
+
+
+def test_jacobian_frustum_limit_parity(oracle):
+    """A narrow field of view (f = 300 on 128x96): most Gaussians sit beyond
+    1.3x the half field of view, and a quarter of them are large enough to
+    reach into the image, so the clamped Jacobian and its adjoint are used."""
+    sc = scenes.single_view_scene(seed=9, n=2000)
+    sc["params"][3:6, ::4] += 1.5
+    cam = scenes.camera(fx=300, fy=300, cx=64, cy=48, width=128, height=96)
+    sc["cams"] = [cam]
+    p0 = sc["params"]
+    u, v = p0[0] / p0[2], p0[1] / p0[2]
+    clamped = (np.abs(u) > 1.3 * 64 / 300) | (np.abs(v) > 1.3 * 48 / 300)
+    assert clamped.mean() > 0.3
+    H, W, K = cam["height"], cam["width"], sc["K"]
+    r, p, ids = _frame(sc, ctx=B.Context(tile_w=16, tile_h=16))
+    img = r.forward(p, ids, probs=True)
+    torch.cuda.synchronize()
+    pr = oracle.project(p0, cam)
+    spl = r.frame.buf("splats", torch.float32, 2000 * 12).view(2000, 12).cpu().numpy()
+    vis = pr["visible"] & clamped
+    for k, name in ((2, "A"), (3, "B"), (4, "C")):
+        close(spl[vis, k], pr[name][vis], FWD_RTOL, what=name)
+    ref = _oracle_fwd(oracle, sc)
+    ok = unambiguous(ref)
+    assert ok.mean() > 0.95
+    close(img["color"][0].cpu().numpy(), ref["C"], FWD_RTOL, ok, "colour")
+    close(img["depth"][0].cpu().numpy(), ref["D"], FWD_RTOL, ok, "depth")
+    keep = unambiguous(ref, grads=True)
+    up = _sparse_upstream(31, ref, H, W, K, keep)
+    grads = dict(d_color=to_dev(up["gC"][None]), d_depth=to_dev(up["gD"][None]), d_t_final=to_dev(up["gT"][None]),
+                 d_probs=to_dev(up["gP"][None]))
+    g = r.backward(p, img, grads)
+    torch.cuda.synchronize()
+    go, _ = oracle.render_backward(p0, sc["ids"], cam, K=K, **up)
+    # the clamped Gaussians receive gradient, and it matches
+    assert np.abs(go[:6][:, clamped]).max() > 0
+    close(g.cpu().numpy(), go, GRAD_RTOL, what="param grads")

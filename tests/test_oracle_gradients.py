@@ -70,3 +70,39 @@ def test_adjoint_with_background_colour(oracle):
             p[r, i] = old
             fd = (lp - lm) / (2 * h)
             assert grads[r, i] == pytest.approx(fd, rel=1e-4, abs=1e-7)
+
+
+def test_adjoint_with_jacobian_frustum_limit(oracle):
+    """Large Gaussians centred outside 1.3x the half field of view (so their
+    Jacobian is clamped) whose footprints still cover the image."""
+    sc = scenes.tiny_scene(seed=8, n=12, width=20, height=16, f=25.0)
+    p = sc["params"].copy()
+    cam = sc["cams"][0]
+    z = p[2, :6]
+    # x/z = +-0.7 and y/z = 0.6 lie beyond 1.3 * 10/25 = 0.52 and 1.3 * 8/25 = 0.416
+    p[0, :6] = np.array([0.7, -0.7, 0.1, 0.7, -0.7, 0.0]) * z
+    p[1, :6] = np.array([0.0, 0.1, 0.6, 0.6, -0.6, -0.6]) * z
+    p[3:6, :6] = -0.4
+    sc["params"] = p
+    pr = oracle.project(p, cam)
+    u, v = p[0] / p[2], p[1] / p[2]
+    assert np.all((np.abs(u[:6]) > 0.52) | (np.abs(v[:6]) > 0.416))
+    base = oracle.render(p, sc["ids"], cam, K=sc["K"])
+    assert pr["visible"][:6].all()
+    w = scenes.random_image_grads(21, (3, cam["height"], cam["width"]), K=sc["K"])
+    keep = (base["margin"] > 1e-4) & (base["margin_clamp"] > 1e-4) & (base["depth_gap"] > 1e-5)
+    for k in w:
+        w[k] = w[k] * keep
+    grads, _ = oracle.render_backward(p, sc["ids"], cam, K=sc["K"], **w)
+    h = 1e-6
+    for r in range(6):   # mean and log-scale: the parameters the clamp acts on
+        for i in range(6):
+            old = p[r, i]
+            p[r, i] = old + h
+            lp = _loss(oracle, p, sc, w)
+            p[r, i] = old - h
+            lm = _loss(oracle, p, sc, w)
+            p[r, i] = old
+            fd = (lp - lm) / (2 * h)
+            assert grads[r, i] == pytest.approx(fd, rel=1e-4, abs=1e-7), (r, i)
+    assert np.abs(grads[:6, :6]).max() > 1e-3

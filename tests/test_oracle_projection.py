@@ -68,3 +68,26 @@ def test_culling_near_plane_and_behind(oracle):
                         _one([0, 0, 0.25], [-3] * 3, [1, 0, 0, 0])], axis=1)
     pr = oracle.project(p, cam)
     assert list(pr["visible"]) == [False, False, True]
+
+
+@pytest.mark.parametrize("ratio", [(0.9, 0.1), (-1.2, 0.3), (0.2, -0.95), (1.5, 1.4)])
+def test_jacobian_frustum_limit(oracle, ratio):
+    """Outside 1.3x the half field of view the Jacobian is that of the pinhole
+    map at the point moved onto the limit (x/z, y/z clamped, z kept); the 2D
+    mean stays the unclamped projection."""
+    cam = scenes.camera(fx=110, fy=100, cx=64, cy=48, width=128, height=96)
+    lx, ly = 1.3 * 0.5 * 128 / 110, 1.3 * 0.5 * 96 / 100
+    z = 2.5
+    pc = np.array([ratio[0] * z, ratio[1] * z, z])
+    rng = np.random.default_rng(5)
+    ls, q = rng.normal(-1.5, 0.3, 3), rng.normal(size=4)
+    pr = oracle.project(_one(pc, ls, q), cam)
+    clamped = np.array([np.clip(ratio[0], -lx, lx) * z, np.clip(ratio[1], -ly, ly) * z, z])
+    h = 1e-6
+    Jfd = np.stack([(_pix(cam, clamped + h * e) - _pix(cam, clamped - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+    qn = q / np.linalg.norm(q)
+    Rq = Rotation.from_quat([qn[1], qn[2], qn[3], qn[0]]).as_matrix()
+    S2 = Jfd @ Rq @ np.diag(np.exp(2 * ls)) @ Rq.T @ Jfd.T + 0.3 * np.eye(2)
+    got = np.array([[pr["s00"][0], pr["s01"][0]], [pr["s01"][0], pr["s11"][0]]])
+    np.testing.assert_allclose(got, S2, rtol=1e-7, atol=1e-9 * np.abs(S2).max())
+    np.testing.assert_allclose([pr["mx"][0], pr["my"][0]], _pix(cam, pc), rtol=1e-12)
