@@ -94,7 +94,12 @@ typedef struct dqo_camera {
     int32_t width, height;
 } dqo_camera;
 
-/* Size of one frame of work.  All views must share width and height. */
+/* Size of one frame of work.  All views must share width and height.
+ * segments (host memory, read at every call that takes the descriptor) is
+ * either NULL, in which case every view sees all n Gaussians, or
+ * [n_views][2] = (first, count): view v sees Gaussians [first, first + count)
+ * only.  Segments let one launch render independent Gaussian sets (object
+ * crops, per-object jobs) each in its own view; they may overlap. */
 typedef struct dqo_frame_desc {
     int64_t n;             /* Gaussians, >= 0 */
     int32_t n_views;       /* 1..DQO_MAX_VIEWS */
@@ -102,6 +107,7 @@ typedef struct dqo_frame_desc {
     int64_t pair_capacity; /* max (tile, Gaussian) pairs over all views, <= 2^30 */
     int32_t dtype;         /* DQO_F32 or DQO_F64 */
     int32_t reserved;
+    const int64_t* segments; /* NULL or [n_views][2] (first, count), within [0, n] */
 } dqo_frame_desc;
 
 /* Sub-buffers of the caller-allocated state buffer (dqo_state_layout). */

@@ -47,7 +47,8 @@ class Camera(ctypes.Structure):
 
 class FrameDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_views", ctypes.c_int32), ("K", ctypes.c_int32),
-                ("pair_capacity", ctypes.c_int64), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("pair_capacity", ctypes.c_int64), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("segments", ctypes.POINTER(ctypes.c_int64))]
 
 
 class Layout(ctypes.Structure):
@@ -201,7 +202,7 @@ class Frame:
     """Caller-owned device state of one frame of work (n Gaussians, V views)."""
 
     def __init__(self, ctx: Context, cams: Sequence[dict], n: int, K: int, capacity: int,
-                 dtype=torch.float32, device="cuda"):
+                 dtype=torch.float32, device="cuda", segments=None):
         self.ctx = ctx
         self.cam_dicts = list(cams)
         self.cams = make_cameras(cams)
@@ -209,6 +210,11 @@ class Frame:
         self.tdtype = dtype
         self.device = torch.device(device)
         self.desc = FrameDesc(n=int(n), n_views=len(cams), K=int(K), pair_capacity=int(capacity), dtype=self.dt)
+        self.segments = None
+        if segments is not None:   # [V][2] (first, count); kept alive with the descriptor
+            seg = np.ascontiguousarray(np.asarray(segments, dtype=np.int64).reshape(len(cams), 2))
+            self.segments = (ctypes.c_int64 * seg.size)(*seg.ravel().tolist())
+            self.desc.segments = ctypes.cast(self.segments, ctypes.POINTER(ctypes.c_int64))
         self.layout = Layout()
         ctx.check(lib().dqo_state_layout(ctx.h, ctypes.byref(self.desc), self.cams, ctypes.byref(self.layout)))
         self.state = torch.empty(int(self.layout.total), dtype=torch.uint8, device=self.device)
@@ -368,12 +374,16 @@ class Rasterizer:
     """Frame + image buffers for a fixed camera set, with capacity management."""
 
     def __init__(self, cams: Sequence[dict], n: int, K: int, capacity: Optional[int] = None,
-                 dtype=torch.float32, ctx: Optional[Context] = None, device="cuda"):
+                 dtype=torch.float32, ctx: Optional[Context] = None, device="cuda", segments=None):
         self.ctx = ctx if ctx is not None else Context()
         self.cams, self.n, self.K, self.dtype, self.device = list(cams), int(n), int(K), dtype, device
-        cap = capacity if capacity is not None else max(1024, 4 * n * len(cams))
-        self.frame = Frame(self.ctx, self.cams, n, K, min(cap, 1 << 30), dtype, device)
+        self.segments = segments
+        cap = capacity if capacity is not None else max(1024, 4 * n * (len(cams) if segments is None else 1))
+        self.frame = self._new_frame(min(cap, 1 << 30))
         self.generation = 0   # bumped by every bin(): identifies the pair list in the state
+
+    def _new_frame(self, capacity):
+        return Frame(self.ctx, self.cams, self.n, self.K, capacity, self.dtype, self.device, segments=self.segments)
 
     def bin(self, params, ids, grow=True, stream=None):
         """project_cull_bin + sort; when grow is set, checks the pair count (a
@@ -385,7 +395,7 @@ class Rasterizer:
             rc, st, npairs = f.read_status(stream)
             if st & STATUS_OVERFLOW:
                 cap = min(1 << 30, int(math.ceil(npairs * 1.25)) + 1024)
-                self.frame = f = Frame(self.ctx, self.cams, self.n, self.K, cap, self.dtype, self.device)
+                self.frame = f = self._new_frame(cap)
                 f.project_cull_bin(params, ids, stream)
                 rc, st, npairs = f.read_status(stream)
             if st & STATUS_TIMEOUT:
@@ -454,17 +464,18 @@ class Trainer:
     with preallocated buffers and no host synchronisation."""
 
     def __init__(self, params: torch.Tensor, ids: torch.Tensor, cams, K, targets: Dict[str, torch.Tensor],
-                 lrs=None, capacity=None, loss_weights=(1.0, 1.0, 1.0), ctx=None):
+                 lrs=None, capacity=None, loss_weights=(1.0, 1.0, 1.0), ctx=None, segments=None):
         self.params = params.contiguous()
         self.ids = ids
         self.n = params.shape[1]
         self.dtype = params.dtype
-        self.r = Rasterizer(cams, self.n, K, capacity=capacity, dtype=self.dtype, ctx=ctx)
+        self.r = Rasterizer(cams, self.n, K, capacity=capacity, dtype=self.dtype, ctx=ctx, segments=segments,
+                            device=params.device)
         self.r.bin(self.params, ids, grow=True)  # sizes the pair list once
         if self.r.frame.capacity < (1 << 30):   # headroom for pairs added while training
             cap = min(1 << 30, int(self.r.frame.read_status()[2] * 1.5) + 4096)
             if cap > self.r.frame.capacity:
-                self.r.frame = Frame(self.r.ctx, self.r.cams, self.n, K, cap, self.dtype, params.device)
+                self.r.frame = self.r._new_frame(cap)
                 self.r.bin(self.params, ids, grow=True)
         f = self.r.frame
         self.targets = targets

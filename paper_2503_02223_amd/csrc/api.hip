@@ -64,6 +64,14 @@ int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera
         return fail(ctx, DQO_EINVAL, "pair_capacity = %lld outside [0, 2^30]", (long long)d->pair_capacity);
     if ((int64_t)d->n * d->n_views > (int64_t(1) << 31) - 1)
         return fail(ctx, DQO_EINVAL, "n * n_views must be < 2^31");
+    if (d->segments) {
+        for (int v = 0; v < d->n_views; ++v) {
+            const int64_t first = d->segments[2 * v], count = d->segments[2 * v + 1];
+            if (first < 0 || count < 0 || first + count > d->n)
+                return fail(ctx, DQO_EINVAL, "segment of view %d = [%lld, +%lld) outside [0, %lld)", v,
+                            (long long)first, (long long)count, (long long)d->n);
+        }
+    }
     const int W = cams[0].width, H = cams[0].height;
     if (W < 1 || H < 1 || W > 32767 || H > 32767) return fail(ctx, DQO_EINVAL, "image size %dx%d invalid", W, H);
     for (int v = 0; v < d->n_views; ++v) {
@@ -179,6 +187,8 @@ Frame<T> make_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camer
         dc.cy = (T)cams[v].cy;
         dc.limx = (T)(1.3 * 0.5 * cams[v].width / cams[v].fx);
         dc.limy = (T)(1.3 * 0.5 * cams[v].height / cams[v].fy);
+        dc.seg_lo = d->segments ? (int32_t)d->segments[2 * v] : 0;
+        dc.seg_hi = d->segments ? (int32_t)(d->segments[2 * v] + d->segments[2 * v + 1]) : (int32_t)d->n;
     }
     f.views.n_views = d->n_views;
     f.views.W = cams[0].width;
@@ -264,7 +274,7 @@ int dqo_ctx_destroy(dqo_ctx* ctx) {
 
 const char* dqo_last_error(const dqo_ctx* ctx) { return ctx ? ctx->err : "NULL context"; }
 
-const char* dqo_version(void) { return "dqo 0.1 gfx950"; }
+const char* dqo_version(void) { return "dqo 0.2 gfx950"; }
 
 const char* dqo_status_string(int code) {
     switch (code) {

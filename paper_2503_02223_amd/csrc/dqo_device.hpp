@@ -49,6 +49,7 @@ struct DevCam {
     T t[3];
     T fx, fy, cx, cy;
     T limx, limy;  // |x/z|, |y/z| limits of the projection Jacobian (1.3 x half field of view)
+    int32_t seg_lo, seg_hi;  // Gaussians [seg_lo, seg_hi) are seen by this view
 };
 
 // Everything a kernel needs to know about the views (passed by value).

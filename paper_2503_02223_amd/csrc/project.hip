@@ -120,17 +120,18 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
     if (i < M) {
         const int v = (int)(i / n);
         const int64_t g = i - (int64_t)v * n;
+        const bool in_seg = g >= V.cam[v].seg_lo && g < V.cam[v].seg_hi;
         T p[kParams];
         bool finite = true;
 #pragma unroll
         for (int r = 0; r < kParams; ++r) {
-            p[r] = params[(int64_t)r * n + g];
+            p[r] = in_seg ? params[(int64_t)r * n + g] : T(0);
             finite = finite && isfinite(p[r]);
         }
         if (!finite) atomicOr(&ctrl->status, (uint32_t)DQO_STATUS_NONFINITE);
         Proj<T> pr;
         pr.visible = false;
-        if (finite) project_item(V.cam[v], cs, p, pr);
+        if (finite && in_seg) project_item(V.cam[v], cs, p, pr);
         uint32_t cnt = 0;
         short4 rc = make_short4(0, 0, -1, -1);
         T w[kSplatWords];
@@ -383,6 +384,7 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
 #pragma unroll
     for (int r = 0; r < kParams; ++r) acc[r] = T(0);
     for (int v = 0; v < V.n_views; ++v) {
+        if (g < V.cam[v].seg_lo || g >= V.cam[v].seg_hi) continue;
         const int64_t item = (int64_t)v * n + g;
         const uint32_t cnt = counts[item];
         if (cnt == 0) continue;

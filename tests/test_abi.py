@@ -83,3 +83,17 @@ def test_null_pointers_rejected_before_launch():
     assert L.dqo_adam_step(ctx.h, B.F32, None, None, None, None, 0, ctypes.byref(hp), 0, None) == B.EINVAL
     assert L.dqo_fit_dual_quadric(ctx.h, 2, 4, None, None, None, 1, None, None, 1.0, None, None, None, None,
                                   None, None) == B.EINVAL
+
+
+def test_segments_validated_on_host():
+    ctx = B.Context()
+    sc = scenes.single_view_scene(n=100)
+    cams = B.make_cameras(sc["cams"] * 2)
+    L = B.Layout()
+    for seg, ok in (([0, 60, 60, 40], True), ([0, 100, 0, 100], True), ([0, 0, 100, 0], True),
+                    ([0, 60, 60, 41], False), ([-1, 10, 0, 5], False), ([0, -2, 0, 5], False)):
+        arr = (ctypes.c_int64 * 4)(*seg)
+        d = B.FrameDesc(n=100, n_views=2, K=3, pair_capacity=5000, dtype=B.F32,
+                        segments=ctypes.cast(arr, ctypes.POINTER(ctypes.c_int64)))
+        rc = B.lib().dqo_state_layout(ctx.h, ctypes.byref(d), cams, ctypes.byref(L))
+        assert (rc == 0) == ok, seg
