@@ -31,6 +31,18 @@ EXPORTED = ["dqo_config_default", "dqo_ctx_create", "dqo_ctx_destroy", "dqo_last
             "dqo_project_cull_bin", "dqo_sort", "dqo_render_forward", "dqo_object_loss", "dqo_render_backward",
             "dqo_project_backward", "dqo_adam_step", "dqo_adam_step_counted", "dqo_fit_dual_quadric",
             "dqo_id_boxes"]
+# include/dqo_learned.h
+EXPORTED_LEARNED = ["dqo_net_layout_get", "dqo_net_workspace_size", "dqo_net_pack", "dqo_net_forward", "dqo_net_loss",
+                    "dqo_net_backward", "dqo_adam_flat", "dqo_init_gaussians", "dqo_init_labels", "dqo_net_fallback",
+                    "dqo_masked_psnr"]
+NET_LAYERS = 4
+
+
+class NetLayout(ctypes.Structure):
+    _fields_ = [("cin", ctypes.c_int32 * NET_LAYERS), ("cout", ctypes.c_int32 * NET_LAYERS),
+                ("cin_pad", ctypes.c_int32 * NET_LAYERS), ("cout_pad", ctypes.c_int32 * NET_LAYERS),
+                ("w_offset", ctypes.c_int64 * NET_LAYERS), ("b_offset", ctypes.c_int64 * NET_LAYERS),
+                ("wk_offset", ctypes.c_int64 * NET_LAYERS), ("n_params", ctypes.c_int64), ("w_elems", ctypes.c_int64)]
 
 
 class Config(ctypes.Structure):
@@ -126,7 +138,18 @@ def lib():
     L.dqo_adam_step_counted.argtypes = [ctx, i32, vp, vp, vp, vp, i64, P(AdamParams), vp, vp]
     L.dqo_fit_dual_quadric.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp]
     L.dqo_id_boxes.argtypes = [ctx, vp, i32, i32, i32, i32, vp, vp, vp, vp]
-    for f in EXPORTED:
+    L.dqo_net_layout_get.argtypes = [P(NetLayout)]
+    L.dqo_net_workspace_size.argtypes = [i32, i32, i32, P(i64)]
+    L.dqo_net_pack.argtypes = [ctx, vp, vp, vp, vp]
+    L.dqo_net_forward.argtypes = [ctx, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+    L.dqo_net_loss.argtypes = [ctx, i32, i32, i32, vp, vp, vp, P(d), vp, vp, vp]
+    L.dqo_net_backward.argtypes = [ctx, i32, i32, i32, vp, vp, vp, vp]
+    L.dqo_adam_flat.argtypes = [ctx, vp, vp, vp, vp, i64, d, d, d, d, vp, vp]
+    L.dqo_init_gaussians.argtypes = [ctx, i32, i32, i32, vp, P(Camera), vp, vp, vp, i64, vp, vp, i32, vp]
+    L.dqo_init_labels.argtypes = [ctx, i32, i32, i32, vp, P(Camera), vp, vp, i64, vp, vp]
+    L.dqo_net_fallback.argtypes = [ctx, i32, i32, i32, vp, vp, d, vp, vp, vp]
+    L.dqo_masked_psnr.argtypes = [ctx, i32, i32, i32, vp, vp, vp, vp]
+    for f in EXPORTED + EXPORTED_LEARNED:
         if f not in ("dqo_config_default", "dqo_last_error", "dqo_status_string", "dqo_version"):
             getattr(L, f).restype = ctypes.c_int
     _lib = L

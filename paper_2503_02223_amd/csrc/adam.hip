@@ -1,5 +1,5 @@
-// Adam over the structure-of-arrays parameter block [14][n] with one learning
-// rate per row.  The update follows PyTorch's order of operations:
+// Adam over the structure-of-arrays parameter block [rows][n] (rows = 14 for
+// Gaussians, 1 for a flat vector) with one learning rate per row.  The update follows PyTorch's order of operations:
 // m <- m + (1 - b1)(g - m); v <- b2 v + (1 - b2) g^2;
 // p <- p - (lr / bc1) * m / (sqrt(v) / sqrt(bc2) + eps).
 // The bias corrections come either from the host (step known at launch) or
@@ -90,7 +90,7 @@ __global__ void step_increment_kernel(int64_t* d_step) { *d_step += 1; }
 
 template <typename T>
 hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, const dqo_adam& hp, int64_t step, int64_t* d_step,
-                       hipStream_t st) {
+                       hipStream_t st, int rows) {
     if (n == 0) {
         if (d_step) hipLaunchKernelGGL(step_increment_kernel, dim3(1), dim3(1), 0, st, d_step);
         return hipGetLastError();
@@ -115,21 +115,21 @@ hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, const dqo_adam& 
     bool done = false;
     if constexpr (sizeof(T) == 4) {
         if (vec) {
-            hipLaunchKernelGGL(adam_kernel_vec4, dim3(gx, kParams), dim3(256), 0, st, (float4*)p, (const float4*)g,
+            hipLaunchKernelGGL(adam_kernel_vec4, dim3(gx, rows), dim3(256), 0, st, (float4*)p, (const float4*)g,
                                (float4*)m, (float4*)v, len, a, (const int64_t*)d_step);
             done = true;
         }
     }
     if (!done)
-        hipLaunchKernelGGL(adam_kernel<T>, dim3(gx, kParams), dim3(256), 0, st, p, g, m, v, n, a,
+        hipLaunchKernelGGL(adam_kernel<T>, dim3(gx, rows), dim3(256), 0, st, p, g, m, v, n, a,
                            (const int64_t*)d_step);
     if (d_step) hipLaunchKernelGGL(step_increment_kernel, dim3(1), dim3(1), 0, st, d_step);
     return hipGetLastError();
 }
 
 template hipError_t launch_adam<float>(float*, const float*, float*, float*, int64_t, const dqo_adam&, int64_t,
-                                       int64_t*, hipStream_t);
+                                       int64_t*, hipStream_t, int);
 template hipError_t launch_adam<double>(double*, const double*, double*, double*, int64_t, const dqo_adam&, int64_t,
-                                        int64_t*, hipStream_t);
+                                        int64_t*, hipStream_t, int);
 
 }  // namespace dqo

@@ -5,30 +5,12 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "ctx.hpp"
 #include "dqo_device.hpp"
-
-struct dqo_ctx {
-    dqo_config cfg;
-    mutable char err[512];
-};
 
 namespace {
 
 using namespace dqo;
-
-int fail(const dqo_ctx* c, int code, const char* fmt, ...) {
-    if (c) {
-        va_list ap;
-        va_start(ap, fmt);
-        vsnprintf(c->err, sizeof(c->err), fmt, ap);
-        va_end(ap);
-    }
-    return code;
-}
-
-int hip_fail(const dqo_ctx* c, hipError_t e, const char* where) {
-    return fail(c, DQO_EHIP, "%s: %s", where, hipGetErrorString(e));
-}
 
 bool tile_ok(int tw, int th) {
     return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 32 && th == 8) ||

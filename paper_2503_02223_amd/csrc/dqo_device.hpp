@@ -235,7 +235,7 @@ hipError_t launch_object_loss(const Frame<T>& f, const dqo_images& img, const dq
                               hipStream_t st);
 template <typename T>
 hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, const dqo_adam& hp, int64_t step, int64_t* d_step,
-                       hipStream_t st);
+                       hipStream_t st, int rows = kParams);
 hipError_t launch_id_boxes(const int32_t* id_map, int n_views, int W, int H, int K, double* boxes, int32_t* box_obj,
                            int32_t* box_view, hipStream_t st);
 hipError_t launch_fit_quadric(int n_obj, int64_t n_boxes, const double* boxes, const int32_t* box_obj,
