@@ -245,11 +245,86 @@ def bench_large(args):
     print(json.dumps(out), flush=True)
 
 
+LEARNED_MODEL = os.path.join(ROOT, "paper_2503_02223_amd", "data", "learned_init.npz")
+HELD_OUT_SEED, VAL_SEED, TRAIN_SEED = 3, 2, 1
+
+
+def eval_learned(ctx, model_path, n_objects=20, iters=300):
+    """Time-to-PSNR of the learned initialization on held-out crops (seeded
+    superquadric objects never used in training)."""
+    from paper_2503_02223_amd import learned as L
+    crops = L.make_crop_set(HELD_OUT_SEED, n_objects)
+    net, chan_w, thr = L.load_model(model_path, ctx=ctx)
+    recs, summary = L.time_to_psnr(ctx, net, thr, crops, iters=iters)
+    if summary["mean_seconds_learned"]:
+        summary["speedup_seconds"] = round(summary["mean_seconds_plain"] / summary["mean_seconds_learned"], 3)
+        summary["speedup_iters"] = round(iters / max(summary["mean_iters_learned"], 1e-9), 3)
+    summary["model"] = os.path.relpath(model_path, ROOT)
+    return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in summary.items()}, recs
+
+
+def bench_learned(args):
+    """Learned initialization end to end: 128x128 object crops, labels from the
+    plain optimizer (300 iterations per crop, 16 crops per launch), network
+    training with the MFMA kernels, fallback threshold on a validation split,
+    then time-to-PSNR on 20 held-out objects."""
+    from paper_2503_02223_amd import learned as L
+    t0 = time.time()
+    crops_tr = L.make_crop_set(TRAIN_SEED, args.n_train, workers=args.workers)
+    crops_val = L.make_crop_set(VAL_SEED, args.n_val, workers=args.workers)
+    t_data = time.time() - t0
+    log(f"crops: {crops_tr.shape[0]} train, {crops_val.shape[0]} validation in {t_data:.1f} s")
+    torch.cuda.init()
+    ctx = B.Context()
+    t0 = time.time()
+    rg, lab = L.generate_labels(ctx, crops_tr, iters=args.label_iters, log=log)
+    t_labels = time.time() - t0
+    chan_w = L.channel_weights(crops_tr, lab)
+    log(f"labels in {t_labels:.1f} s; channel weights {chan_w}")
+    net = L.Net(ctx, seed=0)
+    hist, t_train = L.train_net(net, rg, lab, chan_w, steps=args.train_steps, batch=args.batch, lr=args.lr,
+                                log=log)
+    thr = L.choose_threshold(net, torch.tensor(crops_val, device="cuda"))
+    os.makedirs(os.path.dirname(args.save), exist_ok=True)
+    L.save_model(args.save, net, chan_w, thr, dict(n_train=args.n_train, label_iters=args.label_iters,
+                                                   train_steps=args.train_steps, batch=args.batch, lr=args.lr))
+    log(f"model saved to {args.save}; threshold {thr:.4f}")
+    del rg, lab
+    summary, recs = eval_learned(ctx, args.save, n_objects=args.n_test, iters=args.label_iters)
+    for r in recs:
+        log(json.dumps(r))
+    out = {
+        "metric": "time-to-PSNR learned vs plain init", "value": summary.get("mean_seconds_learned"), "unit": "s",
+        "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "bf16 net / f32 rasterizer",
+        "data": "synthetic",
+        "config": {"workload": f"{args.n_train} training + {args.n_val} validation + {args.n_test} held-out "
+                               "superquadric crops 128x128 (f=110); labels = Gaussians after "
+                               f"{args.label_iters} plain-optimizer iterations; target = plain PSNR after "
+                               f"{args.label_iters} iterations",
+                   "train_steps": args.train_steps, "batch": args.batch},
+        "learned_init": summary,
+        "timing_s": {"crops_cpu": round(t_data, 2), "labels_gpu": round(t_labels, 2), "train_gpu": round(t_train, 2)},
+        "train_loss": hist,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="slam", choices=["slam", "keyframes", "large"],
+    ap.add_argument("--workload", default="slam", choices=["slam", "keyframes", "large", "learned-init"],
                     help="slam: 200k Gaussians at 640x480 (default, the headline line); keyframes: 8 views over "
-                         "1.2M Gaussians in a HIP graph; large: 1M at 1200x680 through autograd")
+                         "1.2M Gaussians in a HIP graph; large: 1M at 1200x680 through autograd; learned-init: "
+                         "train the initialization network and measure time-to-PSNR")
+    ap.add_argument("--n-train", type=int, default=5000)
+    ap.add_argument("--n-val", type=int, default=256)
+    ap.add_argument("--n-test", type=int, default=20)
+    ap.add_argument("--label-iters", type=int, default=300)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--save", default=os.path.join(ROOT, "gpurun_out", "learned_init.npz"))
+    ap.add_argument("--no-learned", action="store_true", help="skip the time-to-PSNR part of the default run")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
@@ -273,6 +348,8 @@ def main():
         print("bench.py measures one GPU only: the multi-GPU (view-sharded) path is designed but not built; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "learned-init":
+        return bench_learned(args)  # generates its crops before the GPU is touched
     torch.cuda.init()
     if args.workload == "keyframes":
         return bench_keyframes(args)
@@ -322,6 +399,10 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(sc, n_pix=args.cpu_pixels)
+    learned = None
+    if not args.no_learned and os.path.exists(LEARNED_MODEL):
+        log("time-to-PSNR of the learned initialization on 20 held-out objects")
+        learned, _ = eval_learned(B.Context(), LEARNED_MODEL)
     out = {
         "metric": METRIC, "value": round(1e3 / ms, 2), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
@@ -331,7 +412,7 @@ def main():
                                "object CE) + render bwd + project bwd + Adam",
                    "n_gaussians": args.n, "width": 640, "height": 480, "K": sc["K"], "pairs": npairs,
                    "tile": args.tile, "loss": [round(x, 6) for x in loss]},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "learned_init": learned,
     }
     print(json.dumps(out), flush=True)
 

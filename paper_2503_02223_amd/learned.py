@@ -257,3 +257,162 @@ def label_batch(ctx, rgbdm_np: np.ndarray, iters=300, device="cuda"):
     opt.run(iters)
     labels = init_labels(ctx, rgbdm, opt.cams, opt.off_dev, opt.tr.params)
     return rgbdm, labels, opt
+
+
+# ---------------------------------------------------------------- pipeline
+def make_crop_set(seed, count, workers=1):
+    """count crops (numpy, (count, 5, 128, 128) float32), generated in chunks of
+    16 with seeds seed * 100003 + chunk, optionally by a pool of processes
+    (call it before the GPU is touched: the workers only run numpy)."""
+    chunks = [(seed * 100003 + c, min(16, count - 16 * c)) for c in range((count + 15) // 16)]
+    if workers > 1 and len(chunks) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.starmap(CR.make_crops, chunks)
+    else:
+        parts = [CR.make_crops(s, c) for s, c in chunks]
+    return np.concatenate(parts, 0)
+
+
+def generate_labels(ctx, crops_np: np.ndarray, iters=300, device="cuda", log=None):
+    """Labels of every crop from `iters` plain-optimizer iterations, 16 crops
+    per launch.  Returns (rgbdm, labels) as device tensors."""
+    n = crops_np.shape[0]
+    rgbdm = torch.tensor(crops_np, device=device)
+    labels = torch.empty(n, 5, crops_np.shape[2], crops_np.shape[3], dtype=torch.float32, device=device)
+    t0 = time.time()
+    for s in range(0, n, B.MAX_VIEWS):
+        e = min(n, s + B.MAX_VIEWS)
+        rg = rgbdm[s:e]
+        opt = CropOptimizer(ctx, rg, crops_np[s:e])
+        opt.run(iters)
+        init_labels(ctx, rg, opt.cams, opt.off_dev, opt.tr.params, labels=labels[s:e])
+        opt.tr.check()
+        if log and (s // B.MAX_VIEWS) % 50 == 0:
+            torch.cuda.synchronize()
+            log(f"labels {e}/{n} ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return rgbdm, labels
+
+
+def channel_weights(crops_np, labels: torch.Tensor):
+    """1 / variance of each label channel over the valid pixels."""
+    ok = torch.tensor((crops_np[:, 4] > 0.5) & (crops_np[:, 3] > 0), device=labels.device)
+    w = []
+    for c in range(5):
+        v = labels[:, c][ok]
+        w.append(float(1.0 / max(v.var().item(), 1e-6)))
+    return w
+
+
+def train_net(net: Net, rgbdm, labels, chan_w, steps=3000, batch=32, lr=2e-3, seed=0, log=None):
+    """Adam on random batches; the learning rate decays by cosine to 5% of lr."""
+    rng = np.random.default_rng(seed)
+    n = rgbdm.shape[0]
+    xb = torch.empty((batch,) + tuple(rgbdm.shape[1:]), dtype=torch.float32, device=rgbdm.device)
+    lb = torch.empty((batch,) + tuple(labels.shape[1:]), dtype=torch.float32, device=rgbdm.device)
+    out = torch.empty(batch, NET_OUT, rgbdm.shape[2], rgbdm.shape[3], dtype=torch.float32, device=rgbdm.device)
+    hist = []
+    t0 = time.time()
+    for it in range(steps):
+        idx = torch.tensor(rng.choice(n, batch, replace=False), device=rgbdm.device)
+        torch.index_select(rgbdm, 0, idx, out=xb)
+        torch.index_select(labels, 0, idx, out=lb)
+        cur = lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * it / max(1, steps))))
+        net.train_step(xb, lb, chan_w, cur, out=out)
+        if it % 250 == 0 or it == steps - 1:
+            hist.append((it, float(net.loss[0].item()), float(net.loss[1].item())))
+            if log:
+                log(f"train step {it}: loss {hist[-1][1]:.4f} fit {hist[-1][2]:.4f} ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return hist, time.time() - t0
+
+
+def predict(net: Net, rgbdm, batch=32):
+    outs = []
+    for s in range(0, rgbdm.shape[0], batch):
+        outs.append(net.forward(rgbdm[s:s + batch].contiguous()))
+    return torch.cat(outs, 0)
+
+
+def choose_threshold(net: Net, rgbdm_val, quantile=0.95):
+    """Fallback threshold: the given quantile of the validation crops' mean
+    predicted log-error."""
+    out = predict(net, rgbdm_val)
+    _, mean = net.fallback(rgbdm_val, out, float("inf"))
+    return float(np.quantile(mean.cpu().numpy(), quantile))
+
+
+def save_model(path, net: Net, chan_w, threshold, meta: dict):
+    np.savez(path, theta=net.theta.cpu().numpy(), chan_w=np.asarray(chan_w, np.float64),
+             threshold=np.float64(threshold), meta=np.array(repr(meta)))
+
+
+def load_model(path, ctx=None, device="cuda"):
+    z = np.load(path, allow_pickle=False)
+    net = Net(ctx=ctx, theta=z["theta"], device=device)
+    return net, [float(x) for x in z["chan_w"]], float(z["threshold"])
+
+
+def _elapsed(fn):
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) * 1e-3
+
+
+def time_to_psnr(ctx, net: Net, threshold, crops_np: np.ndarray, iters=300, device="cuda", max_factor=2):
+    """Per held-out crop: the plain method's PSNR after `iters` iterations is
+    the target; the learned initialization (network inference, fallback
+    decision, Gaussian initialization) then runs the same optimizer until it
+    reaches that PSNR, for at most max_factor * iters iterations.  Returns
+    per-crop records and the means over all crops (a crop that never reaches
+    the target counts with max_factor * iters iterations and their time)."""
+    recs = []
+    for i in range(crops_np.shape[0]):
+        c_np = crops_np[i:i + 1]
+        rg = torch.tensor(c_np, device=device)
+        opt = CropOptimizer(ctx, rg, c_np)
+        # plain: target PSNR and its time
+        t_plain = _elapsed(lambda: (opt.reset(), opt.run(iters)))
+        target = float(opt.final_psnr().item())
+        # learned: inference + decision + init, then iterations until the target
+        pred = torch.empty(1, NET_OUT, rg.shape[2], rg.shape[3], dtype=torch.float32, device=device)
+        use = torch.empty(1, dtype=torch.int32, device=device)
+
+        def start():
+            net.forward(rg, out=pred)
+            u, _ = net.fallback(rg, pred, threshold)
+            use.copy_(u)
+            opt.reset(pred, use)
+
+        start()
+        cap = max_factor * iters
+        hist = opt.run(cap, record_psnr=True).cpu().numpy()[:, 0]
+        fin = float(opt.final_psnr().item())
+        psnr = np.concatenate([hist[:cap], [fin]])  # psnr[k] = PSNR after k updates
+        hit = np.nonzero(psnr >= target)[0]
+        reached = bool(hit.size)
+        k = int(hit[0]) if reached else cap
+        init_psnr = float(hist[0])
+        t_learned = _elapsed(lambda: (start(), opt.run(k)))
+        opt.reset()
+        plain_init_psnr = float(opt.final_psnr().item())
+        recs.append(dict(target_psnr=target, plain_init_psnr=plain_init_psnr, learned_init_psnr=init_psnr,
+                         used_prediction=int(use.item()), reached=reached, iters_learned=k,
+                         seconds_learned=t_learned, iters_plain=iters, seconds_plain=t_plain))
+    summary = dict(objects=len(recs), reached=int(sum(r["reached"] for r in recs)),
+                   reached_within_plain_iters=int(sum(r["reached"] and r["iters_learned"] <= iters for r in recs)),
+                   fallback_rate=float(np.mean([1 - r["used_prediction"] for r in recs])),
+                   mean_iters_learned=float(np.mean([r["iters_learned"] for r in recs])),
+                   median_iters_learned=float(np.median([r["iters_learned"] for r in recs])),
+                   mean_seconds_learned=float(np.mean([r["seconds_learned"] for r in recs])),
+                   mean_seconds_plain=float(np.mean([r["seconds_plain"] for r in recs])),
+                   iters_plain=iters,
+                   mean_target_psnr=float(np.mean([r["target_psnr"] for r in recs])),
+                   mean_plain_init_psnr=float(np.mean([r["plain_init_psnr"] for r in recs])),
+                   mean_learned_init_psnr=float(np.mean([r["learned_init_psnr"] for r in recs])))
+    return recs, summary

@@ -236,3 +236,20 @@ def test_plain_optimizer_on_crops_improves_psnr():
     np.testing.assert_allclose(hist[0], p0, rtol=1e-9)
     assert (p1 > p0 + 1.0).all(), (p0, p1)
     opt.tr.check()
+
+
+def test_trained_network_reaches_plain_psnr_in_fewer_iterations():
+    """The committed network (trained by bench.py --workload learned-init on
+    5,000 crops) against the plain initialization on held-out objects: the
+    learned start reaches the PSNR that the plain start has after 300
+    iterations in fewer iterations."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2503_02223_amd", "data",
+                        "learned_init.npz")
+    ctx = B.Context()
+    net, _, thr = L.load_model(path, ctx=ctx)
+    crops = L.make_crop_set(3, 8)  # the held-out seed of the benchmark
+    recs, summary = L.time_to_psnr(ctx, net, thr, crops, iters=300)
+    assert summary["median_iters_learned"] < 300, recs
+    assert summary["mean_iters_learned"] < 300, recs
+    assert summary["mean_seconds_learned"] < summary["mean_seconds_plain"], summary
