@@ -84,6 +84,14 @@ __device__ __forceinline__ void store_splat_lds<float>(float* dst, const float (
     for (int q = 0; q < 3; ++q) d4[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
 }
 
+// Records whose contribution tests are evaluated together (FP32; FP64 keeps 4
+// to bound register use).
+#ifndef DQO_FWD_GROUP
+#define DQO_FWD_GROUP 8
+#endif
+template <typename T>
+constexpr int fwd_group() { return (sizeof(T) == 8 && DQO_FWD_GROUP > 4) ? 4 : DQO_FWD_GROUP; }
+
 template <typename T, int TW, int TH, bool PROBS>
 __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const uint32_t* __restrict__ pvals,
@@ -130,33 +138,53 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
         if (b0 + 2 * BLOCK + tid < re) rec2 = min(pvals[b0 + 2 * BLOCK + tid], M - 1);
         const int nb = (int)min((uint32_t)BLOCK, re - b0);
         if (!wave_any(!done)) continue;
-        for (int j = 0; j < nb; ++j) {
-            const T* sp = s_sp + j * kSplatWords;
-            T dx, dy;
-            const T Q = quad_form(sp, sx, sy, dx, dy);
-            const bool in = (Q <= cs.q_max) && !done;
-            if (!wave_any(in)) continue;
-            const T a0 = min(sp[5] * fast_exp<T>(T(-0.5) * Q), cs.alpha_max);
-            const bool contrib = in && (a0 >= cs.alpha_min);
-            const T a = contrib ? a0 : T(0);
-            const T Tn = Tt * (T(1) - a);
-            const bool stop = contrib && (Tn < cs.t_min);
-            const T w = stop ? T(0) : a * Tt;
-            if (wave_any(w != T(0))) {
-                c0 = fmadd(w, sp[8], c0);
-                c1 = fmadd(w, sp[9], c1);
-                c2 = fmadd(w, sp[10], c2);
-                dd = fmadd(w, sp[6], dd);
-                const int id = word_to_id<T>(sp[7]);
+        // Groups of fwd_group<T>() records: their contribution tests (quadratic
+        // form, exponential, thresholds) are independent and evaluated side
+        // by side, which hides the VALU and LDS latency that one wavefront
+        // per SIMD would otherwise expose; only the transmittance recurrence
+        // then runs serially, in depth order, with the same arithmetic as a
+        // one-by-one walk.
+        constexpr int kFwdGroup = fwd_group<T>();
+        for (int j0 = 0; j0 < nb; j0 += kFwdGroup) {
+            T rec[kFwdGroup][kSplatWords];
+            T a0[kFwdGroup];
+            bool c0k[kFwdGroup];
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < kFwdGroup; ++k) {
+                const int j = min(j0 + k, nb - 1);
+                load_splat<T>(rec[k], s_sp + j * kSplatWords);
+            }
+#pragma unroll
+            for (int k = 0; k < kFwdGroup; ++k) {
+                T dx, dy;
+                const T Q = quad_form(rec[k], sx, sy, dx, dy);
+                a0[k] = min(rec[k][5] * fast_exp<T>(T(-0.5) * Q), cs.alpha_max);
+                c0k[k] = (j0 + k < nb) && (Q <= cs.q_max) && (a0[k] >= cs.alpha_min);
+                any = any || c0k[k];
+            }
+            if (!wave_any(any && !done)) continue;
+#pragma unroll
+            for (int k = 0; k < kFwdGroup; ++k) {
+                const bool contrib = c0k[k] && !done;
+                const T a = contrib ? a0[k] : T(0);
+                const T Tn = Tt * (T(1) - a);
+                const bool stop = contrib && (Tn < cs.t_min);
+                const T w = stop ? T(0) : a * Tt;
+                c0 = fmadd(w, rec[k][8], c0);
+                c1 = fmadd(w, rec[k][9], c1);
+                c2 = fmadd(w, rec[k][10], c2);
+                dd = fmadd(w, rec[k][6], dd);
+                const int id = word_to_id<T>(rec[k][7]);
                 pt += (id == tgt) ? w : T(0);
                 if (w != T(0)) {
-                    lastpos = (int)(b0 + j);
+                    lastpos = (int)(b0 + j0 + k);
                     ++nb_count;
                     if (PROBS && id >= 0 && id < K) s_P[id * BLOCK + tid] += w;
                 }
                 Tt = stop ? Tt : Tn;
+                done = done || stop;
             }
-            if (stop) done = true;
             if (!wave_any(!done)) break;
         }
     }
