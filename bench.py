@@ -30,7 +30,7 @@ FLOP_PER_BLENDED = 46.0    # gradient of one blended (pixel, Gaussian) incl. its
 # HBM bytes per launch of the render backward from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (scaled by a 256 MiB copy: x2.000 and x1.000), valid only for the kernel source
 # they were taken with (see profiles/); reported as null otherwise.
-MEASURED_TRAFFIC = {"render_src_sha256_16": "9810c6e35d9130d2", "bytes_per_launch": 182090729}
+MEASURED_TRAFFIC = {"render_src_sha256_16": "0ca37abb87a4c9f7", "bytes_per_launch": 182117717}
 
 
 def measured_traffic():
