@@ -31,7 +31,7 @@ struct Geo {
     int depth_blocks, scan_blocks, pair_blocks, pair_passes, pair_first_buf;
     int64_t lb_words;
     // scratch sub-offsets (relative to DQO_BUF_SCRATCH)
-    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_g2d, off_sched, off_lbd, off_lbs, off_lbp;
+    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_lbd, off_lbs, off_lbp;
 };
 
 int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams) {
@@ -83,9 +83,9 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.items = (int64_t)d->n * d->n_views;
     const int64_t M = g.items, cap = d->pair_capacity;
     const int64_t ts = d->dtype == DQO_F64 ? 8 : 4;
-    g.depth_blocks = (int)((M + kSortTile - 1) / kSortTile);
+    g.depth_blocks = (int)((M + kDepthTile - 1) / kDepthTile);
     g.scan_blocks = (int)((M + kScanTile - 1) / kScanTile);
-    g.pair_blocks = (int)((cap + kSortTile - 1) / kSortTile);
+    g.pair_blocks = (int)((cap + kPairTile - 1) / kPairTile);
     int64_t sz[DQO_BUF_COUNT];
     sz[DQO_BUF_SPLATS] = M * kSplatWords * ts;
     sz[DQO_BUF_RECTS] = M * 8;
@@ -103,7 +103,6 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.off_dv1 = so; so = align256(so + M * 4);
     g.off_pk1 = so; so = align256(so + cap * 4);
     g.off_pv1 = so; so = align256(so + cap * 4);
-    g.off_g2d = so; so = align256(so + M * kGradWords * ts);
     g.off_sched = so; so = align256(so + tiles_total * 4);
     g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * g.depth_blocks * kRadixBins * 8);
     g.off_lbs = so; so = align256(so + (int64_t)g.scan_blocks * 8);
@@ -138,7 +137,6 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.pair_vals[1] = (uint32_t*)(sc + g.off_pv1);
     s.ranges = (uint32_t*)(b + g.L.offset[DQO_BUF_RANGES]);
     s.partials = b + g.L.offset[DQO_BUF_PARTIALS];
-    s.g2d = sc + g.off_g2d;
     s.schedule = (uint32_t*)(sc + g.off_sched);
     s.ctrl = (Ctrl*)(b + g.L.offset[DQO_BUF_CONTROL]);
     s.lb_depth = (uint64_t*)(sc + g.off_lbd);

@@ -16,8 +16,20 @@ constexpr int kGradWords = 10;    // dmx,dmy,dA,dB,dC,do,dr,dg,db,dz
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
-constexpr int kSortIpt = 16;                            // items per thread in a radix pass
-constexpr int kSortTile = kSortThreads * kSortIpt;      // 4096 items per block
+// Items per thread of a radix pass: the depth passes (n items) use short
+// blocks so that many run at once and each block's serial ranking is short;
+// the pair passes (millions of pairs) use long blocks so that the look-back
+// chain stays short.
+#ifndef DQO_DEPTH_IPT
+#define DQO_DEPTH_IPT 4
+#endif
+#ifndef DQO_PAIR_IPT
+#define DQO_PAIR_IPT 16
+#endif
+constexpr int kDepthIpt = DQO_DEPTH_IPT;
+constexpr int kPairIpt = DQO_PAIR_IPT;
+constexpr int kDepthTile = kSortThreads * kDepthIpt;
+constexpr int kPairTile = kSortThreads * kPairIpt;
 constexpr int kScanThreads = 256;
 constexpr int kScanIpt = 4;
 constexpr int kScanTile = kScanThreads * kScanIpt;      // 1024 items per block
@@ -90,6 +102,9 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
 // Exclusive prefix of `slot` over the chain 0..slot-1 (decoupled look-back).
 // Publishes the aggregate first, then the inclusive value.  Every wait is
 // bounded: on timeout the status bit is set and the partial sum is used.
+#ifndef DQO_LB_WINDOW
+#define DQO_LB_WINDOW 32
+#endif
 __device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* words, int stride, int slot, uint32_t agg,
                                                        uint32_t epoch, uint32_t* status) {
     if (slot == 0) {
@@ -101,8 +116,10 @@ __device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* words, int stri
     int j = slot - 1;
     uint32_t spins = 0;
     // Look back over a window of predecessors per round trip: the loads are
-    // independent, so the walk costs one memory latency per kLbWindow blocks.
-    constexpr int kLbWindow = 8;
+    // independent, so the walk costs one memory latency per kLbWindow blocks
+    // (when every block starts at once, the inclusive prefix advances by one
+    // window per round trip).
+    constexpr int kLbWindow = DQO_LB_WINDOW;
     while (j >= 0) {
         uint64_t w[kLbWindow];
 #pragma unroll
@@ -196,7 +213,6 @@ struct StatePtrs {
     uint32_t* ranges;
     uint32_t* schedule;   // [V*tiles] launch order of the render workgroups
     void* partials;
-    void* g2d;            // [V*n][10] per-item sums of the pair partials
     Ctrl* ctrl;
     uint64_t* lb_depth;   // [kMaxDepthPasses][blocks][256]
     uint64_t* lb_scan;    // [blocks]

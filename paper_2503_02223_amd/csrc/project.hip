@@ -273,7 +273,7 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
                                          s.depth_vals[src ^ 1], nullptr, (uint32_t)M, p * kRadixBits,
                                          s.ctrl->hist_depth[p],
                                          s.lb_depth + (size_t)p * s.depth_blocks * kRadixBins,
-                                         &s.ctrl->counters[kCounterDepth + p], s.ctrl, st);
+                                         &s.ctrl->counters[kCounterDepth + p], s.ctrl, st, kDepthIpt);
         if (e != hipSuccess) return e;
         src ^= 1;
     }
@@ -286,59 +286,6 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
 }
 
 // ---------------------------------------------------------------- backward
-// Per (view, Gaussian) item, in depth order so that neighbouring threads read
-// neighbouring pair slots: sum the item's per-tile partials in slot order into
-// g2d[item] (zero for items without pairs).
-template <typename T>
-__global__ __launch_bounds__(256) void pair_sum_kernel(const uint32_t* __restrict__ order,
-                                                       const uint32_t* __restrict__ counts,
-                                                       const uint32_t* __restrict__ offsets,
-                                                       const T* __restrict__ partials, T* __restrict__ g2d,
-                                                       uint32_t cap, uint32_t M) {
-    // The 256 items of a block own one contiguous run of slots (offsets are an
-    // exclusive scan in depth order); the run is staged through LDS in chunks
-    // with coalesced loads and every thread sums its own slots from LDS.
-    constexpr int kChunkSlots = 512;
-    __shared__ T s_p[kChunkSlots * kGradWords];
-    __shared__ uint32_t s_lo, s_hi;
-    const int tid = threadIdx.x;
-    const uint32_t r = blockIdx.x * 256 + tid;
-    const bool valid = r < M;
-    const uint32_t item = valid ? min(order[r], M - 1) : 0u;
-    uint32_t cnt = valid ? counts[item] : 0u;
-    const uint32_t off = valid ? offsets[item] : 0u;
-    if ((uint64_t)off + cnt > cap) cnt = 0;
-    if (tid == 0) {
-        s_lo = 0xffffffffu;
-        s_hi = 0u;
-    }
-    __syncthreads();
-    if (cnt) {
-        atomicMin(&s_lo, off);
-        atomicMax(&s_hi, off + cnt);
-    }
-    __syncthreads();
-    const uint32_t lo = s_lo, hi = s_hi;
-    T d[kGradWords];
-#pragma unroll
-    for (int k = 0; k < kGradWords; ++k) d[k] = T(0);
-    for (uint32_t c0 = lo; c0 < hi; c0 += kChunkSlots) {
-        const uint32_t nsl = min((uint32_t)kChunkSlots, hi - c0);
-        __syncthreads();
-        for (uint32_t k = tid; k < nsl * kGradWords; k += 256) s_p[k] = partials[(size_t)c0 * kGradWords + k];
-        __syncthreads();
-        const uint32_t j0 = max(off, c0), j1 = min(off + cnt, c0 + nsl);
-        for (uint32_t j = j0; j < j1; ++j) {
-#pragma unroll
-            for (int k = 0; k < kGradWords; ++k) d[k] += s_p[(j - c0) * kGradWords + k];
-        }
-    }
-    if (valid) {
-#pragma unroll
-        for (int k = 0; k < kGradWords; ++k) g2d[(size_t)item * kGradWords + k] = d[k];
-    }
-}
-
 // Zeroes the partials of the pairs of this frame (the render backward writes
 // only the pairs that contribute somewhere in their tile).
 template <typename T>
@@ -368,12 +315,65 @@ hipError_t launch_zero_partials(const StatePtrs& s, hipStream_t st) {
 template hipError_t launch_zero_partials<float>(const StatePtrs&, hipStream_t);
 template hipError_t launch_zero_partials<double>(const StatePtrs&, hipStream_t);
 
+// Sum of an item's cnt consecutive slots of kGradWords values, added in slot
+// order.  The loads of kSlotBatch slots are issued before any of them is added,
+// so a Gaussian spanning many tiles costs one memory latency per batch instead
+// of one per slot (such Gaussians set the kernel's duration).
+constexpr int kSlotBatch = 8;
+
+template <typename T>
+__device__ __forceinline__ void sum_slots(const T* __restrict__ src, uint32_t cnt, T (&d)[kGradWords]) {
+#pragma unroll
+    for (int k = 0; k < kGradWords; ++k) d[k] = T(0);
+    for (uint32_t j0 = 0; j0 < cnt; j0 += kSlotBatch) {
+        T v[kSlotBatch][kGradWords];
+#pragma unroll
+        for (int b = 0; b < kSlotBatch; ++b) {
+            const uint32_t j = min(j0 + (uint32_t)b, cnt - 1u);
+#pragma unroll
+            for (int k = 0; k < kGradWords; ++k) v[b][k] = src[(size_t)j * kGradWords + k];
+        }
+#pragma unroll
+        for (int b = 0; b < kSlotBatch; ++b)
+            if (j0 + (uint32_t)b < cnt) {
+#pragma unroll
+                for (int k = 0; k < kGradWords; ++k) d[k] += v[b][k];
+            }
+    }
+}
+template <>
+__device__ __forceinline__ void sum_slots<float>(const float* __restrict__ src, uint32_t cnt,
+                                                 float (&d)[kGradWords]) {
+    static_assert(kGradWords % 2 == 0, "slots are read as float2");
+#pragma unroll
+    for (int k = 0; k < kGradWords; ++k) d[k] = 0.0f;
+    const float2* s2 = reinterpret_cast<const float2*>(src);  // slots are 40 B: 8-byte aligned
+    for (uint32_t j0 = 0; j0 < cnt; j0 += kSlotBatch) {
+        float2 v[kSlotBatch][kGradWords / 2];
+#pragma unroll
+        for (int b = 0; b < kSlotBatch; ++b) {
+            const uint32_t j = min(j0 + (uint32_t)b, cnt - 1u);
+#pragma unroll
+            for (int k = 0; k < kGradWords / 2; ++k) v[b][k] = s2[(size_t)j * (kGradWords / 2) + k];
+        }
+#pragma unroll
+        for (int b = 0; b < kSlotBatch; ++b)
+            if (j0 + (uint32_t)b < cnt) {
+#pragma unroll
+                for (int k = 0; k < kGradWords / 2; ++k) {
+                    d[2 * k] += v[b][k].x;
+                    d[2 * k + 1] += v[b][k].y;
+                }
+            }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Consts<T> cs, int64_t n,
                                                                const T* __restrict__ params,
                                                                const uint32_t* __restrict__ counts,
                                                                const uint32_t* __restrict__ offsets,
-                                                               const T* __restrict__ g2d, uint32_t cap,
+                                                               const T* __restrict__ partials, uint32_t cap,
                                                                T* __restrict__ grads) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= n) return;
@@ -390,9 +390,10 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
         if (cnt == 0) continue;
         const uint32_t off = offsets[item];
         if ((uint64_t)off + cnt > cap) continue;
-        T d[kGradWords];  // summed over the item's tiles by pair_sum_kernel
-#pragma unroll
-        for (int k = 0; k < kGradWords; ++k) d[k] = g2d[(size_t)item * kGradWords + k];
+        // The item's per-tile partials occupy cnt consecutive slots; they are
+        // summed in slot order (a fixed order: the result is deterministic).
+        T d[kGradWords];
+        sum_slots<T>(partials + (size_t)off * kGradWords, cnt, d);
         const DevCam<T>& c = V.cam[v];
         Proj<T> pr;
         project_item(c, cs, p, pr);
@@ -501,11 +502,8 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
 template <typename T>
 hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads, hipStream_t st) {
     if (f.n == 0) return hipSuccess;
-    const uint32_t M = (uint32_t)f.s.items;
-    hipLaunchKernelGGL(pair_sum_kernel<T>, dim3((M + 255) / 256), dim3(256), 0, st, f.s.depth_vals[0], f.s.counts,
-                       f.s.offsets, (const T*)f.s.partials, (T*)f.s.g2d, (uint32_t)f.s.capacity, M);
     hipLaunchKernelGGL(project_backward_kernel<T>, dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st, f.views,
-                       f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.g2d,
+                       f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.partials,
                        (uint32_t)f.s.capacity, grads);
     return hipGetLastError();
 }

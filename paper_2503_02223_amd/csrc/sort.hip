@@ -1,6 +1,6 @@
 // Stable LSD radix sort passes (8-bit digits, one kernel per pass) and tile ranges.
 //
-// A pass reads 2048 (key, value) items per block, ranks them stably inside the
+// A pass reads 256 x IPT (key, value) items per block, ranks them stably inside the
 // block with wave-wide match ballots, obtains the block's global offset per
 // digit by decoupled look-back over the preceding blocks (block order is taken
 // from an atomic ticket, so every block it waits on is already running), then
@@ -12,12 +12,14 @@
 
 namespace dqo {
 
+template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
     const uint32_t* __restrict__ ghist, uint64_t* lb, uint32_t* counter, Ctrl* ctrl) {
-    __shared__ uint32_t s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
+    constexpr int kTile = kSortThreads * IPT;
+    __shared__ uint32_t s_keys[kTile];
+    __shared__ uint32_t s_vals[kTile];
     __shared__ uint32_t s_wcnt[kSortThreads / kWave][kRadixBins];
     __shared__ uint32_t s_dstart[kRadixBins];
     __shared__ uint32_t s_gbase[kRadixBins];
@@ -34,15 +36,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     const uint32_t bid = s_bid;
     uint32_t n = n_host;
     if (n_dev) n = min(*n_dev, n_host);
-    const uint32_t base = bid * (uint32_t)kSortTile;
+    const uint32_t base = bid * (uint32_t)kTile;
     if (base >= n) return;  // uniform over the block; no later block waits on this one
     const uint32_t epoch = ctrl->epoch;
 
-    uint32_t key[kSortIpt], val[kSortIpt], rank[kSortIpt];
+    uint32_t key[IPT], val[IPT], rank[IPT];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int i = 0; i < kSortIpt; ++i) {
-        const uint32_t pos = base + wave * (kWave * kSortIpt) + i * kWave + lane;
+    for (int i = 0; i < IPT; ++i) {
+        const uint32_t pos = base + wave * (kWave * IPT) + i * kWave + lane;
         const bool valid = pos < n;
         key[i] = valid ? kin[pos] : 0u;
         val[i] = valid ? vin[pos] : 0u;
@@ -80,19 +82,19 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     __syncthreads();
 
 #pragma unroll
-    for (int i = 0; i < kSortIpt; ++i) {
-        const uint32_t pos = base + wave * (kWave * kSortIpt) + i * kWave + lane;
+    for (int i = 0; i < IPT; ++i) {
+        const uint32_t pos = base + wave * (kWave * IPT) + i * kWave + lane;
         if (pos < n) {
             const uint32_t d = (key[i] >> shift) & (kRadixBins - 1);
             const uint32_t p = s_dstart[d] + s_wcnt[wave][d] + rank[i];
-            if (p < (uint32_t)kSortTile) {
+            if (p < (uint32_t)kTile) {
                 s_keys[p] = key[i];
                 s_vals[p] = val[i];
             }
         }
     }
     __syncthreads();
-    const uint32_t cnt = min((uint32_t)kSortTile, n - base);
+    const uint32_t cnt = min((uint32_t)kTile, n - base);
     for (uint32_t q = tid; q < cnt; q += kSortThreads) {
         const uint32_t k = s_keys[q];
         const uint32_t d = (k >> shift) & (kRadixBins - 1);
@@ -160,11 +162,20 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
 
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
-                             uint64_t* lb, uint32_t* counter, Ctrl* ctrl, hipStream_t st) {
+                             uint64_t* lb, uint32_t* counter, Ctrl* ctrl, hipStream_t st, int ipt) {
     if (n_host == 0) return hipSuccess;
-    const int blocks = (int)((n_host + kSortTile - 1) / kSortTile);
-    hipLaunchKernelGGL(radix_pass_kernel, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev,
-                       n_host, shift, ghist, lb, counter, ctrl);
+    const int blocks = (int)((n_host + kSortThreads * ipt - 1) / (kSortThreads * ipt));
+    if (ipt == 4)
+        hipLaunchKernelGGL(radix_pass_kernel<4>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
+                           n_dev, n_host, shift, ghist, lb, counter, ctrl);
+    else if (ipt == 8)
+        hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
+                           n_dev, n_host, shift, ghist, lb, counter, ctrl);
+    else if (ipt == 16)
+        hipLaunchKernelGGL(radix_pass_kernel<16>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
+                           n_dev, n_host, shift, ghist, lb, counter, ctrl);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -176,7 +187,7 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         hipError_t e = launch_radix_pass(s.pair_keys[src], s.pair_vals[src], s.pair_keys[src ^ 1],
                                          s.pair_vals[src ^ 1], n_dev, cap, p * kRadixBits,
                                          s.ctrl->hist_pair[p], s.lb_pair + (size_t)p * s.pair_blocks * kRadixBins,
-                                         &s.ctrl->counters[kCounterPair + p], s.ctrl, st);
+                                         &s.ctrl->counters[kCounterPair + p], s.ctrl, st, kPairIpt);
         if (e != hipSuccess) return e;
         src ^= 1;
     }
