@@ -278,6 +278,45 @@ int dqo_adam_step(const dqo_ctx* ctx, int32_t dtype, void* params, const void* g
 int dqo_adam_step_counted(const dqo_ctx* ctx, int32_t dtype, void* params, const void* grads, void* m, void* v,
                           int64_t n, const dqo_adam* hp /* host */, int64_t* d_step, void* stream);
 
+/* ---- incremental update ---------------------------------------------------- */
+
+/* Thresholds of Eq. (7) and the opacities of the Gaussians added where they
+ * fire (opaque OG for geometry, transparent TG for colour; Sec. IV).
+ * Defaults: theta_alpha 0.5 (unstated in the paper), theta_d = theta_c = 0.1
+ * (stated), OG 0.9, TG 0.1. */
+typedef struct dqo_increment_cfg {
+    double theta_alpha; /* ins below it: the object's geometry is missing */
+    double theta_d;     /* |rendered depth - observed depth| above it: incomplete */
+    double theta_c;     /* mean |rendered colour - observed colour| over r, g, b above it */
+    double og_opacity, tg_opacity;
+} dqo_increment_cfg;
+
+/* Unstable-pixel masks of Eq. (7), per object as in Eq. (8), from the images
+ * of a loss-mode forward (img->color, depth and p_target, rendered with
+ * img->target = tgt->id, so that p_target = ins of the observed object) and
+ * the observed frame tgt (colour, depth, id).  masks[V][H][W] uint8 (device,
+ * written): bit 0 Mask_geo (ins < theta_alpha, or observed depth > 0 and
+ * |D - observed| > theta_d), bit 1 Mask_rgb (mean colour error > theta_c);
+ * pixels observed as no object (id -1) or with id >= K are 0.  obj_counts
+ * (device int32 [K][2], overwritten): per object, its Mask_geo and Mask_rgb
+ * pixel counts.  All floating-point buffers are of the frame's dtype. */
+int dqo_incremental_masks(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams,
+                          const dqo_images* img, const dqo_targets* tgt, const dqo_increment_cfg* cfg /* host */,
+                          uint8_t* masks, int32_t* obj_counts, void* stream);
+
+/* Gaussians added at the unstable pixels with observed depth d > 0: an OG
+ * Gaussian at Mask_geo pixels, else a TG Gaussian at Mask_rgb pixels, in view
+ * order then raster order; the mean is the pixel centre (u + 1/2, v + 1/2)
+ * back-projected at depth d through view v's camera, log-scales log(d / fx),
+ * identity quaternion, opacity logit of og/tg_opacity, the observed colour,
+ * id = the observed id.  They are written to columns [n_old, n_cap) of
+ * params[14][n_cap] (frame dtype) and ids[n_cap]; counts (device int64
+ * [V + 1], written): [0] the number to add (columns beyond n_cap are not
+ * written: compare with n_cap - n_old), [1 + v] per view. */
+int dqo_densify(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const dqo_targets* tgt,
+                const uint8_t* masks, const dqo_increment_cfg* cfg /* host */, int64_t n_old, int64_t n_cap,
+                void* params, int32_t* ids, int64_t* counts, void* stream);
+
 /* ---- quadric -------------------------------------------------------------- */
 
 /* 2D boxes of every object in rendered id maps (the observed boxes from which

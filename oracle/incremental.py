@@ -1,5 +1,6 @@
-"""Oracle of the incremental update (test infrastructure only; numpy, FP64
-except where a decision is taken on FP32 images, which it takes in FP32).
+"""Oracle of the incremental update (test infrastructure only; numpy, FP64:
+images given in FP32 are widened first, and the returned margin tells a test
+which pixels sit too close to a threshold for the two precisions to agree).
 
 Sec. III-C, Eq. (7)-(8): after a frame is rendered, the pixels of object k
 whose geometry is missing or unstable form Mask_geo (the rendered instance

@@ -30,7 +30,7 @@ EXPORTED = ["dqo_config_default", "dqo_ctx_create", "dqo_ctx_destroy", "dqo_last
             "dqo_version", "dqo_state_layout", "dqo_state_init", "dqo_read_status", "dqo_clear_status",
             "dqo_project_cull_bin", "dqo_sort", "dqo_render_forward", "dqo_object_loss", "dqo_render_backward",
             "dqo_project_backward", "dqo_adam_step", "dqo_adam_step_counted", "dqo_fit_dual_quadric",
-            "dqo_id_boxes"]
+            "dqo_id_boxes", "dqo_incremental_masks", "dqo_densify"]
 # include/dqo_learned.h
 EXPORTED_LEARNED = ["dqo_net_layout_get", "dqo_net_workspace_size", "dqo_net_pack", "dqo_net_forward", "dqo_net_loss",
                     "dqo_net_backward", "dqo_adam_flat", "dqo_init_gaussians", "dqo_init_labels", "dqo_net_fallback",
@@ -89,6 +89,15 @@ class LossWeights(ctypes.Structure):
                 ("ce_eps", ctypes.c_double)]
 
 
+class IncrementCfg(ctypes.Structure):
+    _fields_ = [("theta_alpha", ctypes.c_double), ("theta_d", ctypes.c_double), ("theta_c", ctypes.c_double),
+                ("og_opacity", ctypes.c_double), ("tg_opacity", ctypes.c_double)]
+
+
+# thresholds of Eq. (7) (theta_alpha is not stated in the paper) and the OG / TG opacities
+INCREMENT_DEFAULTS = dict(theta_alpha=0.5, theta_d=0.1, theta_c=0.1, og_opacity=0.9, tg_opacity=0.1)
+
+
 class AdamParams(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_double * NUM_PARAMS), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
                 ("eps", ctypes.c_double)]
@@ -135,6 +144,8 @@ def lib():
     L.dqo_render_backward.argtypes = fr + [vp, P(Images), P(ImageGrads), vp]
     L.dqo_project_backward.argtypes = fr + [vp, vp, vp, vp]
     L.dqo_adam_step.argtypes = [ctx, i32, vp, vp, vp, vp, i64, P(AdamParams), i64, vp]
+    L.dqo_incremental_masks.argtypes = fr + [P(Images), P(Targets), P(IncrementCfg), vp, vp, vp]
+    L.dqo_densify.argtypes = fr + [P(Targets), vp, P(IncrementCfg), i64, i64, vp, vp, vp, vp]
     L.dqo_adam_step_counted.argtypes = [ctx, i32, vp, vp, vp, vp, i64, P(AdamParams), vp, vp]
     L.dqo_fit_dual_quadric.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp]
     L.dqo_id_boxes.argtypes = [ctx, vp, i32, i32, i32, i32, vp, vp, vp, vp]
@@ -323,6 +334,30 @@ class Frame:
     def project_backward(self, params: torch.Tensor, grads: torch.Tensor, stream=None):
         self.ctx.check(lib().dqo_project_backward(*self._fr(), _ptr(params), _ptr(self.state), _ptr(grads),
                                                   _stream(stream)))
+
+    # -- incremental update (Eq. (7)-(8)) --
+    def incremental_masks(self, img, tgt: Dict[str, torch.Tensor], masks: torch.Tensor, obj_counts: torch.Tensor,
+                          stream=None, **cfg):
+        """img: a loss-mode forward's images (p_target rendered with target = tgt["id"])."""
+        assert masks.dtype == torch.uint8 and masks.shape == (self.V, self.H, self.W)
+        assert obj_counts.dtype == torch.int32 and obj_counts.numel() >= 2 * self.K
+        s = Frame._images(img)
+        t = Targets(_ptr(tgt["color"]), _ptr(tgt["depth"]), _ptr(tgt["id"]))
+        c = IncrementCfg(**{**INCREMENT_DEFAULTS, **cfg})
+        self.ctx.check(lib().dqo_incremental_masks(*self._fr(), ctypes.byref(s), ctypes.byref(t), ctypes.byref(c),
+                                                   _ptr(masks), _ptr(obj_counts), _stream(stream)))
+
+    def densify(self, tgt: Dict[str, torch.Tensor], masks: torch.Tensor, params: torch.Tensor, ids: torch.Tensor,
+                n_old: int, counts: torch.Tensor, stream=None, **cfg):
+        """Writes the new Gaussians into columns [n_old, params.shape[1]) of params / ids; counts int64[V + 1]."""
+        assert masks.dtype == torch.uint8 and masks.shape == (self.V, self.H, self.W)
+        assert params.dtype == self.tdtype and params.shape[0] == NUM_PARAMS and ids.shape == (params.shape[1],)
+        assert counts.dtype == torch.int64 and counts.numel() >= self.V + 1
+        t = Targets(_ptr(tgt["color"]), _ptr(tgt["depth"]), _ptr(tgt["id"]))
+        c = IncrementCfg(**{**INCREMENT_DEFAULTS, **cfg})
+        self.ctx.check(lib().dqo_densify(*self._fr(), ctypes.byref(t), _ptr(masks), ctypes.byref(c), int(n_old),
+                                         int(params.shape[1]), _ptr(params), _ptr(ids), _ptr(counts),
+                                         _stream(stream)))
 
 
 def adam_step(ctx: Context, params, grads, m, v, lrs, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):

@@ -187,8 +187,17 @@ Frame<T> make_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camer
     for (int k = 0; k < 3; ++k) f.consts.bg[k] = (T)c.bg[k];
     f.n = d->n;
     f.K = d->K;
-    f.s = state_ptrs(g, state);
+    if (state) f.s = state_ptrs(g, state);  // the image-space passes need only the views
     return f;
+}
+
+int check_increment_cfg(const dqo_ctx* ctx, const dqo_increment_cfg* c) {
+    if (!c) return fail(ctx, DQO_EINVAL, "increment config must not be NULL");
+    if (!(c->theta_alpha >= 0 && c->theta_alpha <= 1)) return fail(ctx, DQO_EINVAL, "theta_alpha outside [0, 1]");
+    if (!(c->theta_d >= 0) || !(c->theta_c >= 0)) return fail(ctx, DQO_EINVAL, "theta_d and theta_c must be >= 0");
+    if (!(c->og_opacity > 0 && c->og_opacity < 1) || !(c->tg_opacity > 0 && c->tg_opacity < 1))
+        return fail(ctx, DQO_EINVAL, "OG and TG opacities must lie in (0, 1)");
+    return DQO_OK;
 }
 
 int check_images(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_images* img, bool need_probs_ok) {
@@ -437,6 +446,59 @@ int dqo_project_backward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_
     Frame<double> f = make_frame<double>(ctx, d, cams, g, (void*)state);
     return run(ctx, "project_backward", [&] {
         return launch_project_backward<double>(f, (const double*)params, (double*)grads, (hipStream_t)stream);
+    });
+}
+
+int dqo_incremental_masks(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams,
+                          const dqo_images* img, const dqo_targets* tgt, const dqo_increment_cfg* cfg,
+                          uint8_t* masks, int32_t* obj_counts, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if ((rc = check_increment_cfg(ctx, cfg))) return rc;
+    if (d->K < 1) return fail(ctx, DQO_EINVAL, "incremental masks need K >= 1");
+    if (!img || !img->color || !img->depth || !img->p_target)
+        return fail(ctx, DQO_EINVAL, "incremental masks need rendered color, depth and p_target");
+    if (!tgt || !tgt->color || !tgt->depth || !tgt->id)
+        return fail(ctx, DQO_EINVAL, "incremental masks need target color, depth and id");
+    if (!masks || !obj_counts) return fail(ctx, DQO_EINVAL, "masks and obj_counts must not be NULL");
+    Geo g = geometry(ctx, d, cams);
+    if (d->dtype == DQO_F32) {
+        Frame<float> f = make_frame<float>(ctx, d, cams, g, nullptr);
+        return run(ctx, "incremental_masks", [&] {
+            return launch_incremental_masks<float>(f, *img, *tgt, *cfg, masks, obj_counts, (hipStream_t)stream);
+        });
+    }
+    Frame<double> f = make_frame<double>(ctx, d, cams, g, nullptr);
+    return run(ctx, "incremental_masks", [&] {
+        return launch_incremental_masks<double>(f, *img, *tgt, *cfg, masks, obj_counts, (hipStream_t)stream);
+    });
+}
+
+int dqo_densify(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const dqo_targets* tgt,
+                const uint8_t* masks, const dqo_increment_cfg* cfg, int64_t n_old, int64_t n_cap, void* params,
+                int32_t* ids, int64_t* counts, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if ((rc = check_increment_cfg(ctx, cfg))) return rc;
+    if (!tgt || !tgt->color || !tgt->depth || !tgt->id)
+        return fail(ctx, DQO_EINVAL, "densify needs target color, depth and id");
+    if (!masks || !counts) return fail(ctx, DQO_EINVAL, "masks and counts must not be NULL");
+    if (n_old < 0 || n_cap < n_old || n_cap > (int64_t(1) << 31) - 1)
+        return fail(ctx, DQO_EINVAL, "need 0 <= n_old <= n_cap < 2^31 (n_old %lld, n_cap %lld)", (long long)n_old,
+                    (long long)n_cap);
+    if (n_cap > n_old && (!params || !ids)) return fail(ctx, DQO_EINVAL, "params and ids must not be NULL");
+    Geo g = geometry(ctx, d, cams);
+    if (d->dtype == DQO_F32) {
+        Frame<float> f = make_frame<float>(ctx, d, cams, g, nullptr);
+        return run(ctx, "densify", [&] {
+            return launch_densify<float>(f, *tgt, masks, *cfg, n_old, n_cap, (float*)params, ids, counts,
+                                         (hipStream_t)stream);
+        });
+    }
+    Frame<double> f = make_frame<double>(ctx, d, cams, g, nullptr);
+    return run(ctx, "densify", [&] {
+        return launch_densify<double>(f, *tgt, masks, *cfg, n_old, n_cap, (double*)params, ids, counts,
+                                      (hipStream_t)stream);
     });
 }
 

@@ -262,5 +262,12 @@ hipError_t launch_clear_status(Ctrl* ctrl, hipStream_t st);
 hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_zero_partials(const StatePtrs& s, hipStream_t st);
+template <typename T>
+hipError_t launch_incremental_masks(const Frame<T>& f, const dqo_images& img, const dqo_targets& tgt,
+                                    const dqo_increment_cfg& cfg, uint8_t* masks, int32_t* counts, hipStream_t st);
+template <typename T>
+hipError_t launch_densify(const Frame<T>& f, const dqo_targets& tgt, const uint8_t* masks,
+                          const dqo_increment_cfg& cfg, int64_t n_old, int64_t n_cap, T* params, int32_t* ids,
+                          int64_t* counts, hipStream_t st);
 
 }  // namespace dqo
