@@ -347,6 +347,45 @@ int dqo_fit_dual_quadric(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, con
                          const int32_t* img_wh, double border, double* Q, double* mu, double* R, double* axes,
                          int32_t* status, void* stream);
 
+/* ---- quadric refinement ---------------------------------------------------- */
+
+/* Object pose training by the IoU loss of Eq. (9).  An object's quadric is
+ * theta[10] = (mu[3], q[4] = (w, x, y, z), log-axes[3]): Q* = Z diag(a^2, b^2,
+ * c^2, -1) Z^T with Z = [[R(q / |q|), mu], [0, 1]] (Eq. (2)-(3)).  For each
+ * box of the object (box_obj == k, 0 <= box_view < n_views), the dual conic
+ * C* = P Q* P^T of camera P[box_view] (Eq. (4)) gives the tangent box
+ * (x0, y0, x1, y1), clipped to [0, W] x [0, H] when img_wh is given; the
+ * object's loss is J_k = sum over its boxes of 1 - IoU(predicted, observed).
+ * A box whose conic is not an ellipse in front of the camera counts 1 with no
+ * gradient.  Inputs use the format of dqo_fit_dual_quadric; at most 256 boxes
+ * per object (an object with more gets NaN losses and is left unchanged).
+ * All buffers are device FP64 / int32. */
+typedef struct dqo_refine_cfg {
+    int32_t iterations;               /* Adam steps, >= 0 */
+    double lr_mu, lr_rot, lr_axes;    /* learning rates of mu, q and the log-axes */
+    double beta1, beta2, eps;         /* Adam (PyTorch's update with bias correction) */
+} dqo_refine_cfg;
+
+/* J_k and dJ_k/dtheta_k for every object at the given theta[n_obj][10]:
+ * loss[n_obj], grad[n_obj][10]; box_iou[n_boxes] (optional) receives the IoU
+ * of every box of an object (entries of other boxes are not written). */
+int dqo_quadric_iou_grad(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, const double* boxes,
+                         const int32_t* box_obj, const int32_t* box_view, int32_t n_views, const double* P,
+                         const int32_t* img_wh, const double* theta, double* loss, double* grad, double* box_iou,
+                         void* stream);
+
+/* Refines every object whose status is DQO_QUADRIC_OK (status may be NULL:
+ * all objects) in one launch: theta is formed from mu[n_obj][3], R[n_obj][9]
+ * (row-major rotation) and axes[n_obj][3], `iterations` Adam steps on J_k are
+ * taken, and mu, R = R(q / |q|) and axes = exp(log-axes) are overwritten;
+ * Q[n_obj][16] (optional) receives the refined Q*.  loss[n_obj][2] = (J_k
+ * before, J_k after); NaN for objects that are skipped.  box_iou[n_boxes]
+ * (optional): final IoU of each box of a refined object. */
+int dqo_refine_quadrics(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, const double* boxes,
+                        const int32_t* box_obj, const int32_t* box_view, int32_t n_views, const double* P,
+                        const int32_t* img_wh, const int32_t* status, const dqo_refine_cfg* cfg /* host */,
+                        double* mu, double* R, double* axes, double* Q, double* loss, double* box_iou, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

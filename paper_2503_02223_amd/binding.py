@@ -30,7 +30,8 @@ EXPORTED = ["dqo_config_default", "dqo_ctx_create", "dqo_ctx_destroy", "dqo_last
             "dqo_version", "dqo_state_layout", "dqo_state_init", "dqo_read_status", "dqo_clear_status",
             "dqo_project_cull_bin", "dqo_sort", "dqo_render_forward", "dqo_object_loss", "dqo_render_backward",
             "dqo_project_backward", "dqo_adam_step", "dqo_adam_step_counted", "dqo_fit_dual_quadric",
-            "dqo_id_boxes", "dqo_incremental_masks", "dqo_densify"]
+            "dqo_id_boxes", "dqo_incremental_masks", "dqo_densify", "dqo_quadric_iou_grad",
+            "dqo_refine_quadrics"]
 # include/dqo_learned.h
 EXPORTED_LEARNED = ["dqo_net_layout_get", "dqo_net_workspace_size", "dqo_net_pack", "dqo_net_forward", "dqo_net_loss",
                     "dqo_net_backward", "dqo_adam_flat", "dqo_init_gaussians", "dqo_init_labels", "dqo_net_fallback",
@@ -98,6 +99,16 @@ class IncrementCfg(ctypes.Structure):
 INCREMENT_DEFAULTS = dict(theta_alpha=0.5, theta_d=0.1, theta_c=0.1, og_opacity=0.9, tg_opacity=0.1)
 
 
+class RefineCfg(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("lr_mu", ctypes.c_double), ("lr_rot", ctypes.c_double),
+                ("lr_axes", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
+# Adam on the quadric pose (the paper does not state its optimiser settings)
+REFINE_DEFAULTS = dict(iterations=100, lr_mu=0.01, lr_rot=0.01, lr_axes=0.01, beta1=0.9, beta2=0.999, eps=1e-15)
+
+
 class AdamParams(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_double * NUM_PARAMS), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
                 ("eps", ctypes.c_double)]
@@ -149,6 +160,9 @@ def lib():
     L.dqo_adam_step_counted.argtypes = [ctx, i32, vp, vp, vp, vp, i64, P(AdamParams), vp, vp]
     L.dqo_fit_dual_quadric.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp]
     L.dqo_id_boxes.argtypes = [ctx, vp, i32, i32, i32, i32, vp, vp, vp, vp]
+    L.dqo_quadric_iou_grad.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.dqo_refine_quadrics.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, vp, P(RefineCfg), vp, vp, vp, vp, vp,
+                                      vp, vp]
     L.dqo_net_layout_get.argtypes = [P(NetLayout)]
     L.dqo_net_workspace_size.argtypes = [i32, i32, i32, P(i64)]
     L.dqo_net_pack.argtypes = [ctx, vp, vp, vp, vp]
@@ -419,6 +433,37 @@ def fit_dual_quadric(ctx: Context, boxes, box_obj, box_view, Ps, n_obj, img_wh=N
                                          _ptr(box_view), int(Ps.shape[0]), _ptr(Ps), _ptr(img_wh), float(border),
                                          _ptr(Q), _ptr(mu), _ptr(R), _ptr(axes), _ptr(status), _stream(stream)))
     return dict(Q=Q, mu=mu, R=R, axes=axes, status=status)
+
+
+def quadric_iou_grad(ctx: Context, boxes, box_obj, box_view, Ps, theta, img_wh=None, stream=None):
+    """J_k and dJ_k/dtheta_k of Eq. (9) at theta[n_obj][10] (device tensors)."""
+    n_obj = int(theta.shape[0])
+    dev = theta.device
+    loss = torch.empty(n_obj, dtype=torch.float64, device=dev)
+    grad = torch.empty(n_obj, 10, dtype=torch.float64, device=dev)
+    iou = torch.full((boxes.shape[0],), float("nan"), dtype=torch.float64, device=dev)
+    ctx.check(lib().dqo_quadric_iou_grad(ctx.h, n_obj, int(boxes.shape[0]), _ptr(boxes), _ptr(box_obj),
+                                         _ptr(box_view), int(Ps.shape[0]), _ptr(Ps), _ptr(img_wh), _ptr(theta),
+                                         _ptr(loss), _ptr(grad), _ptr(iou), _stream(stream)))
+    return dict(loss=loss, grad=grad, iou=iou)
+
+
+def refine_quadrics(ctx: Context, boxes, box_obj, box_view, Ps, fit, img_wh=None, stream=None, **cfg):
+    """Refines fit = dict(mu, R, axes[, status]) in place by Adam on the IoU
+    loss; returns fit with Q, loss (n_obj, 2) and the final per-box IoU."""
+    c = RefineCfg(**{**REFINE_DEFAULTS, **cfg})
+    n_obj = int(fit["mu"].shape[0])
+    dev = fit["mu"].device
+    Q = fit.get("Q")
+    if Q is None:
+        Q = torch.empty(n_obj, 4, 4, dtype=torch.float64, device=dev)
+    loss = torch.empty(n_obj, 2, dtype=torch.float64, device=dev)
+    iou = torch.full((boxes.shape[0],), float("nan"), dtype=torch.float64, device=dev)
+    ctx.check(lib().dqo_refine_quadrics(ctx.h, n_obj, int(boxes.shape[0]), _ptr(boxes), _ptr(box_obj),
+                                        _ptr(box_view), int(Ps.shape[0]), _ptr(Ps), _ptr(img_wh),
+                                        _ptr(fit.get("status")), ctypes.byref(c), _ptr(fit["mu"]), _ptr(fit["R"]),
+                                        _ptr(fit["axes"]), _ptr(Q), _ptr(loss), _ptr(iou), _stream(stream)))
+    return dict(fit, Q=Q, loss=loss, iou=iou)
 
 
 # ------------------------------------------------------------------ helpers

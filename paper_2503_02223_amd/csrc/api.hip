@@ -191,6 +191,15 @@ Frame<T> make_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camer
     return f;
 }
 
+int check_quadric_inputs(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, const double* boxes,
+                         const int32_t* box_obj, const int32_t* box_view, int32_t n_views, const double* P) {
+    if (n_obj < 0 || n_boxes < 0 || n_views < 0) return fail(ctx, DQO_EINVAL, "negative size");
+    if (n_obj > 65535) return fail(ctx, DQO_EINVAL, "n_obj too large");
+    if (n_boxes > 0 && (!boxes || !box_obj || !box_view || !P || n_views < 1))
+        return fail(ctx, DQO_EINVAL, "boxes, box_obj, box_view and P are required");
+    return DQO_OK;
+}
+
 int check_increment_cfg(const dqo_ctx* ctx, const dqo_increment_cfg* c) {
     if (!c) return fail(ctx, DQO_EINVAL, "increment config must not be NULL");
     if (!(c->theta_alpha >= 0 && c->theta_alpha <= 1)) return fail(ctx, DQO_EINVAL, "theta_alpha outside [0, 1]");
@@ -565,6 +574,42 @@ int dqo_fit_dual_quadric(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, con
     return run(ctx, "fit_dual_quadric", [&] {
         return launch_fit_quadric(n_obj, n_boxes, boxes, box_obj, box_view, n_views, P, img_wh, border, Q, mu, R,
                                   axes, status, (hipStream_t)stream);
+    });
+}
+
+int dqo_quadric_iou_grad(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, const double* boxes,
+                         const int32_t* box_obj, const int32_t* box_view, int32_t n_views, const double* P,
+                         const int32_t* img_wh, const double* theta, double* loss, double* grad, double* box_iou,
+                         void* stream) {
+    if (!ctx) return DQO_EINVAL;
+    int rc = check_quadric_inputs(ctx, n_obj, n_boxes, boxes, box_obj, box_view, n_views, P);
+    if (rc) return rc;
+    if (n_obj > 0 && (!theta || !loss || !grad)) return fail(ctx, DQO_EINVAL, "theta, loss and grad are required");
+    return run(ctx, "quadric_iou_grad", [&] {
+        return launch_quadric_iou_grad(n_obj, n_views, n_boxes, boxes, box_obj, box_view, P, img_wh, theta, loss,
+                                       grad, box_iou, (hipStream_t)stream);
+    });
+}
+
+int dqo_refine_quadrics(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, const double* boxes,
+                        const int32_t* box_obj, const int32_t* box_view, int32_t n_views, const double* P,
+                        const int32_t* img_wh, const int32_t* status, const dqo_refine_cfg* cfg, double* mu,
+                        double* R, double* axes, double* Q, double* loss, double* box_iou, void* stream) {
+    if (!ctx) return DQO_EINVAL;
+    int rc = check_quadric_inputs(ctx, n_obj, n_boxes, boxes, box_obj, box_view, n_views, P);
+    if (rc) return rc;
+    if (!cfg) return fail(ctx, DQO_EINVAL, "refine config must not be NULL");
+    if (cfg->iterations < 0 || cfg->iterations > 1000000)
+        return fail(ctx, DQO_EINVAL, "iterations = %d outside [0, 1e6]", cfg->iterations);
+    if (!(cfg->lr_mu >= 0) || !(cfg->lr_rot >= 0) || !(cfg->lr_axes >= 0) || !isfinite(cfg->lr_mu) ||
+        !isfinite(cfg->lr_rot) || !isfinite(cfg->lr_axes))
+        return fail(ctx, DQO_EINVAL, "learning rates must be finite and >= 0");
+    if (!(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0))
+        return fail(ctx, DQO_EINVAL, "need 0 <= beta1, beta2 < 1 and eps > 0");
+    if (n_obj > 0 && (!mu || !R || !axes || !loss)) return fail(ctx, DQO_EINVAL, "mu, R, axes and loss are required");
+    return run(ctx, "refine_quadrics", [&] {
+        return launch_refine_quadrics(n_obj, n_views, n_boxes, boxes, box_obj, box_view, P, img_wh, status, *cfg, mu,
+                                      R, axes, Q, loss, box_iou, (hipStream_t)stream);
     });
 }
 

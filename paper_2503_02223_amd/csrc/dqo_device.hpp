@@ -262,6 +262,14 @@ hipError_t launch_clear_status(Ctrl* ctrl, hipStream_t st);
 hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_zero_partials(const StatePtrs& s, hipStream_t st);
+hipError_t launch_quadric_iou_grad(int n_obj, int n_views, int64_t n_boxes, const double* boxes,
+                                   const int32_t* box_obj, const int32_t* box_view, const double* P,
+                                   const int32_t* img_wh, const double* theta, double* loss, double* grad,
+                                   double* box_iou, hipStream_t st);
+hipError_t launch_refine_quadrics(int n_obj, int n_views, int64_t n_boxes, const double* boxes,
+                                  const int32_t* box_obj, const int32_t* box_view, const double* P,
+                                  const int32_t* img_wh, const int32_t* status, const dqo_refine_cfg& c, double* mu,
+                                  double* R, double* axes, double* Q, double* loss, double* box_iou, hipStream_t st);
 template <typename T>
 hipError_t launch_incremental_masks(const Frame<T>& f, const dqo_images& img, const dqo_targets& tgt,
                                     const dqo_increment_cfg& cfg, uint8_t* masks, int32_t* counts, hipStream_t st);
