@@ -102,7 +102,7 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t* p) {
 // Publishes the aggregate first, then the inclusive value.  Every wait is
 // bounded: on timeout the status bit is set and the partial sum is used.
 #ifndef DQO_LB_WINDOW
-#define DQO_LB_WINDOW 32
+#define DQO_LB_WINDOW 8
 #endif
 __device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* words, int stride, int slot, uint32_t agg,
                                                        uint32_t epoch, uint32_t* status) {
@@ -117,7 +117,9 @@ __device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* words, int stri
     // Look back over a window of predecessors per round trip: the loads are
     // independent, so the walk costs one memory latency per kLbWindow blocks
     // (when every block starts at once, the inclusive prefix advances by one
-    // window per round trip).
+    // window per round trip).  A stalled block re-reads its whole window, so
+    // wide windows cost bandwidth: 8 measured fastest of 8, 16, 32 and 64
+    // (49 and 367 blocks of 256 digit chains).
     constexpr int kLbWindow = DQO_LB_WINDOW;
     while (j >= 0) {
         uint64_t w[kLbWindow];

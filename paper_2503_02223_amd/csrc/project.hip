@@ -110,9 +110,12 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
                                                       const T* __restrict__ params, const int32_t* __restrict__ ids,
                                                       T* __restrict__ splats, short4* __restrict__ rects,
                                                       uint32_t* __restrict__ counts, uint32_t* __restrict__ dkeys,
-                                                      uint32_t* __restrict__ dvals, Ctrl* ctrl) {
+                                                      uint32_t* __restrict__ dvals, uint32_t* __restrict__ ranges,
+                                                      int64_t range_words, Ctrl* ctrl) {
     __shared__ uint32_t s_hist[kMaxDepthPasses][kRadixBins];
     const int tid = threadIdx.x;
+    // Tile ranges start empty: the sort writes only the bounds of tiles that hold pairs.
+    for (int64_t w = (int64_t)blockIdx.x * 256 + tid; w < range_words; w += (int64_t)gridDim.x * 256) ranges[w] = 0u;
 #pragma unroll
     for (int p = 0; p < kMaxDepthPasses; ++p) s_hist[p][tid] = 0u;
     __syncthreads();
@@ -177,6 +180,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     uint32_t cap, int64_t n, int tiles_x, int tiles_per_view, int pair_passes, uint64_t* lb, Ctrl* ctrl) {
     __shared__ uint32_t s_incl[kScanTile];
     __shared__ uint32_t s_rec[kScanTile];
+    __shared__ short4 s_rect[kScanTile];
     __shared__ uint32_t s_hist[kMaxPairPasses][kRadixBins];
     __shared__ uint32_t s_tmp[kScanThreads / kWave];
     __shared__ uint32_t s_base, s_bid, s_agg;
@@ -189,18 +193,27 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     const uint32_t base = bid * (uint32_t)kScanTile;
     if (base >= M) return;
     const uint32_t epoch = ctrl->epoch;
-    uint32_t c[kScanIpt], sum = 0;
+    // The block's records with their counts and tile rectangles, gathered
+    // with every load in flight at once and kept in LDS for the emission.
+    uint32_t c[kScanIpt], rec[kScanIpt], sum = 0;
+    short4 rc[kScanIpt];
 #pragma unroll
     for (int k = 0; k < kScanIpt; ++k) {
         const uint32_t q = tid * kScanIpt + k;
-        uint32_t rec = 0xffffffffu, cnt = 0;
-        if (base + q < M) {
-            rec = min(order[base + q], M - 1);  // order is a permutation of [0, M)
-            cnt = counts[rec];
-        }
-        s_rec[q] = rec;
-        c[k] = cnt;
-        sum += cnt;
+        rec[k] = base + q < M ? min(order[base + q], M - 1) : 0xffffffffu;  // order is a permutation of [0, M)
+    }
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        const bool ok = rec[k] != 0xffffffffu;
+        c[k] = ok ? counts[rec[k]] : 0u;
+        rc[k] = ok ? rects[rec[k]] : make_short4(0, 0, -1, -1);
+    }
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        const uint32_t q = tid * kScanIpt + k;
+        s_rec[q] = rec[k];
+        s_rect[q] = rc[k];
+        sum += c[k];
     }
     const uint32_t texcl = block_exclusive_scan_256(sum, s_tmp);
     uint32_t run = texcl;
@@ -238,16 +251,16 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
         const uint32_t q = lo;
         const uint32_t start = q ? s_incl[q - 1] : 0u;
         const uint32_t j = e - start;
-        const uint32_t rec = s_rec[q];
-        const short4 rc = rects[rec];
-        const uint32_t w = (uint32_t)(rc.z - rc.x + 1);
-        const uint32_t tx = rc.x + j % w, ty = rc.y + j / w;
-        const uint32_t v = (uint32_t)(rec / n);
+        const uint32_t r = s_rec[q];
+        const short4 rq = s_rect[q];
+        const uint32_t w = (uint32_t)(rq.z - rq.x + 1);
+        const uint32_t tx = rq.x + j % w, ty = rq.y + j / w;
+        const uint32_t v = (uint32_t)(r / n);
         const uint32_t tile = v * (uint32_t)tiles_per_view + ty * (uint32_t)tiles_x + tx;
         const uint32_t gpos = gbase + e;
         if (gpos < cap) {
             pkeys[gpos] = tile;
-            pvals[gpos] = rec;
+            pvals[gpos] = r;
             for (int p = 0; p < pair_passes; ++p) atomicAdd(&s_hist[p][(tile >> (8 * p)) & 255u], 1u);
         }
     }
@@ -263,10 +276,11 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
     const StatePtrs& s = f.s;
     hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(256), 0, st, s.ctrl);
     const int64_t M = s.items;
-    if (M == 0) return hipGetLastError();
+    const int64_t range_words = 2 * (int64_t)f.views.tiles_per_view * f.views.n_views;
+    if (M == 0) return launch_zero_words(s.ranges, range_words, st);
     hipLaunchKernelGGL(project_kernel<T>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, f.views, f.consts,
                        f.n, M, params, ids, (T*)s.splats, s.rects, s.counts, s.depth_keys[0], s.depth_vals[0],
-                       s.ctrl);
+                       s.ranges, range_words, s.ctrl);
     int src = 0;
     for (int p = 0; p < kMaxDepthPasses; ++p) {
         hipError_t e = launch_radix_pass(s.depth_keys[src], s.depth_vals[src], s.depth_keys[src ^ 1],

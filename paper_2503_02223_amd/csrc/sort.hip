@@ -7,6 +7,8 @@
 // writes the items out digit-sorted through LDS so stores are coalesced.
 // Digit histograms of every pass are accumulated before the first pass by the
 // kernel that produced the keys.
+#include <algorithm>
+
 #include "dqo_device.hpp"
 #include "sort_common.hpp"
 
@@ -42,12 +44,18 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
 
     uint32_t key[IPT], val[IPT], rank[IPT];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // All loads first: interleaved with the ballots below they were issued one
+    // at a time, each waiting a full memory latency.
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const uint32_t pos = base + wave * (kWave * IPT) + i * kWave + lane;
+        key[i] = pos < n ? kin[pos] : 0u;
+        val[i] = pos < n ? vin[pos] : 0u;
+    }
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const uint32_t pos = base + wave * (kWave * IPT) + i * kWave + lane;
         const bool valid = pos < n;
-        key[i] = valid ? kin[pos] : 0u;
-        val[i] = valid ? vin[pos] : 0u;
         const uint32_t d = (key[i] >> shift) & (kRadixBins - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -106,22 +114,18 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     }
 }
 
-// [start, end) of every global tile id in the sorted pair keys, by binary search.
-__global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
-                                   uint32_t n_host, uint32_t* __restrict__ ranges, int tiles_total) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= tiles_total) return;
+// [start, end) of every tile that holds pairs, from the boundaries of the
+// sorted pair keys (tiles without pairs keep the empty range written when the
+// frame was projected).
+__global__ __launch_bounds__(256) void tile_bounds_kernel(const uint32_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ n_dev, uint32_t n_host,
+                                                          uint32_t* __restrict__ ranges) {
     const uint32_t n = min(*n_dev, n_host);
-    auto lower = [&](uint32_t v) {
-        uint32_t lo = 0, hi = n;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (keys[mid] < v) lo = mid + 1; else hi = mid;
-        }
-        return lo;
-    };
-    ranges[2 * t] = lower((uint32_t)t);
-    ranges[2 * t + 1] = lower((uint32_t)t + 1u);
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        const uint32_t t = keys[i];
+        if (i == 0 || keys[i - 1] != t) ranges[2 * t] = i;
+        if (i + 1 == n || keys[i + 1] != t) ranges[2 * t + 1] = i + 1;
+    }
 }
 
 // Launch order of the render workgroups: tiles by decreasing pair count (in
@@ -192,8 +196,8 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         src ^= 1;
     }
     if (tiles_total > 0) {
-        hipLaunchKernelGGL(tile_ranges_kernel, dim3((tiles_total + 255) / 256), dim3(256), 0, st, s.pair_keys[0],
-                           n_dev, cap, s.ranges, tiles_total);
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ((int64_t)cap + 255) / 256));
+        hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges);
         hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
                            s.schedule);
     }
