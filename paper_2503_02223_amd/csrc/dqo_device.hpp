@@ -29,9 +29,11 @@ constexpr int kDepthIpt = DQO_DEPTH_IPT;
 constexpr int kPairIpt = DQO_PAIR_IPT;
 constexpr int kDepthTile = kSortThreads * kDepthIpt;
 constexpr int kPairTile = kSortThreads * kPairIpt;
-constexpr int kScanThreads = 256;
-constexpr int kScanIpt = 4;
-constexpr int kScanTile = kScanThreads * kScanIpt;      // 1024 items per block
+// Scan + emission: one record per thread, 1024 per block, so that each of the
+// 16 wavefronts emits the pairs of its own 64 records.
+constexpr int kScanThreads = 1024;
+constexpr int kScanIpt = 1;
+constexpr int kScanTile = kScanThreads * kScanIpt;
 constexpr int kMaxDepthPasses = 4;
 constexpr int kMaxPairPasses = 4;
 constexpr int kLossBlocks = 512;

@@ -180,14 +180,18 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     uint32_t cap, int64_t n, int tiles_x, int tiles_per_view, int pair_passes, uint64_t* lb, Ctrl* ctrl) {
     __shared__ uint32_t s_incl[kScanTile];
     __shared__ uint32_t s_rec[kScanTile];
+    __shared__ uint32_t s_tbase[kScanTile];
     __shared__ short4 s_rect[kScanTile];
+    __shared__ uint16_t s_nzq[kScanThreads / kWave][kWave];
+    __shared__ uint8_t s_start[kScanThreads / kWave][kWave];
     __shared__ uint32_t s_hist[kMaxPairPasses][kRadixBins];
     __shared__ uint32_t s_tmp[kScanThreads / kWave];
     __shared__ uint32_t s_base, s_bid, s_agg;
     const int tid = threadIdx.x;
     if (tid == 0) s_bid = atomicAdd(&ctrl->counters[kCounterScan], 1u);
-#pragma unroll
-    for (int p = 0; p < kMaxPairPasses; ++p) s_hist[p][tid] = 0u;
+    if (tid < kRadixBins) {
+        for (int p = 0; p < kMaxPairPasses; ++p) s_hist[p][tid] = 0u;
+    }
     __syncthreads();
     const uint32_t bid = s_bid;
     const uint32_t base = bid * (uint32_t)kScanTile;
@@ -213,9 +217,10 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
         const uint32_t q = tid * kScanIpt + k;
         s_rec[q] = rec[k];
         s_rect[q] = rc[k];
+        s_tbase[q] = rec[k] != 0xffffffffu ? (uint32_t)(rec[k] / (uint32_t)n) * (uint32_t)tiles_per_view : 0u;
         sum += c[k];
     }
-    const uint32_t texcl = block_exclusive_scan_256(sum, s_tmp);
+    const uint32_t texcl = block_exclusive_scan<kScanThreads>(sum, s_tmp);
     uint32_t run = texcl;
 #pragma unroll
     for (int k = 0; k < kScanIpt; ++k) {
@@ -241,34 +246,60 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
         const uint32_t q = tid * kScanIpt + k;
         if (base + q < M) offsets[s_rec[q]] = gbase + s_incl[q] - c[k];
     }
-    // Cooperative emission: consecutive threads write consecutive pair slots.
-    for (uint32_t e = tid; e < agg; e += kScanThreads) {
-        uint32_t lo = 0, hi = kScanTile - 1;
-        while (lo < hi) {  // first q with s_incl[q] > e
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s_incl[mid] > e) hi = mid; else lo = mid + 1;
-        }
-        const uint32_t q = lo;
-        const uint32_t start = q ? s_incl[q - 1] : 0u;
-        const uint32_t j = e - start;
-        const uint32_t r = s_rec[q];
-        const short4 rq = s_rect[q];
-        const uint32_t w = (uint32_t)(rq.z - rq.x + 1);
-        const uint32_t tx = rq.x + j % w, ty = rq.y + j / w;
-        const uint32_t v = (uint32_t)(r / n);
-        const uint32_t tile = v * (uint32_t)tiles_per_view + ty * (uint32_t)tiles_x + tx;
-        const uint32_t gpos = gbase + e;
-        if (gpos < cap) {
-            pkeys[gpos] = tile;
-            pvals[gpos] = r;
-            for (int p = 0; p < pair_passes; ++p) atomicAdd(&s_hist[p][(tile >> (8 * p)) & 255u], 1u);
+    // Emission, one wavefront per group of 64 consecutive records: each round
+    // writes 64 consecutive pair slots.  The record owning slot o is the last
+    // record with pairs that starts at or before o; within a round it is found
+    // from a 64-bit mask of the record starts that fall in the round (one flag
+    // byte per slot in LDS, read back through a ballot) and a population
+    // count, instead of a search.
+    const int lane = tid & (kWave - 1), wave = tid >> 6;
+    const uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;
+    constexpr int kGroups = kScanTile / (kScanThreads / kWave) / kWave;
+#pragma unroll 1
+    for (int g = 0; g < kGroups; ++g) {
+        const int q = (wave * kGroups + g) * kWave + lane;
+        const uint32_t incl = s_incl[q];
+        const uint32_t excl = q ? s_incl[q - 1] : 0u;
+        const bool has = incl > excl;
+        const uint32_t g0 = __shfl(excl, 0), g1 = __shfl(incl, kWave - 1);
+        const uint64_t nzmask = __ballot(has);
+        if (has) s_nzq[wave][__popcll(nzmask & lt)] = (uint16_t)q;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t r0 = g0; r0 < g1; r0 += kWave) {
+            s_start[wave][lane] = 0;
+            if (has && excl >= r0 && excl < r0 + kWave) s_start[wave][excl - r0] = 1;
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t marks = __ballot(s_start[wave][lane] != 0);
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t before = (uint32_t)__popcll(__ballot(has && excl < r0));
+            const uint32_t o = r0 + (uint32_t)lane;
+            if (o < g1) {
+                const uint32_t k = (uint32_t)__popcll(marks & ((2ull << lane) - 1ull));
+                const int qo = s_nzq[wave][before + k - 1];
+                const uint32_t j = o - (qo ? s_incl[qo - 1] : 0u);
+                const short4 rq = s_rect[qo];
+                const uint32_t w = (uint32_t)(rq.z - rq.x + 1);
+                // j / w from the reciprocal, corrected to the exact quotient
+                uint32_t ty = (uint32_t)((float)j * __builtin_amdgcn_rcpf((float)w));
+                if (ty * w > j) --ty;
+                else if ((ty + 1u) * w <= j) ++ty;
+                const uint32_t tx = j - ty * w;
+                const uint32_t tile = s_tbase[qo] + ((uint32_t)rq.y + ty) * (uint32_t)tiles_x + (uint32_t)rq.x + tx;
+                const uint32_t gpos = gbase + o;
+                if (gpos < cap) {
+                    pkeys[gpos] = tile;
+                    pvals[gpos] = s_rec[qo];
+                    for (int p = 0; p < pair_passes; ++p) atomicAdd(&s_hist[p][(tile >> (8 * p)) & 255u], 1u);
+                }
+            }
         }
     }
     __syncthreads();
-    for (int p = 0; p < pair_passes; ++p) {
-        const uint32_t h = s_hist[p][tid];
-        if (h) atomicAdd(&ctrl->hist_pair[p][tid], h);
-    }
+    if (tid < kRadixBins)
+        for (int p = 0; p < pair_passes; ++p) {
+            const uint32_t h = s_hist[p][tid];
+            if (h) atomicAdd(&ctrl->hist_pair[p][tid], h);
+        }
 }
 
 template <typename T>

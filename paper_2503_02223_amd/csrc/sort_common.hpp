@@ -13,9 +13,10 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
     return v;
 }
 
-// Exclusive scan over a 256-thread block (4 waves); s_tmp holds 4 words.
+// Exclusive scan over a block of NT threads; s_tmp holds NT / 64 words.
 // Contains two barriers: every thread of the block must call it.
-__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* s_tmp) {
+template <int NT>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     const uint32_t incl = wave_inclusive_scan(v, lane);
@@ -25,6 +26,9 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
     for (int w = 0; w < wave; ++w) off += s_tmp[w];
     __syncthreads();
     return off + incl - v;
+}
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t* s_tmp) {
+    return block_exclusive_scan<256>(v, s_tmp);
 }
 
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
