@@ -31,7 +31,7 @@ struct Geo {
     int depth_blocks, scan_blocks, pair_blocks, pair_passes, pair_first_buf;
     int64_t lb_words;
     // scratch sub-offsets (relative to DQO_BUF_SCRATCH)
-    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_lbd, off_lbs, off_lbp;
+    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_lbd, off_lbs, off_lbp;
 };
 
 int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams) {
@@ -104,6 +104,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.off_pk1 = so; so = align256(so + cap * 4);
     g.off_pv1 = so; so = align256(so + cap * 4);
     g.off_sched = so; so = align256(so + tiles_total * 4);
+    g.off_sums = so; so = align256(so + M * kGradWords * ts);
     g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * g.depth_blocks * kRadixBins * 8);
     g.off_lbs = so; so = align256(so + (int64_t)g.scan_blocks * 8);
     g.off_lbp = so; so = align256(so + (int64_t)kMaxPairPasses * g.pair_blocks * kRadixBins * 8);
@@ -138,6 +139,7 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.ranges = (uint32_t*)(b + g.L.offset[DQO_BUF_RANGES]);
     s.partials = b + g.L.offset[DQO_BUF_PARTIALS];
     s.schedule = (uint32_t*)(sc + g.off_sched);
+    s.sums = sc + g.off_sums;
     s.ctrl = (Ctrl*)(b + g.L.offset[DQO_BUF_CONTROL]);
     s.lb_depth = (uint64_t*)(sc + g.off_lbd);
     s.lb_scan = (uint64_t*)(sc + g.off_lbs);

@@ -216,6 +216,7 @@ struct StatePtrs {
     uint32_t* ranges;
     uint32_t* schedule;   // [V*tiles] launch order of the render workgroups
     void* partials;
+    void* sums;           // [V*n][kGradWords] per-item totals of the pair partials
     Ctrl* ctrl;
     uint64_t* lb_depth;   // [kMaxDepthPasses][blocks][256]
     uint64_t* lb_scan;    // [blocks]

@@ -364,52 +364,105 @@ template hipError_t launch_zero_partials<double>(const StatePtrs&, hipStream_t);
 // order.  The loads of kSlotBatch slots are issued before any of them is added,
 // so a Gaussian spanning many tiles costs one memory latency per batch instead
 // of one per slot (such Gaussians set the kernel's duration).
-constexpr int kSlotBatch = 8;
+// Per-item totals of the pair partials.  An item's (tile, Gaussian)
+// partials occupy consecutive slots, and items that are consecutive in depth
+// order occupy consecutive slot ranges, so one wavefront takes 64 consecutive
+// items and reads their slots 64 at a time, coalesced.  Each round sums the
+// slots of every item by a segmented scan over the lanes (a fixed tree per
+// segment) and adds the segment totals to the item's accumulator in LDS in
+// round order: the result does not depend on timing.
+constexpr int kSlotWaves = 4;
+
+// Lane-shifted copy of x by DPP (row_shr:n within 16-lane rows, or the
+// row_bcast:15 / row_bcast:31 steps across rows); lanes without a source get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_shift(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_shift(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Inclusive scan of v over the lanes within segments: lane l sums lanes
+// [seg_lo, l], where seg_lo (the first lane of l's segment) is the same for
+// all lanes of a segment.  Row-local shifts by 1, 2, 4, 8, then the last lane
+// of rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3.
+template <typename T>
+__device__ __forceinline__ T segmented_scan(T v, int lane, int seg_lo) {
+    T t;
+    t = dpp_shift<0x111, 0xF>(v); if (lane - 1 >= seg_lo && (lane & 15) >= 1) v += t;
+    t = dpp_shift<0x112, 0xF>(v); if (lane - 2 >= seg_lo && (lane & 15) >= 2) v += t;
+    t = dpp_shift<0x114, 0xF>(v); if (lane - 4 >= seg_lo && (lane & 15) >= 4) v += t;
+    t = dpp_shift<0x118, 0xF>(v); if (lane - 8 >= seg_lo && (lane & 15) >= 8) v += t;
+    t = dpp_shift<0x142, 0xA>(v); if ((lane & 16) && (lane & ~15) - 1 >= seg_lo) v += t;
+    t = dpp_shift<0x143, 0xC>(v); if (lane >= 32 && 31 >= seg_lo) v += t;
+    return v;
+}
 
 template <typename T>
-__device__ __forceinline__ void sum_slots(const T* __restrict__ src, uint32_t cnt, T (&d)[kGradWords]) {
-#pragma unroll
-    for (int k = 0; k < kGradWords; ++k) d[k] = T(0);
-    for (uint32_t j0 = 0; j0 < cnt; j0 += kSlotBatch) {
-        T v[kSlotBatch][kGradWords];
-#pragma unroll
-        for (int b = 0; b < kSlotBatch; ++b) {
-            const uint32_t j = min(j0 + (uint32_t)b, cnt - 1u);
-#pragma unroll
-            for (int k = 0; k < kGradWords; ++k) v[b][k] = src[(size_t)j * kGradWords + k];
-        }
-#pragma unroll
-        for (int b = 0; b < kSlotBatch; ++b)
-            if (j0 + (uint32_t)b < cnt) {
-#pragma unroll
-                for (int k = 0; k < kGradWords; ++k) d[k] += v[b][k];
-            }
+__global__ __launch_bounds__(kSlotWaves * kWave) void slot_sum_kernel(const uint32_t* __restrict__ order,
+                                                                      const uint32_t* __restrict__ counts,
+                                                                      const uint32_t* __restrict__ offsets,
+                                                                      const T* __restrict__ partials, uint32_t M,
+                                                                      uint32_t cap, T* __restrict__ sums) {
+    __shared__ T s_acc[kSlotWaves][kWave][kGradWords + 1];
+    __shared__ uint16_t s_nz[kSlotWaves][kWave];
+    __shared__ uint8_t s_start[kSlotWaves][kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+    const uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;
+    const uint32_t q = ((uint32_t)blockIdx.x * kSlotWaves + wave) * kWave + lane;
+    uint32_t rec = 0, c = 0, off = 0;
+    if (q < M) {
+        rec = min(order[q], M - 1);
+        c = counts[rec];
+        off = offsets[rec];
     }
-}
-template <>
-__device__ __forceinline__ void sum_slots<float>(const float* __restrict__ src, uint32_t cnt,
-                                                 float (&d)[kGradWords]) {
-    static_assert(kGradWords % 2 == 0, "slots are read as float2");
 #pragma unroll
-    for (int k = 0; k < kGradWords; ++k) d[k] = 0.0f;
-    const float2* s2 = reinterpret_cast<const float2*>(src);  // slots are 40 B: 8-byte aligned
-    for (uint32_t j0 = 0; j0 < cnt; j0 += kSlotBatch) {
-        float2 v[kSlotBatch][kGradWords / 2];
+    for (int k = 0; k < kGradWords; ++k) s_acc[wave][lane][k] = T(0);
+    const bool has = c > 0;
+    const uint64_t nzmask = __ballot(has);
+    if (nzmask == 0ull) return;  // wave-uniform; no barrier follows
+    if (has) s_nz[wave][__popcll(nzmask & lt)] = (uint16_t)lane;
+    const int first = __ffsll((unsigned long long)nzmask) - 1, lastl = 63 - __clzll(nzmask);
+    const uint32_t S0 = __shfl(off, first);
+    const uint32_t S1 = (uint32_t)min((uint64_t)cap, (uint64_t)__shfl(off, lastl) + __shfl(c, lastl));
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t r0 = S0; r0 < S1; r0 += kWave) {
+        s_start[wave][lane] = 0;
+        if (has && off >= r0 && off < r0 + kWave) s_start[wave][off - r0] = 1;
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t marks = __ballot(s_start[wave][lane] != 0);
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t before = (uint32_t)__popcll(__ballot(has && off < r0));
+        const uint32_t s = r0 + (uint32_t)lane;
+        const bool live = s < S1;
+        const uint64_t upto = marks & ((2ull << lane) - 1ull);
+        T v[kGradWords];
+        int owner = 0;
+        if (live) {
+            owner = s_nz[wave][before + (uint32_t)__popcll(upto) - 1u];
 #pragma unroll
-        for (int b = 0; b < kSlotBatch; ++b) {
-            const uint32_t j = min(j0 + (uint32_t)b, cnt - 1u);
+            for (int k = 0; k < kGradWords; ++k) v[k] = partials[(size_t)s * kGradWords + k];
+        } else {
 #pragma unroll
-            for (int k = 0; k < kGradWords / 2; ++k) v[b][k] = s2[(size_t)j * (kGradWords / 2) + k];
+            for (int k = 0; k < kGradWords; ++k) v[k] = T(0);
         }
+        const int seg_lo = upto ? 63 - __clzll(upto) : 0;
 #pragma unroll
-        for (int b = 0; b < kSlotBatch; ++b)
-            if (j0 + (uint32_t)b < cnt) {
+        for (int k = 0; k < kGradWords; ++k) v[k] = segmented_scan<T>(v[k], lane, seg_lo);
+        const bool seg_end = live && (lane == kWave - 1 || ((marks >> (lane + 1)) & 1ull) || s + 1u >= S1);
+        if (seg_end) {
 #pragma unroll
-                for (int k = 0; k < kGradWords / 2; ++k) {
-                    d[2 * k] += v[b][k].x;
-                    d[2 * k + 1] += v[b][k].y;
-                }
-            }
+            for (int k = 0; k < kGradWords; ++k) s_acc[wave][owner][k] += v[k];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (has && (uint64_t)off + c <= cap) {
+#pragma unroll
+        for (int k = 0; k < kGradWords; ++k) sums[(size_t)rec * kGradWords + k] = s_acc[wave][lane][k];
     }
 }
 
@@ -418,7 +471,7 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
                                                                const T* __restrict__ params,
                                                                const uint32_t* __restrict__ counts,
                                                                const uint32_t* __restrict__ offsets,
-                                                               const T* __restrict__ partials, uint32_t cap,
+                                                               const T* __restrict__ sums, uint32_t cap,
                                                                T* __restrict__ grads) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= n) return;
@@ -435,10 +488,9 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
         if (cnt == 0) continue;
         const uint32_t off = offsets[item];
         if ((uint64_t)off + cnt > cap) continue;
-        // The item's per-tile partials occupy cnt consecutive slots; they are
-        // summed in slot order (a fixed order: the result is deterministic).
         T d[kGradWords];
-        sum_slots<T>(partials + (size_t)off * kGradWords, cnt, d);
+#pragma unroll
+        for (int k = 0; k < kGradWords; ++k) d[k] = sums[(size_t)item * kGradWords + k];
         const DevCam<T>& c = V.cam[v];
         Proj<T> pr;
         project_item(c, cs, p, pr);
@@ -547,8 +599,12 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
 template <typename T>
 hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads, hipStream_t st) {
     if (f.n == 0) return hipSuccess;
+    const int64_t M = f.s.items;
+    hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
+                       dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
+                       (const T*)f.s.partials, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
     hipLaunchKernelGGL(project_backward_kernel<T>, dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st, f.views,
-                       f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.partials,
+                       f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.sums,
                        (uint32_t)f.s.capacity, grads);
     return hipGetLastError();
 }
