@@ -208,6 +208,95 @@ def bench_keyframes(args):
     print(json.dumps(out), flush=True)
 
 
+def _left_perturb(cam, w, tau):
+    """Camera with R' = exp([w]x) R and t' = exp([w]x) t + tau."""
+    from scipy.spatial.transform import Rotation
+    E = Rotation.from_rotvec(np.asarray(w, np.float64)).as_matrix()
+    out = dict(cam)
+    out["R"] = E @ np.asarray(cam["R"], np.float64).reshape(3, 3)
+    out["t"] = E @ np.asarray(cam["t"], np.float64).reshape(3) + np.asarray(tau, np.float64)
+    return out
+
+
+def _pose_error(cam, ref):
+    """Rotation angle (deg) between the two camera rotations and distance (m)
+    between the camera centres -R^T t."""
+    R, Rr = np.asarray(cam["R"]).reshape(3, 3), np.asarray(ref["R"]).reshape(3, 3)
+    ang = np.degrees(np.arccos(np.clip((np.trace(R @ Rr.T) - 1) / 2, -1, 1)))
+    c, cr = -R.T @ np.asarray(cam["t"]), -Rr.T @ np.asarray(ref["t"])
+    return float(ang), float(np.linalg.norm(c - cr))
+
+
+def bench_tracking(args):
+    """Camera tracking through the rasterizer: the 200k-Gaussian room seen
+    from a displaced camera (0.5 deg, 4 cm), the pose optimised against the
+    frame rendered from the true pose.  One iteration = project/bin + sort +
+    render fwd (loss mode) + object loss + render bwd + pose gradient
+    (dqo_pose_backward) + an Adam step on the 6-vector on the host."""
+    sc = scenes.slam_view_scene(seed=0, n=args.n)
+    n, K = sc["params"].shape[1], sc["K"]
+    true_cam = sc["cams"][0]
+    p = torch.tensor(sc["params"], dtype=torch.float32, device="cuda")
+    ids = torch.tensor(sc["ids"], device="cuda")
+    r0 = B.Rasterizer([true_cam], n, K, ctx=B.Context(tile_w=8, tile_h=8))
+    t0 = r0.forward(p, ids, probs=True, id_map=True)
+    torch.cuda.synchronize()
+    targets = dict(color=t0["color"].clone(), depth=t0["depth"].clone(), id=t0["id_map"].clone())
+    del r0, t0
+    start = _left_perturb(true_cam, [0.006, -0.005, 0.003], [0.03, -0.025, 0.01])
+    r = B.Rasterizer([start], n, K, ctx=B.Context(tile_w=8, tile_h=8))
+    img = r.frame.new_images(target=targets["id"])
+    gi = dict(d_color=torch.empty_like(img["color"]), d_depth=torch.empty_like(img["depth"]),
+              d_p_target=torch.empty_like(img["depth"]))
+    loss = torch.zeros(4, dtype=torch.float64, device="cuda")
+    pose_g = torch.empty(1, 6, dtype=torch.float64, device="cuda")
+    lr = np.array([1e-3] * 3 + [4e-3] * 3)
+    iters = args.steps
+
+    def run(n_it):
+        cam = dict(start)
+        m, v = np.zeros(6), np.zeros(6)
+        hist = []
+        for it in range(1, n_it + 1):
+            r.cams[0] = cam                        # a re-sized frame takes its cameras from here
+            r.frame.cams[0] = B.make_cameras([cam])[0]
+            r.bin(p, ids, grow=True)
+            f = r.frame
+            f.render_forward(img)
+            f.object_loss(img, targets, gi, loss)
+            f.render_backward(img, gi)
+            f.pose_backward(p, pose_g)
+            g = pose_g.cpu().numpy()[0]          # synchronises: the host takes the pose step
+            hist.append(float(loss[0].item()))
+            m = 0.9 * m + 0.1 * g
+            v = 0.999 * v + 0.001 * g * g
+            step = -lr * (m / (1 - 0.9 ** it)) / (np.sqrt(v / (1 - 0.999 ** it)) + 1e-12)
+            cam = _left_perturb(cam, step[:3], step[3:])
+        return cam, hist
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    cam, hist = run(iters)
+    dt = time.perf_counter() - t_start
+    ms = dt * 1e3 / iters
+    e0, e1 = _pose_error(start, true_cam), _pose_error(cam, true_cam)
+    out = {
+        "metric": "camera tracking iters/s (640x480, 200k Gaussians, pose gradient through the rasterizer)",
+        "value": round(1e3 / ms, 2), "unit": "iters/s", "n_gpus": 1, "steps": iters, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "room of 200k Gaussians at 640x480 (8x8 tiles), target rendered from the true pose, "
+                               "start displaced by 0.5 deg and 4 cm; iteration = project/bin + sort + render fwd + "
+                               "object loss + render bwd + pose gradient + host Adam step on (w, tau)",
+                   "n_gaussians": n},
+        "tracking": {"start_error_deg_m": [round(e0[0], 4), round(e0[1], 4)],
+                     "final_error_deg_m": [round(e1[0], 4), round(e1[1], 4)],
+                     "loss_first_last": [round(hist[0], 6), round(hist[-1], 6)]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_large(args):
     """1M Gaussians at 1200x680 through the torch.autograd.Function (forward +
     L1 colour/depth loss + backward, FP32), with peak device memory against the
@@ -328,10 +417,11 @@ def bench_learned(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="slam", choices=["slam", "keyframes", "large", "learned-init"],
+    ap.add_argument("--workload", default="slam", choices=["slam", "keyframes", "large", "learned-init", "tracking"],
                     help="slam: 200k Gaussians at 640x480 (default, the headline line); keyframes: 8 views over "
                          "1.2M Gaussians in a HIP graph; large: 1M at 1200x680 through autograd; learned-init: "
-                         "train the initialization network and measure time-to-PSNR")
+                         "train the initialization network and measure time-to-PSNR; tracking: camera pose "
+                         "optimisation through the rasterizer on the 200k view")
     ap.add_argument("--n-train", type=int, default=5000)
     ap.add_argument("--n-val", type=int, default=256)
     ap.add_argument("--n-test", type=int, default=20)
@@ -372,6 +462,8 @@ def main():
         return bench_keyframes(args)
     if args.workload == "large":
         return bench_large(args)
+    if args.workload == "tracking":
+        return bench_tracking(args)
     log("building workload")
     sc, p, ids, targets = build_workload(n=args.n)
     tr = B.Trainer(p, ids, sc["cams"], sc["K"], targets, ctx=B.Context(tile_w=tw, tile_h=th))

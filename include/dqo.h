@@ -278,6 +278,27 @@ int dqo_adam_step(const dqo_ctx* ctx, int32_t dtype, void* params, const void* g
 int dqo_adam_step_counted(const dqo_ctx* ctx, int32_t dtype, void* params, const void* grads, void* m, void* v,
                           int64_t n, const dqo_adam* hp /* host */, int64_t* d_step, void* stream);
 
+/* Camera-pose gradient of every view, for tracking with the rasterizer (the
+ * paper tracks the camera through the same differentiable rendering, Sec. IV).
+ * The pose of view v is x_c = R x_w + t, perturbed on the left in the camera
+ * frame: R' = exp([w]x) R, t' = exp([w]x) t + tau.  pose_grads (device
+ * double [V][6], overwritten) = (dL/dw, dL/dtau) at w = tau = 0, for the loss
+ * whose image gradients the preceding dqo_render_backward took.  Reduction
+ * order is fixed (bitwise reproducible). */
+int dqo_pose_backward(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams, const void* params,
+                      const void* state, double* pose_grads, void* stream);
+
+/* dqo_project_backward and dqo_adam_step_counted in one pass: each
+ * Gaussian's gradient is applied at once by the same Adam update to params
+ * (in place), m and v (device, [14][n], the frame's dtype); the update uses
+ * step = *d_step + 1 and the call advances *d_step by one.  grads (optional,
+ * NULL to skip) receives the gradient.  Results are bitwise those of the two
+ * separate calls.  params must be the parameters the frame was projected
+ * with (they are read before being overwritten, per Gaussian). */
+int dqo_project_backward_adam(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams, void* params,
+                              const void* state, void* m, void* v, const dqo_adam* hp /* host */, int64_t* d_step,
+                              void* grads, void* stream);
+
 /* ---- incremental update ---------------------------------------------------- */
 
 /* Thresholds of Eq. (7) and the opacities of the Gaussians added where they
@@ -385,6 +406,34 @@ int dqo_refine_quadrics(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, cons
                         const int32_t* box_obj, const int32_t* box_view, int32_t n_views, const double* P,
                         const int32_t* img_wh, const int32_t* status, const dqo_refine_cfg* cfg /* host */,
                         double* mu, double* R, double* axes, double* Q, double* loss, double* box_iou, void* stream);
+
+/* ---- object association ---------------------------------------------------- */
+
+/* Association scores of a batch of detections (Sec. III-B, Eq. (4)-(6)), FP64.
+ * Objects: mu[n_obj][3], R[n_obj][9] (row-major rotation), axes[n_obj][3].
+ * Detections: boxes[n_det][4] (x0, y0, x1, y1) of frames det_frame[n_det] in
+ * [0, n_frames), whose cameras are P[n_frames][12] (P = K [R|t]) and image
+ * sizes img_wh[n_frames][2].  Outputs (device, overwritten):
+ *   iou[n_obj][n_det]  IoU of object k's projected box (the tangent box of
+ *                      C* = P Q* P^T, clipped to the image; 0 when the
+ *                      projection is not an ellipse in front of the camera)
+ *                      with detection j, in detection j's frame;
+ *   match[n_det]       the object of largest IoU (lowest index among equals)
+ *                      when that IoU >= iou_min, else -1 (a new object);
+ *   occ[n_det][n_det]  (optional, NULL to skip) Eq. (6)'s overlap ratio
+ *                      |B_i n B_j| / |B_j| for detections of the same frame
+ *                      with |B_j| < |B_i|, else 0.
+ * All inputs are device memory. */
+int dqo_associate(const dqo_ctx* ctx, int32_t n_obj, const double* mu, const double* R, const double* axes,
+                  int64_t n_det, const double* boxes, const int32_t* det_frame, int32_t n_frames, const double* P,
+                  const int32_t* img_wh, double iou_min, double* iou, int32_t* match, double* occ, void* stream);
+
+/* Quadric distance of Eq. (5) between two sets of quadrics:
+ * qd[a][b] = exp(-tau (||mu_a - mu_b|| + ||S_a - S_b||_F)) with the shape
+ * matrix S = R diag(axes^2) R^T (device FP64 in and out; qd[na][nb]). */
+int dqo_quadric_distance(const dqo_ctx* ctx, int32_t na, const double* mu_a, const double* R_a, const double* axes_a,
+                         int32_t nb, const double* mu_b, const double* R_b, const double* axes_b, double tau,
+                         double* qd, void* stream);
 
 #ifdef __cplusplus
 }

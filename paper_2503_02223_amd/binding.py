@@ -29,9 +29,9 @@ BUF_NAMES = ["splats", "rects", "counts", "offsets", "depth_keys", "depth_order"
 EXPORTED = ["dqo_config_default", "dqo_ctx_create", "dqo_ctx_destroy", "dqo_last_error", "dqo_status_string",
             "dqo_version", "dqo_state_layout", "dqo_state_init", "dqo_read_status", "dqo_clear_status",
             "dqo_project_cull_bin", "dqo_sort", "dqo_render_forward", "dqo_object_loss", "dqo_render_backward",
-            "dqo_project_backward", "dqo_adam_step", "dqo_adam_step_counted", "dqo_fit_dual_quadric",
+            "dqo_project_backward", "dqo_project_backward_adam", "dqo_pose_backward", "dqo_adam_step", "dqo_adam_step_counted", "dqo_fit_dual_quadric",
             "dqo_id_boxes", "dqo_incremental_masks", "dqo_densify", "dqo_quadric_iou_grad",
-            "dqo_refine_quadrics"]
+            "dqo_refine_quadrics", "dqo_associate", "dqo_quadric_distance"]
 # include/dqo_learned.h
 EXPORTED_LEARNED = ["dqo_net_layout_get", "dqo_net_workspace_size", "dqo_net_pack", "dqo_net_forward", "dqo_net_loss",
                     "dqo_net_backward", "dqo_adam_flat", "dqo_init_gaussians", "dqo_init_labels", "dqo_net_fallback",
@@ -154,12 +154,16 @@ def lib():
     L.dqo_object_loss.argtypes = fr + [P(Images), P(Targets), P(LossWeights), vp, P(ImageGrads), vp, vp]
     L.dqo_render_backward.argtypes = fr + [vp, P(Images), P(ImageGrads), vp]
     L.dqo_project_backward.argtypes = fr + [vp, vp, vp, vp]
+    L.dqo_project_backward_adam.argtypes = fr + [vp, vp, vp, vp, P(AdamParams), vp, vp, vp]
+    L.dqo_pose_backward.argtypes = fr + [vp, vp, vp, vp]
     L.dqo_adam_step.argtypes = [ctx, i32, vp, vp, vp, vp, i64, P(AdamParams), i64, vp]
     L.dqo_incremental_masks.argtypes = fr + [P(Images), P(Targets), P(IncrementCfg), vp, vp, vp]
     L.dqo_densify.argtypes = fr + [P(Targets), vp, P(IncrementCfg), i64, i64, vp, vp, vp, vp]
     L.dqo_adam_step_counted.argtypes = [ctx, i32, vp, vp, vp, vp, i64, P(AdamParams), vp, vp]
     L.dqo_fit_dual_quadric.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp]
     L.dqo_id_boxes.argtypes = [ctx, vp, i32, i32, i32, i32, vp, vp, vp, vp]
+    L.dqo_associate.argtypes = [ctx, i32, vp, vp, vp, i64, vp, vp, i32, vp, vp, d, vp, vp, vp, vp]
+    L.dqo_quadric_distance.argtypes = [ctx, i32, vp, vp, vp, i32, vp, vp, vp, d, vp, vp]
     L.dqo_quadric_iou_grad.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.dqo_refine_quadrics.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, vp, P(RefineCfg), vp, vp, vp, vp, vp,
                                       vp, vp]
@@ -349,6 +353,24 @@ class Frame:
         self.ctx.check(lib().dqo_project_backward(*self._fr(), _ptr(params), _ptr(self.state), _ptr(grads),
                                                   _stream(stream)))
 
+    def project_backward_adam(self, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lrs, d_step: torch.Tensor,
+                              grads: Optional[torch.Tensor] = None, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+        """project_backward + adam_step_counted in one pass (params, m, v updated in place)."""
+        assert d_step.dtype == torch.int64 and d_step.numel() == 1
+        hp = _adam_hp(lrs, beta1, beta2, eps)
+        self.ctx.check(lib().dqo_project_backward_adam(*self._fr(), _ptr(params), _ptr(self.state), _ptr(m), _ptr(v),
+                                                       ctypes.byref(hp), _ptr(d_step), _ptr(grads), _stream(stream)))
+
+    def pose_backward(self, params: torch.Tensor, pose_grads: Optional[torch.Tensor] = None, stream=None):
+        """(dL/dw, dL/dtau) per view, [V][6] float64 on the device (left
+        perturbation of each camera: R' = exp([w]x) R, t' = exp([w]x) t + tau)."""
+        if pose_grads is None:
+            pose_grads = torch.empty(self.V, 6, dtype=torch.float64, device=self.device)
+        assert pose_grads.dtype == torch.float64 and pose_grads.numel() >= 6 * self.V
+        self.ctx.check(lib().dqo_pose_backward(*self._fr(), _ptr(params), _ptr(self.state), _ptr(pose_grads),
+                                               _stream(stream)))
+        return pose_grads
+
     # -- incremental update (Eq. (7)-(8)) --
     def incremental_masks(self, img, tgt: Dict[str, torch.Tensor], masks: torch.Tensor, obj_counts: torch.Tensor,
                           stream=None, **cfg):
@@ -433,6 +455,33 @@ def fit_dual_quadric(ctx: Context, boxes, box_obj, box_view, Ps, n_obj, img_wh=N
                                          _ptr(box_view), int(Ps.shape[0]), _ptr(Ps), _ptr(img_wh), float(border),
                                          _ptr(Q), _ptr(mu), _ptr(R), _ptr(axes), _ptr(status), _stream(stream)))
     return dict(Q=Q, mu=mu, R=R, axes=axes, status=status)
+
+
+# association thresholds (the paper leaves tau and the IoU threshold unstated)
+ASSOC_DEFAULTS = dict(iou_min=0.3, tau=1.0)
+
+
+def associate(ctx: Context, mu, R, axes, boxes, det_frame, Ps, img_wh, iou_min=ASSOC_DEFAULTS["iou_min"],
+              occlusion=True, stream=None):
+    """Association scores of detections against object quadrics (device tensors)."""
+    n_obj, n_det = int(mu.shape[0]), int(boxes.shape[0])
+    dev = boxes.device
+    iou = torch.empty(n_obj, n_det, dtype=torch.float64, device=dev)
+    match = torch.empty(n_det, dtype=torch.int32, device=dev)
+    occ = torch.empty(n_det, n_det, dtype=torch.float64, device=dev) if occlusion else None
+    ctx.check(lib().dqo_associate(ctx.h, n_obj, _ptr(mu), _ptr(R), _ptr(axes), n_det, _ptr(boxes), _ptr(det_frame),
+                                  int(Ps.shape[0]), _ptr(Ps), _ptr(img_wh), float(iou_min), _ptr(iou), _ptr(match),
+                                  _ptr(occ), _stream(stream)))
+    return dict(iou=iou, match=match, occ=occ)
+
+
+def quadric_distance(ctx: Context, a, b, tau=ASSOC_DEFAULTS["tau"], stream=None):
+    """Eq. (5) between quadric sets a and b (dicts of mu, R, axes device tensors)."""
+    na, nb = int(a["mu"].shape[0]), int(b["mu"].shape[0])
+    qd = torch.empty(na, nb, dtype=torch.float64, device=a["mu"].device)
+    ctx.check(lib().dqo_quadric_distance(ctx.h, na, _ptr(a["mu"]), _ptr(a["R"]), _ptr(a["axes"]), nb, _ptr(b["mu"]),
+                                         _ptr(b["R"]), _ptr(b["axes"]), float(tau), _ptr(qd), _stream(stream)))
+    return qd
 
 
 def quadric_iou_grad(ctx: Context, boxes, box_obj, box_view, Ps, theta, img_wh=None, stream=None):
@@ -564,10 +613,12 @@ class Trainer:
     """The timed training iteration: project/bin, sort, render forward (loss
     mode: probability of each pixel's target object), object loss, render
     backward, project backward and Adam, all as libdqo calls on one stream
-    with preallocated buffers and no host synchronisation."""
+    with preallocated buffers and no host synchronisation.  With fused set,
+    project backward and Adam are one call (same results, one pass over the
+    parameters); self.grads is then not written."""
 
     def __init__(self, params: torch.Tensor, ids: torch.Tensor, cams, K, targets: Dict[str, torch.Tensor],
-                 lrs=None, capacity=None, loss_weights=(1.0, 1.0, 1.0), ctx=None, segments=None):
+                 lrs=None, capacity=None, loss_weights=(1.0, 1.0, 1.0), ctx=None, segments=None, fused=True):
         self.params = params.contiguous()
         self.ids = ids
         self.n = params.shape[1]
@@ -596,6 +647,7 @@ class Trainer:
         self.lw = loss_weights
         self.step_count = 0
         self.d_step = torch.zeros(1, dtype=torch.int64, device=dev)  # Adam step count on the device
+        self.fused = fused   # project backward and Adam in one pass (bitwise the same as the two calls)
 
     def step(self, stream=None):
         f = self.r.frame
@@ -604,9 +656,13 @@ class Trainer:
         f.render_forward(self.img, stream)
         f.object_loss(self.img, self.targets, self.grads_img, self.loss, *self.lw, stream=stream)
         f.render_backward(self.img, self.grads_img, stream)
-        f.project_backward(self.params, self.grads, stream)
         self.step_count += 1
-        adam_step_counted(self.r.ctx, self.params, self.grads, self.m, self.v, self.lrs, self.d_step, stream=stream)
+        if self.fused:
+            f.project_backward_adam(self.params, self.m, self.v, self.lrs, self.d_step, stream=stream)
+        else:
+            f.project_backward(self.params, self.grads, stream)
+            adam_step_counted(self.r.ctx, self.params, self.grads, self.m, self.v, self.lrs, self.d_step,
+                              stream=stream)
 
     def capture(self):
         """Records one training step (every kernel of it, on one stream) in a

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdqo.so")
 SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "loss.hip", "adam.hip", "quadric.hip",
-           "net.hip", "init.hip", "learned_api.hip", "incremental.hip", "refine.hip"]
+           "net.hip", "init.hip", "learned_api.hip", "incremental.hip", "refine.hip", "assoc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed-FP32 instructions (v_pk_*_f32) anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

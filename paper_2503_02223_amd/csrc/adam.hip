@@ -5,26 +5,9 @@
 // The bias corrections come either from the host (step known at launch) or
 // from a step counter in device memory (graph-capturable: the same launch
 // replays every iteration).
-#include "dqo_device.hpp"
+#include "adam_common.hpp"
 
 namespace dqo {
-
-template <typename T>
-struct AdamArgs {
-    double lr[kParams];
-    double beta1, beta2;
-    T b1c, b2, b2c, eps;
-    T step_size[kParams];  // lr / bc1 per row (host step)
-    T inv_sqrt_bc2;        // (host step)
-};
-
-template <typename T>
-__device__ __forceinline__ void adam_one(T& p, T g, T& m, T& v, T ss, T isb, const AdamArgs<T>& a) {
-    m = m + a.b1c * (g - m);
-    v = v * a.b2 + a.b2c * g * g;
-    const T denom = sqrt(v) * isb + a.eps;
-    p = p - ss * (m / denom);
-}
 
 // Step size and 1/sqrt(bc2) of this row: from the host, or from the device
 // step counter (computed once per workgroup).
@@ -36,13 +19,7 @@ __device__ __forceinline__ void step_factors(const AdamArgs<T>& a, const int64_t
         return;
     }
     __shared__ T s_f[2];
-    if (threadIdx.x == 0) {
-        const double t = (double)(*d_step + 1);
-        const double bc1 = 1.0 - pow(a.beta1, t);
-        const double bc2 = 1.0 - pow(a.beta2, t);
-        s_f[0] = (T)(a.lr[row] / bc1);
-        s_f[1] = (T)(1.0 / sqrt(bc2));
-    }
+    if (threadIdx.x == 0) device_step_factors<T>(a, *d_step, row, s_f[0], s_f[1]);
     __syncthreads();
     ss = s_f[0];
     isb = s_f[1];
@@ -95,18 +72,7 @@ hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, const dqo_adam& 
         if (d_step) hipLaunchKernelGGL(step_increment_kernel, dim3(1), dim3(1), 0, st, d_step);
         return hipGetLastError();
     }
-    AdamArgs<T> a;
-    for (int r = 0; r < kParams; ++r) a.lr[r] = hp.lr[r];
-    a.beta1 = hp.beta1;
-    a.beta2 = hp.beta2;
-    a.b1c = (T)(1.0 - hp.beta1);
-    a.b2 = (T)hp.beta2;
-    a.b2c = (T)(1.0 - hp.beta2);
-    a.eps = (T)hp.eps;
-    const double bc1 = 1.0 - pow(hp.beta1, (double)(step > 0 ? step : 1));
-    const double bc2 = 1.0 - pow(hp.beta2, (double)(step > 0 ? step : 1));
-    for (int r = 0; r < kParams; ++r) a.step_size[r] = (T)(hp.lr[r] / bc1);
-    a.inv_sqrt_bc2 = (T)(1.0 / sqrt(bc2));
+    const AdamArgs<T> a = make_adam_args<T>(hp, step);
     bool vec = sizeof(T) == 4 && (n % 4) == 0 && ((uintptr_t)p % 16) == 0 && ((uintptr_t)g % 16) == 0 &&
                ((uintptr_t)m % 16) == 0 && ((uintptr_t)v % 16) == 0;
     const int64_t len = vec ? n / 4 : n;

@@ -31,7 +31,7 @@ struct Geo {
     int depth_blocks, scan_blocks, pair_blocks, pair_passes, pair_first_buf;
     int64_t lb_words;
     // scratch sub-offsets (relative to DQO_BUF_SCRATCH)
-    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_lbd, off_lbs, off_lbp;
+    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_lbd, off_lbs, off_lbp;
 };
 
 int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams) {
@@ -105,6 +105,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.off_pv1 = so; so = align256(so + cap * 4);
     g.off_sched = so; so = align256(so + tiles_total * 4);
     g.off_sums = so; so = align256(so + M * kGradWords * ts);
+    g.off_pose = so; so = align256(so + (int64_t)d->n_views * ((d->n + 255) / 256) * 6 * 8);
     g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * g.depth_blocks * kRadixBins * 8);
     g.off_lbs = so; so = align256(so + (int64_t)g.scan_blocks * 8);
     g.off_lbp = so; so = align256(so + (int64_t)kMaxPairPasses * g.pair_blocks * kRadixBins * 8);
@@ -140,6 +141,7 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.partials = b + g.L.offset[DQO_BUF_PARTIALS];
     s.schedule = (uint32_t*)(sc + g.off_sched);
     s.sums = sc + g.off_sums;
+    s.pose_partials = (double*)(sc + g.off_pose);
     s.ctrl = (Ctrl*)(b + g.L.offset[DQO_BUF_CONTROL]);
     s.lb_depth = (uint64_t*)(sc + g.off_lbd);
     s.lb_scan = (uint64_t*)(sc + g.off_lbs);
@@ -460,6 +462,49 @@ int dqo_project_backward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_
     });
 }
 
+int dqo_pose_backward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const void* params,
+                      const void* state, double* pose_grads, void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state || !pose_grads || (d->n > 0 && !params))
+        return fail(ctx, DQO_EINVAL, "params, state and pose_grads must not be NULL");
+    Geo g = geometry(ctx, d, cams);
+    if (d->dtype == DQO_F32) {
+        Frame<float> f = make_frame<float>(ctx, d, cams, g, (void*)state);
+        return run(ctx, "pose_backward", [&] {
+            return launch_pose_backward<float>(f, (const float*)params, pose_grads, (hipStream_t)stream);
+        });
+    }
+    Frame<double> f = make_frame<double>(ctx, d, cams, g, (void*)state);
+    return run(ctx, "pose_backward", [&] {
+        return launch_pose_backward<double>(f, (const double*)params, pose_grads, (hipStream_t)stream);
+    });
+}
+
+int dqo_project_backward_adam(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, void* params,
+                              const void* state, void* m, void* v, const dqo_adam* hp, int64_t* d_step, void* grads,
+                              void* stream) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!state || !hp || !d_step || (d->n > 0 && (!params || !m || !v)))
+        return fail(ctx, DQO_EINVAL, "params, state, m, v, hyper-parameters and the step counter are required");
+    if (!(hp->beta1 >= 0 && hp->beta1 < 1 && hp->beta2 >= 0 && hp->beta2 < 1 && hp->eps >= 0))
+        return fail(ctx, DQO_EINVAL, "adam betas must lie in [0, 1) and eps >= 0");
+    Geo g = geometry(ctx, d, cams);
+    if (d->dtype == DQO_F32) {
+        Frame<float> f = make_frame<float>(ctx, d, cams, g, (void*)state);
+        return run(ctx, "project_backward_adam", [&] {
+            return launch_project_backward_adam<float>(f, (float*)params, (float*)grads, (float*)m, (float*)v, *hp,
+                                                       d_step, (hipStream_t)stream);
+        });
+    }
+    Frame<double> f = make_frame<double>(ctx, d, cams, g, (void*)state);
+    return run(ctx, "project_backward_adam", [&] {
+        return launch_project_backward_adam<double>(f, (double*)params, (double*)grads, (double*)m, (double*)v, *hp,
+                                                    d_step, (hipStream_t)stream);
+    });
+}
+
 int dqo_incremental_masks(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams,
                           const dqo_images* img, const dqo_targets* tgt, const dqo_increment_cfg* cfg,
                           uint8_t* masks, int32_t* obj_counts, void* stream) {
@@ -612,6 +657,37 @@ int dqo_refine_quadrics(const dqo_ctx* ctx, int32_t n_obj, int64_t n_boxes, cons
     return run(ctx, "refine_quadrics", [&] {
         return launch_refine_quadrics(n_obj, n_views, n_boxes, boxes, box_obj, box_view, P, img_wh, status, *cfg, mu,
                                       R, axes, Q, loss, box_iou, (hipStream_t)stream);
+    });
+}
+
+int dqo_associate(const dqo_ctx* ctx, int32_t n_obj, const double* mu, const double* R, const double* axes,
+                  int64_t n_det, const double* boxes, const int32_t* det_frame, int32_t n_frames, const double* P,
+                  const int32_t* img_wh, double iou_min, double* iou, int32_t* match, double* occ, void* stream) {
+    if (!ctx) return DQO_EINVAL;
+    if (n_obj < 0 || n_obj > 65535 || n_det < 0 || n_frames < 0) return fail(ctx, DQO_EINVAL, "bad sizes");
+    if ((int64_t)n_obj * n_det > (int64_t(1) << 31) || n_det > (int64_t(1) << 15))
+        return fail(ctx, DQO_EINVAL, "n_obj * n_det must be < 2^31 and n_det <= 32768");
+    if (n_det > 0 && (!boxes || !det_frame || !match || n_frames < 1 || !P || !img_wh))
+        return fail(ctx, DQO_EINVAL, "boxes, det_frame, P, img_wh and match are required");
+    if (n_obj > 0 && n_det > 0 && (!mu || !R || !axes || !iou))
+        return fail(ctx, DQO_EINVAL, "object quadrics and iou are required");
+    if (!isfinite(iou_min)) return fail(ctx, DQO_EINVAL, "iou_min must be finite");
+    return run(ctx, "associate", [&] {
+        return launch_associate(n_obj, mu, R, axes, n_det, boxes, det_frame, n_frames, P, img_wh, iou_min, iou, match,
+                                occ, (hipStream_t)stream);
+    });
+}
+
+int dqo_quadric_distance(const dqo_ctx* ctx, int32_t na, const double* mu_a, const double* R_a, const double* axes_a,
+                         int32_t nb, const double* mu_b, const double* R_b, const double* axes_b, double tau,
+                         double* qd, void* stream) {
+    if (!ctx) return DQO_EINVAL;
+    if (na < 0 || nb < 0 || (int64_t)na * nb > (int64_t(1) << 31)) return fail(ctx, DQO_EINVAL, "bad sizes");
+    if ((int64_t)na * nb > 0 && (!mu_a || !R_a || !axes_a || !mu_b || !R_b || !axes_b || !qd))
+        return fail(ctx, DQO_EINVAL, "quadric buffers and qd must not be NULL");
+    if (!(tau >= 0) || !isfinite(tau)) return fail(ctx, DQO_EINVAL, "tau must be finite and >= 0");
+    return run(ctx, "quadric_distance", [&] {
+        return launch_quadric_distance(na, mu_a, R_a, axes_a, nb, mu_b, R_b, axes_b, tau, qd, (hipStream_t)stream);
     });
 }
 

@@ -42,6 +42,7 @@ constexpr int kLossBlocks = 512;
 constexpr int kCounterDepth = 0;   // + pass
 constexpr int kCounterScan = 4;
 constexpr int kCounterPair = 5;    // + pass
+constexpr int kCounterAdam = 12;   // workgroups done in the fused project-backward + Adam
 constexpr int kNumCounters = 16;
 
 // Control block at the start of DQO_BUF_CONTROL.
@@ -217,6 +218,7 @@ struct StatePtrs {
     uint32_t* schedule;   // [V*tiles] launch order of the render workgroups
     void* partials;
     void* sums;           // [V*n][kGradWords] per-item totals of the pair partials
+    double* pose_partials;  // [V][ceil(n/256)][6] per-block camera-pose gradient sums
     Ctrl* ctrl;
     uint64_t* lb_depth;   // [kMaxDepthPasses][blocks][256]
     uint64_t* lb_scan;    // [blocks]
@@ -267,6 +269,13 @@ hipError_t launch_clear_status(Ctrl* ctrl, hipStream_t st);
 hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_zero_partials(const StatePtrs& s, hipStream_t st);
+hipError_t launch_associate(int n_obj, const double* mu, const double* R, const double* ax, int64_t n_det,
+                            const double* boxes, const int32_t* det_frame, int n_frames, const double* P,
+                            const int32_t* img_wh, double iou_min, double* iou, int32_t* match, double* occ,
+                            hipStream_t st);
+hipError_t launch_quadric_distance(int na, const double* mu_a, const double* R_a, const double* ax_a, int nb,
+                                   const double* mu_b, const double* R_b, const double* ax_b, double tau, double* qd,
+                                   hipStream_t st);
 hipError_t launch_quadric_iou_grad(int n_obj, int n_views, int64_t n_boxes, const double* boxes,
                                    const int32_t* box_obj, const int32_t* box_view, const double* P,
                                    const int32_t* img_wh, const double* theta, double* loss, double* grad,
@@ -275,6 +284,11 @@ hipError_t launch_refine_quadrics(int n_obj, int n_views, int64_t n_boxes, const
                                   const int32_t* box_obj, const int32_t* box_view, const double* P,
                                   const int32_t* img_wh, const int32_t* status, const dqo_refine_cfg& c, double* mu,
                                   double* R, double* axes, double* Q, double* loss, double* box_iou, hipStream_t st);
+template <typename T>
+hipError_t launch_pose_backward(const Frame<T>& f, const T* params, double* pose, hipStream_t st);
+template <typename T>
+hipError_t launch_project_backward_adam(const Frame<T>& f, T* params, T* grads, T* m, T* v, const dqo_adam& hp,
+                                        int64_t* d_step, hipStream_t st);
 template <typename T>
 hipError_t launch_incremental_masks(const Frame<T>& f, const dqo_images& img, const dqo_targets& tgt,
                                     const dqo_increment_cfg& cfg, uint8_t* masks, int32_t* counts, hipStream_t st);

@@ -56,30 +56,39 @@ __global__ __launch_bounds__(kLossThreads) void loss_partial_kernel(const T* __r
     }
 }
 
-__global__ __launch_bounds__(kLossThreads) void loss_final_kernel(Ctrl* ctrl, int nblocks, int64_t npix,
-                                                                  double w_rgb, double w_d, double lam,
-                                                                  double* loss) {
-    // wave c sums component c: lane l takes blocks l, l + 64, ... in order, then a
-    // fixed shuffle tree combines the lanes (deterministic for a given block count)
+// Totals of the per-block partials: wave c sums component c, lane l taking
+// blocks l, l + 64, ... in order, then a fixed shuffle tree combines the
+// lanes (deterministic for a given block count).  Every thread of the block
+// must call it; the totals land in s_tot.
+__device__ __forceinline__ void loss_totals(const Ctrl* ctrl, int nblocks, double* s_tot) {
     const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
     double a = 0;
     for (int b = lane; b < nblocks; b += 64) a += ctrl->loss_partials[b][c];
     a = wave_sum_d(a);
+    if (lane == 0) s_tot[c] = a;
     __syncthreads();
-    if (lane == 0) ctrl->loss_partials[kLossBlocks - 1][c] = a;  // staging (block count < kLossBlocks)
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double* tot = ctrl->loss_partials[kLossBlocks - 1];
-        const double nv = tot[2];
-        const double l_rgb = npix ? tot[0] / (3.0 * (double)npix) : 0.0;
-        const double l_d = nv > 0 ? tot[1] / nv : 0.0;
-        const double l_obj = npix ? tot[3] / (double)npix : 0.0;
-        loss[0] = w_rgb * l_rgb + w_d * l_d + lam * l_obj;
-        loss[1] = l_rgb;
-        loss[2] = l_d;
-        loss[3] = l_obj;
-        ctrl->n_valid = (uint32_t)nv;
-    }
+}
+
+__device__ __forceinline__ void write_loss(const double* tot, int64_t npix, double w_rgb, double w_d, double lam,
+                                           double* loss, Ctrl* ctrl) {
+    const double nv = tot[2];
+    const double l_rgb = npix ? tot[0] / (3.0 * (double)npix) : 0.0;
+    const double l_d = nv > 0 ? tot[1] / nv : 0.0;
+    const double l_obj = npix ? tot[3] / (double)npix : 0.0;
+    loss[0] = w_rgb * l_rgb + w_d * l_d + lam * l_obj;
+    loss[1] = l_rgb;
+    loss[2] = l_d;
+    loss[3] = l_obj;
+    ctrl->n_valid = (uint32_t)nv;
+}
+
+// The loss alone (no gradients requested).
+__global__ __launch_bounds__(kLossThreads) void loss_final_kernel(Ctrl* ctrl, int nblocks, int64_t npix,
+                                                                  double w_rgb, double w_d, double lam,
+                                                                  double* loss) {
+    __shared__ double s_tot[4];
+    loss_totals(ctrl, nblocks, s_tot);
+    if (threadIdx.x == 0) write_loss(s_tot, npix, w_rgb, w_d, lam, loss, ctrl);
 }
 
 template <typename T>
@@ -90,13 +99,19 @@ __global__ __launch_bounds__(kLossThreads) void loss_grad_kernel(const T* __rest
                                                                  const T* __restrict__ pt, const T* __restrict__ tC,
                                                                  const T* __restrict__ tD, int64_t HW, int V,
                                                                  double w_rgb, double w_d, double lam, double eps,
-                                                                 const Ctrl* __restrict__ ctrl, T* __restrict__ gC,
+                                                                 Ctrl* __restrict__ ctrl, int nblocks,
+                                                                 double* __restrict__ loss, T* __restrict__ gC,
                                                                  T* __restrict__ gD, T* __restrict__ gP) {
+    // Every block forms the totals itself (the valid-depth count scales the
+    // depth gradient); block 0 also writes the loss.
+    __shared__ double s_tot[4];
+    loss_totals(ctrl, nblocks, s_tot);
     const int64_t npix = HW * V;
+    if (blockIdx.x == 0 && threadIdx.x == 0) write_loss(s_tot, npix, w_rgb, w_d, lam, loss, ctrl);
     const int64_t i = (int64_t)blockIdx.x * kLossThreads + threadIdx.x;
     if (i >= npix) return;
     const T crgb = (T)(w_rgb / (3.0 * (double)npix));
-    const uint32_t nv = ctrl->n_valid;
+    const uint32_t nv = (uint32_t)s_tot[2];
     const T cd = nv ? (T)(w_d / (double)nv) : T(0);
     const T cobj = (T)(-lam / (double)npix);
     const int64_t v = i / HW, p = i - v * HW;
@@ -123,14 +138,15 @@ hipError_t launch_object_loss(const Frame<T>& f, const dqo_images& img, const dq
     hipLaunchKernelGGL(loss_partial_kernel<T>, dim3(blocks), dim3(kLossThreads), 0, st, (const T*)img.color,
                        (const T*)img.depth, (const T*)img.p_target, (const T*)tgt.color, (const T*)tgt.depth, HW, V,
                        w.ce_eps, f.s.ctrl);
-    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(kLossThreads), 0, st, f.s.ctrl, blocks, npix, w.w_rgb,
-                       w.w_depth, w.lambda, loss);
     if (npix > 0 && g.d_color) {
         hipLaunchKernelGGL(loss_grad_kernel<T>, dim3((unsigned)((npix + kLossThreads - 1) / kLossThreads)),
                            dim3(kLossThreads), 0, st, (const T*)img.color, (const T*)img.depth,
                            (const T*)img.p_target, (const T*)tgt.color, (const T*)tgt.depth, HW, V, w.w_rgb,
-                           w.w_depth, w.lambda, w.ce_eps, f.s.ctrl, (T*)g.d_color, (T*)g.d_depth,
+                           w.w_depth, w.lambda, w.ce_eps, f.s.ctrl, blocks, loss, (T*)g.d_color, (T*)g.d_depth,
                            (T*)g.d_p_target);
+    } else {
+        hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(kLossThreads), 0, st, f.s.ctrl, blocks, npix, w.w_rgb,
+                           w.w_depth, w.lambda, loss);
     }
     return hipGetLastError();
 }

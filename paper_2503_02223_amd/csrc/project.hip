@@ -13,6 +13,7 @@
 // by a scan over the sorted items; a later stable sort by tile id then yields
 // the (tile, depth, index) order with far fewer bytes than sorting 64-bit
 // (tile, depth) keys over all pairs.
+#include "adam_common.hpp"
 #include "dqo_device.hpp"
 #include "sort_common.hpp"
 
@@ -466,18 +467,134 @@ __global__ __launch_bounds__(kSlotWaves * kWave) void slot_sum_kernel(const uint
     }
 }
 
+// Chain rule of one (view, Gaussian) item from its pair-partial totals d
+// (mean2d, conic, opacity, colour, depth) to the 14 parameters (out) and to
+// the camera-frame mean (dpc); false when the item is culled.
 template <typename T>
-__global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Consts<T> cs, int64_t n,
-                                                               const T* __restrict__ params,
-                                                               const uint32_t* __restrict__ counts,
-                                                               const uint32_t* __restrict__ offsets,
-                                                               const T* __restrict__ sums, uint32_t cap,
-                                                               T* __restrict__ grads) {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= n) return;
-    T p[kParams];
+__device__ __forceinline__ bool item_backward(const DevCam<T>& c, const Consts<T>& cs, const T (&p)[kParams],
+                                              const T (&d)[kGradWords], Proj<T>& pr, T (&out)[kParams],
+                                              T (&dpc)[3]) {
+    project_item(c, cs, p, pr);
+    if (!pr.visible) return false;
+    const T* W = c.R;
+    // conic -> 2D covariance: G_S = -Ci Gc Ci with Gc = [[dA, dB/2], [dB/2, dC]]
+    const T hB = T(0.5) * d[3];
+    const T a00 = pr.A * d[2] + pr.B * hB, a01 = pr.A * hB + pr.B * d[4];
+    const T a10 = pr.B * d[2] + pr.C * hB, a11 = pr.B * hB + pr.C * d[4];
+    const T gs00 = -(a00 * pr.A + a01 * pr.B);
+    const T gs01 = -(a00 * pr.B + a01 * pr.C);
+    const T gs11 = -(a10 * pr.B + a11 * pr.C);
+    // Sigma2 = U U^T + dil I: dU = 2 G_S U
+    T dU[6];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        dU[b] = T(2) * (gs00 * pr.U[b] + gs01 * pr.U[3 + b]);
+        dU[3 + b] = T(2) * (gs01 * pr.U[b] + gs11 * pr.U[3 + b]);
+    }
+    // U = T2 M with T2 = J W, M = R diag(s)
+    const T iz = T(1) / pr.z;
+    const T j00 = c.fx * iz, j02 = -c.fx * pr.ux * iz;
+    const T j11 = c.fy * iz, j12 = -c.fy * pr.uy * iz;
+    T T2[6], Mm[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T2[k] = j00 * W[k] + j02 * W[6 + k];
+        T2[3 + k] = j11 * W[3 + k] + j12 * W[6 + k];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Mm[a * 3 + b] = pr.R[a * 3 + b] * pr.s[b];
+    T dT2[6], dM[9];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            dT2[a * 3 + k] = dU[a * 3 + 0] * Mm[k * 3 + 0] + dU[a * 3 + 1] * Mm[k * 3 + 1] +
+                             dU[a * 3 + 2] * Mm[k * 3 + 2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) dM[k * 3 + b] = T2[k] * dU[b] + T2[3 + k] * dU[3 + b];
+    // dJ = dT2 W^T (only the four nonzero entries of J matter)
+    const T dj00 = dT2[0] * W[0] + dT2[1] * W[1] + dT2[2] * W[2];
+    const T dj02 = dT2[0] * W[6] + dT2[1] * W[7] + dT2[2] * W[8];
+    const T dj11 = dT2[3] * W[3] + dT2[4] * W[4] + dT2[5] * W[5];
+    const T dj12 = dT2[3] * W[6] + dT2[4] * W[7] + dT2[5] * W[8];
+    const T iz2 = iz * iz, iz3 = iz2 * iz;
+    // A clamped ratio is a constant: J02 = -fx lim / z then depends on z alone.
+    T dpx = d[0] * c.fx * iz;
+    T dpy = d[1] * c.fy * iz;
+    T dpz = dj00 * (-c.fx * iz2) + dj11 * (-c.fy * iz2) + d[0] * (-c.fx * pr.x * iz2) +
+            d[1] * (-c.fy * pr.y * iz2) + d[9];
+    if (pr.ux_clamped) {
+        dpz += dj02 * (c.fx * pr.ux * iz2);
+    } else {
+        dpx += dj02 * (-c.fx * iz2);
+        dpz += dj02 * (T(2) * c.fx * pr.x * iz3);
+    }
+    if (pr.uy_clamped) {
+        dpz += dj12 * (c.fy * pr.uy * iz2);
+    } else {
+        dpy += dj12 * (-c.fy * iz2);
+        dpz += dj12 * (T(2) * c.fy * pr.y * iz3);
+    }
+    dpc[0] = dpx;
+    dpc[1] = dpy;
+    dpc[2] = dpz;
+    out[0] = W[0] * dpx + W[3] * dpy + W[6] * dpz;
+    out[1] = W[1] * dpx + W[4] * dpy + W[7] * dpz;
+    out[2] = W[2] * dpx + W[5] * dpy + W[8] * dpz;
+    // M = R diag(s)
+    T dR[9];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        T ds = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ds += dM[a * 3 + b] * pr.R[a * 3 + b];
+            dR[a * 3 + b] = dM[a * 3 + b] * pr.s[b];
+        }
+        out[3 + b] = ds * pr.s[b];
+    }
+    // R(q) with q normalised
+    const T w = pr.qn[0], x = pr.qn[1], y = pr.qn[2], z = pr.qn[3];
+    T dq[4];
+    dq[0] = T(2) * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = T(2) * (y * dR[1] + z * dR[2] + y * dR[3] - w * dR[5] + z * dR[6] + w * dR[7]) -
+            T(4) * x * (dR[4] + dR[8]);
+    dq[2] = T(2) * (x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7]) -
+            T(4) * y * (dR[0] + dR[8]);
+    dq[3] = T(2) * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] + x * dR[6] + y * dR[7]) -
+            T(4) * z * (dR[0] + dR[4]);
+    const T dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+    const T iq = T(1) / pr.qnorm;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[6 + k] = (dq[k] - pr.qn[k] * dot) * iq;
+    out[10] = d[5] * pr.o * (T(1) - pr.o);
+    out[11] = d[6];
+    out[12] = d[7];
+    out[13] = d[8];
+    return true;
+}
+
+template <typename T>
+__device__ __forceinline__ void project_backward_one(const Views<T>& V, const Consts<T>& cs, int64_t n, int64_t g,
+                                                     T* __restrict__ params, const uint32_t* __restrict__ counts,
+                                                     const uint32_t* __restrict__ offsets,
+                                                     const T* __restrict__ sums, uint32_t cap, T* __restrict__ grads,
+                                                     T* __restrict__ am, T* __restrict__ av, const AdamArgs<T>& aa,
+                                                     const T* s_ss, T s_isb, bool adam) {
+    T p[kParams], mm[kParams], vv[kParams];
 #pragma unroll
     for (int r = 0; r < kParams; ++r) p[r] = params[(int64_t)r * n + g];
+    if (adam) {  // the moments are loaded with the parameters, not after the gradient
+#pragma unroll
+        for (int r = 0; r < kParams; ++r) {
+            mm[r] = am[(int64_t)r * n + g];
+            vv[r] = av[(int64_t)r * n + g];
+        }
+    }
     T acc[kParams];
 #pragma unroll
     for (int r = 0; r < kParams; ++r) acc[r] = T(0);
@@ -493,108 +610,73 @@ __global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Const
         for (int k = 0; k < kGradWords; ++k) d[k] = sums[(size_t)item * kGradWords + k];
         const DevCam<T>& c = V.cam[v];
         Proj<T> pr;
-        project_item(c, cs, p, pr);
-        if (!pr.visible) continue;
-        const T* W = c.R;
-        // conic -> 2D covariance: G_S = -Ci Gc Ci with Gc = [[dA, dB/2], [dB/2, dC]]
-        const T hB = T(0.5) * d[3];
-        const T a00 = pr.A * d[2] + pr.B * hB, a01 = pr.A * hB + pr.B * d[4];
-        const T a10 = pr.B * d[2] + pr.C * hB, a11 = pr.B * hB + pr.C * d[4];
-        const T gs00 = -(a00 * pr.A + a01 * pr.B);
-        const T gs01 = -(a00 * pr.B + a01 * pr.C);
-        const T gs11 = -(a10 * pr.B + a11 * pr.C);
-        // Sigma2 = U U^T + dil I: dU = 2 G_S U
-        T dU[6];
+        T out[kParams], dpc[3];
+        if (!item_backward<T>(c, cs, p, d, pr, out, dpc)) continue;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            dU[b] = T(2) * (gs00 * pr.U[b] + gs01 * pr.U[3 + b]);
-            dU[3 + b] = T(2) * (gs01 * pr.U[b] + gs11 * pr.U[3 + b]);
-        }
-        // U = T2 M with T2 = J W, M = R diag(s)
-        const T iz = T(1) / pr.z;
-        const T j00 = c.fx * iz, j02 = -c.fx * pr.ux * iz;
-        const T j11 = c.fy * iz, j12 = -c.fy * pr.uy * iz;
-        T T2[6], Mm[9];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            T2[k] = j00 * W[k] + j02 * W[6 + k];
-            T2[3 + k] = j11 * W[3 + k] + j12 * W[6 + k];
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) Mm[a * 3 + b] = pr.R[a * 3 + b] * pr.s[b];
-        T dT2[6], dM[9];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                dT2[a * 3 + k] = dU[a * 3 + 0] * Mm[k * 3 + 0] + dU[a * 3 + 1] * Mm[k * 3 + 1] +
-                                 dU[a * 3 + 2] * Mm[k * 3 + 2];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) dM[k * 3 + b] = T2[k] * dU[b] + T2[3 + k] * dU[3 + b];
-        // dJ = dT2 W^T (only the four nonzero entries of J matter)
-        const T dj00 = dT2[0] * W[0] + dT2[1] * W[1] + dT2[2] * W[2];
-        const T dj02 = dT2[0] * W[6] + dT2[1] * W[7] + dT2[2] * W[8];
-        const T dj11 = dT2[3] * W[3] + dT2[4] * W[4] + dT2[5] * W[5];
-        const T dj12 = dT2[3] * W[6] + dT2[4] * W[7] + dT2[5] * W[8];
-        const T iz2 = iz * iz, iz3 = iz2 * iz;
-        // A clamped ratio is a constant: J02 = -fx lim / z then depends on z alone.
-        T dpx = d[0] * c.fx * iz;
-        T dpy = d[1] * c.fy * iz;
-        T dpz = dj00 * (-c.fx * iz2) + dj11 * (-c.fy * iz2) + d[0] * (-c.fx * pr.x * iz2) +
-                d[1] * (-c.fy * pr.y * iz2) + d[9];
-        if (pr.ux_clamped) {
-            dpz += dj02 * (c.fx * pr.ux * iz2);
-        } else {
-            dpx += dj02 * (-c.fx * iz2);
-            dpz += dj02 * (T(2) * c.fx * pr.x * iz3);
-        }
-        if (pr.uy_clamped) {
-            dpz += dj12 * (c.fy * pr.uy * iz2);
-        } else {
-            dpy += dj12 * (-c.fy * iz2);
-            dpz += dj12 * (T(2) * c.fy * pr.y * iz3);
-        }
-        acc[0] += W[0] * dpx + W[3] * dpy + W[6] * dpz;
-        acc[1] += W[1] * dpx + W[4] * dpy + W[7] * dpz;
-        acc[2] += W[2] * dpx + W[5] * dpy + W[8] * dpz;
-        // M = R diag(s)
-        T dR[9];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            T ds = T(0);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                ds += dM[a * 3 + b] * pr.R[a * 3 + b];
-                dR[a * 3 + b] = dM[a * 3 + b] * pr.s[b];
-            }
-            acc[3 + b] += ds * pr.s[b];
-        }
-        // R(q) with q normalised
-        const T w = pr.qn[0], x = pr.qn[1], y = pr.qn[2], z = pr.qn[3];
-        T dq[4];
-        dq[0] = T(2) * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-        dq[1] = T(2) * (y * dR[1] + z * dR[2] + y * dR[3] - w * dR[5] + z * dR[6] + w * dR[7]) -
-                T(4) * x * (dR[4] + dR[8]);
-        dq[2] = T(2) * (x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7]) -
-                T(4) * y * (dR[0] + dR[8]);
-        dq[3] = T(2) * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] + x * dR[6] + y * dR[7]) -
-                T(4) * z * (dR[0] + dR[4]);
-        const T dot = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-        const T iq = T(1) / pr.qnorm;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[6 + k] += (dq[k] - pr.qn[k] * dot) * iq;
-        acc[10] += d[5] * pr.o * (T(1) - pr.o);
-        acc[11] += d[6];
-        acc[12] += d[7];
-        acc[13] += d[8];
+        for (int r = 0; r < kParams; ++r) acc[r] += out[r];
     }
+    if (adam) {
+        if (grads) {
 #pragma unroll
-    for (int r = 0; r < kParams; ++r) grads[(int64_t)r * n + g] = acc[r];
+            for (int r = 0; r < kParams; ++r) grads[(int64_t)r * n + g] = acc[r];
+        }
+#pragma unroll
+        for (int r = 0; r < kParams; ++r) {
+            const int64_t i = (int64_t)r * n + g;
+            T pp = p[r];
+            adam_one<T>(pp, acc[r], mm[r], vv[r], s_ss[r], s_isb, aa);
+            params[i] = pp;
+            am[i] = mm[r];
+            av[i] = vv[r];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kParams; ++r) grads[(int64_t)r * n + g] = acc[r];
+    }
 }
+
+// Per-Gaussian gradients from the per-item totals (chain rule through the
+// projection, summed over the views).  With moment buffers given, the Adam
+// update of dqo_adam_step_counted is applied at once to params, m and v, and
+// the last workgroup to finish advances the device step.  One kernel serves
+// both uses (a run-time switch), so the gradient is the same compiled
+// arithmetic whether or not Adam follows.
+template <typename T>
+__global__ __launch_bounds__(256) void project_backward_kernel(Views<T> V, Consts<T> cs, int64_t n,
+                                                               T* __restrict__ params,
+                                                               const uint32_t* __restrict__ counts,
+                                                               const uint32_t* __restrict__ offsets,
+                                                               const T* __restrict__ sums, uint32_t cap,
+                                                               T* __restrict__ grads, T* __restrict__ am,
+                                                               T* __restrict__ av, AdamArgs<T> aa,
+                                                               int64_t* d_step, uint32_t* done) {
+    __shared__ T s_ss[kParams];
+    __shared__ T s_isb;
+    const bool adam = am != nullptr;  // uniform over the grid
+    if (adam) {
+        if (threadIdx.x < kParams) {
+            T isb;
+            device_step_factors<T>(aa, *d_step, threadIdx.x, s_ss[threadIdx.x], isb);
+            if (threadIdx.x == 0) s_isb = isb;
+        }
+        __syncthreads();
+    }
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g < n) project_backward_one<T>(V, cs, n, g, params, counts, offsets, sums, cap, grads, am, av, aa, s_ss, s_isb,
+                                       adam);
+    if (adam) {
+        // Every workgroup read the step before it counts itself done: the last
+        // one advances it and re-arms the counter.
+        if (threadIdx.x == 0) {
+            __threadfence();
+            if (atomicAdd(done, 1u) == gridDim.x - 1u) {
+                atomicAdd((unsigned long long*)d_step, 1ull);
+                atomicExch(done, 0u);
+            }
+        }
+    }
+}
+
 
 template <typename T>
 hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads, hipStream_t st) {
@@ -603,9 +685,119 @@ hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads,
     hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
                        dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
                        (const T*)f.s.partials, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
-    hipLaunchKernelGGL(project_backward_kernel<T>, dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st, f.views,
-                       f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.sums,
-                       (uint32_t)f.s.capacity, grads);
+    hipLaunchKernelGGL((project_backward_kernel<T>), dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st,
+                       f.views, f.consts, f.n, const_cast<T*>(params), f.s.counts, f.s.offsets, (const T*)f.s.sums,
+                       (uint32_t)f.s.capacity, grads, (T*)nullptr, (T*)nullptr, AdamArgs<T>{}, (int64_t*)nullptr,
+                       (uint32_t*)nullptr);
+    return hipGetLastError();
+}
+
+// Camera-pose gradient of every view (tracking): each (view, Gaussian) item
+// contributes, through the rigid-motion identity (moving the camera renders
+// what moving every Gaussian by the inverse world motion renders),
+// dL/dtau += g and dL/dw += p x g + R dL/dphi, where g is the gradient of the
+// camera-frame mean p and phi a world-frame left rotation of the item's
+// quaternion (s, u): dL/dphi = (-u dL/ds + s dL/du + u x dL/du) / 2.  Blocks
+// reduce in a fixed order (shuffle tree, then waves in order) into per-block
+// partials in double precision; pose_final_kernel sums them in block order.
+__device__ __forceinline__ double pose_wave_sum(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d);
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pose_grad_kernel(Views<T> V, Consts<T> cs, int64_t n,
+                                                        const T* __restrict__ params,
+                                                        const uint32_t* __restrict__ counts,
+                                                        const uint32_t* __restrict__ offsets,
+                                                        const T* __restrict__ sums, uint32_t cap,
+                                                        double* __restrict__ partials) {
+    __shared__ double s_w[4][6];
+    const int v = blockIdx.y;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double pose[6] = {0, 0, 0, 0, 0, 0};
+    const DevCam<T>& c = V.cam[v];
+    if (g < n && g >= c.seg_lo && g < c.seg_hi) {
+        const int64_t item = (int64_t)v * n + g;
+        const uint32_t cnt = counts[item];
+        const uint32_t off = offsets[item];
+        if (cnt > 0 && (uint64_t)off + cnt <= cap) {
+            T p[kParams], d[kGradWords], out[kParams], dpc[3];
+#pragma unroll
+            for (int r = 0; r < kParams; ++r) p[r] = params[(int64_t)r * n + g];
+#pragma unroll
+            for (int k = 0; k < kGradWords; ++k) d[k] = sums[(size_t)item * kGradWords + k];
+            Proj<T> pr;
+            if (item_backward<T>(c, cs, p, d, pr, out, dpc)) {
+                const T qs = p[6], u0 = p[7], u1 = p[8], u2 = p[9];
+                const T ds = out[6], du0 = out[7], du1 = out[8], du2 = out[9];
+                const T f0 = T(0.5) * (-u0 * ds + qs * du0 + (u1 * du2 - u2 * du1));
+                const T f1 = T(0.5) * (-u1 * ds + qs * du1 + (u2 * du0 - u0 * du2));
+                const T f2 = T(0.5) * (-u2 * ds + qs * du2 + (u0 * du1 - u1 * du0));
+                const T* R = c.R;
+                pose[0] = (double)(pr.y * dpc[2] - pr.z * dpc[1] + R[0] * f0 + R[1] * f1 + R[2] * f2);
+                pose[1] = (double)(pr.z * dpc[0] - pr.x * dpc[2] + R[3] * f0 + R[4] * f1 + R[5] * f2);
+                pose[2] = (double)(pr.x * dpc[1] - pr.y * dpc[0] + R[6] * f0 + R[7] * f1 + R[8] * f2);
+                pose[3] = (double)dpc[0];
+                pose[4] = (double)dpc[1];
+                pose[5] = (double)dpc[2];
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double t = pose_wave_sum(pose[k]);
+        if (lane == 0) s_w[wave][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const double t = ((s_w[0][threadIdx.x] + s_w[1][threadIdx.x]) + s_w[2][threadIdx.x]) + s_w[3][threadIdx.x];
+        partials[((size_t)v * gridDim.x + blockIdx.x) * 6 + threadIdx.x] = t;
+    }
+}
+
+// One wavefront per (view, component): lane l sums blocks l, l + 64, ... in
+// order, then a fixed shuffle tree.
+__global__ __launch_bounds__(384) void pose_final_kernel(const double* __restrict__ partials, int nblocks,
+                                                         double* __restrict__ out) {
+    const int v = blockIdx.x, k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double a = 0.0;
+    for (int b = lane; b < nblocks; b += 64) a += partials[((size_t)v * nblocks + b) * 6 + k];
+    a = pose_wave_sum(a);
+    if (lane == 0) out[v * 6 + k] = a;
+}
+
+template <typename T>
+hipError_t launch_pose_backward(const Frame<T>& f, const T* params, double* pose, hipStream_t st) {
+    const int V = f.views.n_views;
+    if (f.n == 0) return launch_zero_words((uint32_t*)pose, 12 * (int64_t)V, st);
+    const int64_t M = f.s.items;
+    hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
+                       dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
+                       (const T*)f.s.partials, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
+    const int blocks = (int)((f.n + 255) / 256);
+    hipLaunchKernelGGL(pose_grad_kernel<T>, dim3((unsigned)blocks, (unsigned)V), dim3(256), 0, st, f.views, f.consts,
+                       f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.sums, (uint32_t)f.s.capacity,
+                       f.s.pose_partials);
+    hipLaunchKernelGGL(pose_final_kernel, dim3((unsigned)V), dim3(384), 0, st, (const double*)f.s.pose_partials,
+                       blocks, pose);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_project_backward_adam(const Frame<T>& f, T* params, T* grads, T* m, T* v, const dqo_adam& hp,
+                                        int64_t* d_step, hipStream_t st) {
+    if (f.n == 0) return launch_adam<T>(params, grads, m, v, 0, hp, 1, d_step, st, kParams);  // advances the step
+    const int64_t M = f.s.items;
+    hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
+                       dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
+                       (const T*)f.s.partials, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
+    hipLaunchKernelGGL((project_backward_kernel<T>), dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st,
+                       f.views, f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.sums,
+                       (uint32_t)f.s.capacity, grads, m, v, make_adam_args<T>(hp, 1), d_step,
+                       &f.s.ctrl->counters[kCounterAdam]);
     return hipGetLastError();
 }
 
@@ -644,5 +836,11 @@ template hipError_t launch_project_bin<float>(const Frame<float>&, const float*,
 template hipError_t launch_project_bin<double>(const Frame<double>&, const double*, const int32_t*, hipStream_t);
 template hipError_t launch_project_backward<float>(const Frame<float>&, const float*, float*, hipStream_t);
 template hipError_t launch_project_backward<double>(const Frame<double>&, const double*, double*, hipStream_t);
+template hipError_t launch_pose_backward<float>(const Frame<float>&, const float*, double*, hipStream_t);
+template hipError_t launch_pose_backward<double>(const Frame<double>&, const double*, double*, hipStream_t);
+template hipError_t launch_project_backward_adam<float>(const Frame<float>&, float*, float*, float*, float*,
+                                                        const dqo_adam&, int64_t*, hipStream_t);
+template hipError_t launch_project_backward_adam<double>(const Frame<double>&, double*, double*, double*, double*,
+                                                         const dqo_adam&, int64_t*, hipStream_t);
 
 }  // namespace dqo

@@ -83,9 +83,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
         total += c;
     }
     const uint32_t dstart = block_exclusive_scan_256(total, s_tmp);
-    const uint32_t gdig = block_exclusive_scan_256(ghist[t], s_tmp);
+    const uint32_t gcount = ghist[t];
+    const uint32_t gdig = block_exclusive_scan_256(gcount, s_tmp);
     s_dstart[t] = dstart;
-    const uint32_t excl = lookback_exclusive(lb + t, kRadixBins, (int)bid, total, epoch, &ctrl->status);
+    // A digit that no key has anywhere needs no chain: every block skips it.
+    const uint32_t excl =
+        gcount ? lookback_exclusive(lb + t, kRadixBins, (int)bid, total, epoch, &ctrl->status) : 0u;
     s_gbase[t] = gdig + excl;
     __syncthreads();
 

@@ -97,3 +97,34 @@ def test_autotune_picks_a_measured_tile(oracle):
     assert best in ((8, 8), (16, 16))
     assert set(table) == {"8x8", "16x16"} and all(v > 0 for v in table.values())
     assert table[f"{best[0]}x{best[1]}"] == min(table.values())
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_fused_backward_adam_equals_separate_calls(oracle, dtype):
+    """dqo_project_backward_adam against dqo_project_backward followed by
+    dqo_adam_step_counted: bitwise equal parameters, moments and gradients
+    over several steps, the step counter advanced once per call."""
+    sc = scenes.single_view_scene(seed=6, n=2000)
+    cam = sc["cams"][0]
+    tg = oracle.render(scenes.perturb(sc["params"], 7), sc["ids"], cam, K=3)
+    targets = dict(color=to_dev(tg["C"][None], dtype), depth=to_dev(tg["D"][None], dtype),
+                   id=torch.tensor(oracle.id_map(tg["P"], tg["Tf"])[None], dtype=torch.int32, device="cuda"))
+    ids = torch.tensor(sc["ids"], device="cuda")
+    p = to_dev(sc["params"], dtype)
+    sep = B.Trainer(p.clone(), ids, sc["cams"], 3, targets, fused=False)
+    fus = B.Trainer(p.clone(), ids, sc["cams"], 3, targets, fused=True)
+    grads_f = torch.empty_like(p)
+    for i in range(4):
+        sep.step()
+        f = fus.r.frame
+        f.project_cull_bin(fus.params, fus.ids)
+        f.sort()
+        f.render_forward(fus.img)
+        f.object_loss(fus.img, fus.targets, fus.grads_img, fus.loss)
+        f.render_backward(fus.img, fus.grads_img)
+        f.project_backward_adam(fus.params, fus.m, fus.v, fus.lrs, fus.d_step, grads=grads_f)
+        torch.cuda.synchronize()
+        assert torch.equal(sep.grads, grads_f), f"gradients, step {i}"
+        assert torch.equal(sep.params, fus.params), f"params, step {i}"
+        assert torch.equal(sep.m, fus.m) and torch.equal(sep.v, fus.v), f"moments, step {i}"
+        assert int(sep.d_step.item()) == i + 1 and int(fus.d_step.item()) == i + 1
