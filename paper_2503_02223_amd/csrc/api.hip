@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "ctx.hpp"
 #include "dqo_device.hpp"
 
@@ -153,6 +155,11 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.pair_blocks = g.pair_blocks;
     s.pair_passes = g.pair_passes;
     s.pair_first_buf = g.pair_first_buf;
+    // One histogram copy per 64 producer workgroups (up to kHistCopies): enough
+    // to spread the atomics, few enough for the radix passes to sum cheaply.
+    const int64_t proj_blocks = (g.items + 256 * kProjItems - 1) / (256 * kProjItems);
+    s.hist_copies_depth = (int)std::max<int64_t>(1, std::min<int64_t>(kHistCopies, proj_blocks / 64));
+    s.hist_copies_pair = (int)std::max<int64_t>(1, std::min<int64_t>(kHistCopies, g.scan_blocks / 64));
     return s;
 }
 

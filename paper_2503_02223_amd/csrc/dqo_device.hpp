@@ -44,6 +44,8 @@ constexpr int kCounterScan = 4;
 constexpr int kCounterPair = 5;    // + pass
 constexpr int kCounterAdam = 12;   // workgroups done in the fused project-backward + Adam
 constexpr int kNumCounters = 16;
+constexpr int kHistCopies = 16;
+constexpr int kProjItems = 4;      // items per thread of the projection kernel
 
 // Control block at the start of DQO_BUF_CONTROL.
 struct Ctrl {
@@ -52,8 +54,11 @@ struct Ctrl {
     uint32_t num_pairs;   // total pairs requested (may exceed the capacity)
     uint32_t n_valid;     // valid-depth pixel count of the last loss
     uint32_t counters[kNumCounters];
-    uint32_t hist_depth[kMaxDepthPasses][kRadixBins];
-    uint32_t hist_pair[kMaxPairPasses][kRadixBins];
+    // Digit histograms of every radix pass, in kHistCopies copies: a workgroup
+    // adds its counts to copy (block index mod kHistCopies), which spreads the
+    // atomics over more addresses; a radix pass sums the copies of its digit.
+    uint32_t hist_depth[kHistCopies][kMaxDepthPasses][kRadixBins];
+    uint32_t hist_pair[kHistCopies][kMaxPairPasses][kRadixBins];
     double loss_partials[kLossBlocks][4];
 };
 
@@ -230,6 +235,8 @@ struct StatePtrs {
     int pair_blocks;      // radix blocks over capacity
     int pair_passes;
     int pair_first_buf;   // buffer emission writes into so the sort ends in buffer 0
+    int hist_copies_depth;  // histogram copies in use (1..kHistCopies), by producer workgroup count
+    int hist_copies_pair;
 };
 
 template <typename T>

@@ -23,8 +23,10 @@ __global__ void prep_kernel(Ctrl* ctrl) {
     const int t = threadIdx.x;
     if (t == 0) ctrl->epoch = ctrl->epoch + 1u;
     if (t < kNumCounters) ctrl->counters[t] = 0u;
-    for (int p = 0; p < kMaxDepthPasses; ++p) ctrl->hist_depth[p][t] = 0u;
-    for (int p = 0; p < kMaxPairPasses; ++p) ctrl->hist_pair[p][t] = 0u;
+    for (int c = 0; c < kHistCopies; ++c) {
+        for (int p = 0; p < kMaxDepthPasses; ++p) ctrl->hist_depth[c][p][t] = 0u;
+        for (int p = 0; p < kMaxPairPasses; ++p) ctrl->hist_pair[c][p][t] = 0u;
+    }
     if (t == 0) ctrl->num_pairs = 0u;
 }
 
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
                                                       T* __restrict__ splats, short4* __restrict__ rects,
                                                       uint32_t* __restrict__ counts, uint32_t* __restrict__ dkeys,
                                                       uint32_t* __restrict__ dvals, uint32_t* __restrict__ ranges,
-                                                      int64_t range_words, Ctrl* ctrl) {
+                                                      int64_t range_words, int copies, Ctrl* ctrl) {
     __shared__ uint32_t s_hist[kMaxDepthPasses][kRadixBins];
     const int tid = threadIdx.x;
     // Tile ranges start empty: the sort writes only the bounds of tiles that hold pairs.
@@ -120,57 +122,61 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
 #pragma unroll
     for (int p = 0; p < kMaxDepthPasses; ++p) s_hist[p][tid] = 0u;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
-    if (i < M) {
-        const int v = (int)(i / n);
-        const int64_t g = i - (int64_t)v * n;
-        const bool in_seg = g >= V.cam[v].seg_lo && g < V.cam[v].seg_hi;
-        T p[kParams];
-        bool finite = true;
+    // kProjItems items per thread (coalesced per item step): fewer workgroups
+    // flush histogram counts to the shared copies.
+    for (int it = 0; it < kProjItems; ++it) {
+        const int64_t i = ((int64_t)blockIdx.x * kProjItems + it) * 256 + tid;
+        if (i < M) {
+            const int v = (int)(i / n);
+            const int64_t g = i - (int64_t)v * n;
+            const bool in_seg = g >= V.cam[v].seg_lo && g < V.cam[v].seg_hi;
+            T p[kParams];
+            bool finite = true;
 #pragma unroll
-        for (int r = 0; r < kParams; ++r) {
-            p[r] = in_seg ? params[(int64_t)r * n + g] : T(0);
-            finite = finite && isfinite(p[r]);
-        }
-        if (!finite) atomicOr(&ctrl->status, (uint32_t)DQO_STATUS_NONFINITE);
-        Proj<T> pr;
-        pr.visible = false;
-        if (finite && in_seg) project_item(V.cam[v], cs, p, pr);
-        uint32_t cnt = 0;
-        short4 rc = make_short4(0, 0, -1, -1);
-        T w[kSplatWords];
-#pragma unroll
-        for (int k = 0; k < kSplatWords; ++k) w[k] = T(0);
-        if (pr.visible) {
-            const T ex = T(3) * sqrt(pr.s00), ey = T(3) * sqrt(pr.s11);
-            T x0 = floor((pr.mx - ex) / T(V.tile_w)), x1 = floor((pr.mx + ex) / T(V.tile_w));
-            T y0 = floor((pr.my - ey) / T(V.tile_h)), y1 = floor((pr.my + ey) / T(V.tile_h));
-            x0 = max(x0, T(0));
-            y0 = max(y0, T(0));
-            x1 = min(x1, T(V.tiles_x - 1));
-            y1 = min(y1, T(V.tiles_y - 1));
-            if (x0 <= x1 && y0 <= y1) {
-                rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
-                cnt = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
+            for (int r = 0; r < kParams; ++r) {
+                p[r] = in_seg ? params[(int64_t)r * n + g] : T(0);
+                finite = finite && isfinite(p[r]);
             }
-            w[0] = pr.mx; w[1] = pr.my; w[2] = pr.A; w[3] = pr.B; w[4] = pr.C; w[5] = pr.o; w[6] = pr.z;
-            w[7] = id_to_word<T>(ids[g]);
-            w[8] = p[11]; w[9] = p[12]; w[10] = p[13];
-        }
-        store_splat<T>(splats + i * kSplatWords, w);
-        rects[i] = rc;
-        counts[i] = cnt;
-        const uint32_t key = pr.visible ? __float_as_uint((float)pr.z) : 0xffffffffu;
-        dkeys[i] = key;
-        dvals[i] = (uint32_t)i;
+            if (!finite) atomicOr(&ctrl->status, (uint32_t)DQO_STATUS_NONFINITE);
+            Proj<T> pr;
+            pr.visible = false;
+            if (finite && in_seg) project_item(V.cam[v], cs, p, pr);
+            uint32_t cnt = 0;
+            short4 rc = make_short4(0, 0, -1, -1);
+            T w[kSplatWords];
 #pragma unroll
-        for (int ps = 0; ps < kMaxDepthPasses; ++ps) atomicAdd(&s_hist[ps][(key >> (8 * ps)) & 255u], 1u);
+            for (int k = 0; k < kSplatWords; ++k) w[k] = T(0);
+            if (pr.visible) {
+                const T ex = T(3) * sqrt(pr.s00), ey = T(3) * sqrt(pr.s11);
+                T x0 = floor((pr.mx - ex) / T(V.tile_w)), x1 = floor((pr.mx + ex) / T(V.tile_w));
+                T y0 = floor((pr.my - ey) / T(V.tile_h)), y1 = floor((pr.my + ey) / T(V.tile_h));
+                x0 = max(x0, T(0));
+                y0 = max(y0, T(0));
+                x1 = min(x1, T(V.tiles_x - 1));
+                y1 = min(y1, T(V.tiles_y - 1));
+                if (x0 <= x1 && y0 <= y1) {
+                    rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
+                    cnt = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
+                }
+                w[0] = pr.mx; w[1] = pr.my; w[2] = pr.A; w[3] = pr.B; w[4] = pr.C; w[5] = pr.o; w[6] = pr.z;
+                w[7] = id_to_word<T>(ids[g]);
+                w[8] = p[11]; w[9] = p[12]; w[10] = p[13];
+            }
+            store_splat<T>(splats + i * kSplatWords, w);
+            rects[i] = rc;
+            counts[i] = cnt;
+            const uint32_t key = pr.visible ? __float_as_uint((float)pr.z) : 0xffffffffu;
+            dkeys[i] = key;
+            dvals[i] = (uint32_t)i;
+#pragma unroll
+            for (int ps = 0; ps < kMaxDepthPasses; ++ps) atomicAdd(&s_hist[ps][(key >> (8 * ps)) & 255u], 1u);
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int ps = 0; ps < kMaxDepthPasses; ++ps) {
         const uint32_t c = s_hist[ps][tid];
-        if (c) atomicAdd(&ctrl->hist_depth[ps][tid], c);
+        if (c) atomicAdd(&ctrl->hist_depth[blockIdx.x % copies][ps][tid], c);
     }
 }
 
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
 __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts, const short4* __restrict__ rects,
     uint32_t* __restrict__ offsets, uint32_t* __restrict__ pkeys, uint32_t* __restrict__ pvals, uint32_t M,
-    uint32_t cap, int64_t n, int tiles_x, int tiles_per_view, int pair_passes, uint64_t* lb, Ctrl* ctrl) {
+    uint32_t cap, int64_t n, int tiles_x, int tiles_per_view, int pair_passes, int copies, uint64_t* lb, Ctrl* ctrl) {
     __shared__ uint32_t s_incl[kScanTile];
     __shared__ uint32_t s_rec[kScanTile];
     __shared__ uint32_t s_tbase[kScanTile];
@@ -299,7 +305,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     if (tid < kRadixBins)
         for (int p = 0; p < pair_passes; ++p) {
             const uint32_t h = s_hist[p][tid];
-            if (h) atomicAdd(&ctrl->hist_pair[p][tid], h);
+            if (h) atomicAdd(&ctrl->hist_pair[blockIdx.x % copies][p][tid], h);
         }
 }
 
@@ -310,14 +316,15 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
     const int64_t M = s.items;
     const int64_t range_words = 2 * (int64_t)f.views.tiles_per_view * f.views.n_views;
     if (M == 0) return launch_zero_words(s.ranges, range_words, st);
-    hipLaunchKernelGGL(project_kernel<T>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, f.views, f.consts,
+    hipLaunchKernelGGL(project_kernel<T>, dim3((unsigned)((M + 256 * kProjItems - 1) / (256 * kProjItems))), dim3(256),
+                       0, st, f.views, f.consts,
                        f.n, M, params, ids, (T*)s.splats, s.rects, s.counts, s.depth_keys[0], s.depth_vals[0],
-                       s.ranges, range_words, s.ctrl);
+                       s.ranges, range_words, s.hist_copies_depth, s.ctrl);
     int src = 0;
     for (int p = 0; p < kMaxDepthPasses; ++p) {
         hipError_t e = launch_radix_pass(s.depth_keys[src], s.depth_vals[src], s.depth_keys[src ^ 1],
                                          s.depth_vals[src ^ 1], nullptr, (uint32_t)M, p * kRadixBits,
-                                         s.ctrl->hist_depth[p],
+                                         &s.ctrl->hist_depth[0][p][0], kMaxDepthPasses * kRadixBins, s.hist_copies_depth,
                                          s.lb_depth + (size_t)p * s.depth_blocks * kRadixBins,
                                          &s.ctrl->counters[kCounterDepth + p], s.ctrl, st, kDepthIpt);
         if (e != hipSuccess) return e;
@@ -327,7 +334,7 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
     hipLaunchKernelGGL(scan_emit_kernel, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st, s.depth_vals[0],
                        s.counts, s.rects, s.offsets, s.pair_keys[pf], s.pair_vals[pf], (uint32_t)M,
                        (uint32_t)s.capacity, f.n, f.views.tiles_x, f.views.tiles_per_view, s.pair_passes,
-                       s.lb_scan, s.ctrl);
+                       s.hist_copies_pair, s.lb_scan, s.ctrl);
     return hipGetLastError();
 }
 

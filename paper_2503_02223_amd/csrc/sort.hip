@@ -18,7 +18,8 @@ template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
-    const uint32_t* __restrict__ ghist, uint64_t* lb, uint32_t* counter, Ctrl* ctrl) {
+    const uint32_t* __restrict__ ghist, int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter,
+    Ctrl* ctrl) {
     constexpr int kTile = kSortThreads * IPT;
     __shared__ uint32_t s_keys[kTile];
     __shared__ uint32_t s_vals[kTile];
@@ -83,7 +84,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
         total += c;
     }
     const uint32_t dstart = block_exclusive_scan_256(total, s_tmp);
-    const uint32_t gcount = ghist[t];
+    uint32_t gcount = 0;  // the digit's count over all keys: the sum of the histogram copies
+    for (int c = 0; c < hist_copies; ++c) gcount += ghist[c * hist_stride + t];
     const uint32_t gdig = block_exclusive_scan_256(gcount, s_tmp);
     s_dstart[t] = dstart;
     // A digit that no key has anywhere needs no chain: every block skips it.
@@ -169,18 +171,19 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
 
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
-                             uint64_t* lb, uint32_t* counter, Ctrl* ctrl, hipStream_t st, int ipt) {
+                             int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter, Ctrl* ctrl,
+                             hipStream_t st, int ipt) {
     if (n_host == 0) return hipSuccess;
     const int blocks = (int)((n_host + kSortThreads * ipt - 1) / (kSortThreads * ipt));
     if (ipt == 4)
         hipLaunchKernelGGL(radix_pass_kernel<4>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                           n_dev, n_host, shift, ghist, lb, counter, ctrl);
+                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
     else if (ipt == 8)
         hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                           n_dev, n_host, shift, ghist, lb, counter, ctrl);
+                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
     else if (ipt == 16)
         hipLaunchKernelGGL(radix_pass_kernel<16>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                           n_dev, n_host, shift, ghist, lb, counter, ctrl);
+                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -193,7 +196,7 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
     for (int p = 0; p < s.pair_passes; ++p) {
         hipError_t e = launch_radix_pass(s.pair_keys[src], s.pair_vals[src], s.pair_keys[src ^ 1],
                                          s.pair_vals[src ^ 1], n_dev, cap, p * kRadixBits,
-                                         s.ctrl->hist_pair[p], s.lb_pair + (size_t)p * s.pair_blocks * kRadixBins,
+                                         &s.ctrl->hist_pair[0][p][0], kMaxPairPasses * kRadixBins, s.hist_copies_pair, s.lb_pair + (size_t)p * s.pair_blocks * kRadixBins,
                                          &s.ctrl->counters[kCounterPair + p], s.ctrl, st, kPairIpt);
         if (e != hipSuccess) return e;
         src ^= 1;

@@ -33,6 +33,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
-                             uint64_t* lb, uint32_t* counter, Ctrl* ctrl, hipStream_t st, int ipt);
+                             int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter, Ctrl* ctrl,
+                             hipStream_t st, int ipt);
 
 }  // namespace dqo
