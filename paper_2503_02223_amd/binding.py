@@ -580,15 +580,19 @@ class RasterizeFunction(torch.autograd.Function):
         ctx.rasterizer = rasterizer
         ctx.generation = rasterizer.generation
         ctx.ids = ids
-        ctx.img = img
         ctx.want_probs = want_probs and rasterizer.K > 0
-        ctx.save_for_backward(p)
         probs = img["probs"] if ctx.want_probs else img["color"].new_zeros(0)
+        # Outputs are saved through save_for_backward: holding them on ctx would
+        # make a reference cycle (output -> grad_fn -> ctx -> output) that keeps
+        # every iteration's images alive until a cyclic garbage collection.
+        ctx.save_for_backward(p, img["color"], img["depth"], img["t_final"])
+        ctx.last = img["last"]   # not an output
         return img["color"], img["depth"], img["t_final"], probs
 
     @staticmethod
     def backward(ctx, d_color, d_depth, d_t_final, d_probs):
-        (p,) = ctx.saved_tensors
+        p, color, depth, t_final = ctx.saved_tensors
+        img = dict(color=color, depth=depth, t_final=t_final, last=ctx.last)
         r: Rasterizer = ctx.rasterizer
         if r.generation != ctx.generation:
             # Another forward reused the pair list since: rebuild it from the saved
@@ -597,11 +601,10 @@ class RasterizeFunction(torch.autograd.Function):
             r.bin(p, ctx.ids)
             ctx.generation = r.generation
         z = lambda t, like: (t.contiguous() if t is not None else torch.zeros_like(like))
-        grads = dict(d_color=z(d_color, ctx.img["color"]), d_depth=z(d_depth, ctx.img["depth"]),
-                     d_t_final=z(d_t_final, ctx.img["t_final"]))
+        grads = dict(d_color=z(d_color, color), d_depth=z(d_depth, depth), d_t_final=z(d_t_final, t_final))
         if ctx.want_probs and d_probs is not None:
             grads["d_probs"] = d_probs.contiguous()
-        g = r.backward(p, ctx.img, grads)
+        g = r.backward(p, img, grads)
         return g, None, None, None
 
 

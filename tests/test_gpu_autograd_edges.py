@@ -179,3 +179,26 @@ def test_nonfinite_parameters_are_flagged_and_culled(oracle):
     q[2, 5] = q[2, 17] = -5.0  # behind the camera: culled like the non-finite ones
     ref = oracle.render(q, sc["ids"], sc["cams"][0], K=3)
     close(img["color"][0].cpu().numpy(), ref["C"], FWD_RTOL, unambiguous(ref), "colour without the bad Gaussians")
+
+
+def test_autograd_iterations_hold_no_memory():
+    """Repeated forward + backward through the autograd Function keeps the
+    allocated memory constant: no iteration's images stay alive."""
+    import gc
+    sc = scenes.single_view_scene(seed=2, n=2000)
+    r = B.Rasterizer(sc["cams"], 2000, 3)
+    ids = torch.tensor(sc["ids"], device="cuda")
+    p = to_dev(sc["params"]).requires_grad_(True)
+    gc.disable()          # a reference cycle would only be freed by the cyclic collector
+    try:
+        seen = []
+        for _ in range(6):
+            C, D, T, P = B.rasterize(p, ids, r)
+            (C.sum() + D.sum() + P.sum()).backward()
+            p.grad = None
+            del C, D, T, P
+            torch.cuda.synchronize()
+            seen.append(torch.cuda.memory_allocated())
+    finally:
+        gc.enable()
+    assert seen[-1] == seen[1], seen
