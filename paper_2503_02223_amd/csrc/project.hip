@@ -368,10 +368,6 @@ hipError_t launch_zero_partials(const StatePtrs& s, hipStream_t st) {
 template hipError_t launch_zero_partials<float>(const StatePtrs&, hipStream_t);
 template hipError_t launch_zero_partials<double>(const StatePtrs&, hipStream_t);
 
-// Sum of an item's cnt consecutive slots of kGradWords values, added in slot
-// order.  The loads of kSlotBatch slots are issued before any of them is added,
-// so a Gaussian spanning many tiles costs one memory latency per batch instead
-// of one per slot (such Gaussians set the kernel's duration).
 // Per-item totals of the pair partials.  An item's (tile, Gaussian)
 // partials occupy consecutive slots, and items that are consecutive in depth
 // order occupy consecutive slot ranges, so one wavefront takes 64 consecutive
