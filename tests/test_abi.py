@@ -128,3 +128,41 @@ def test_segments_validated_on_host():
                         segments=ctypes.cast(arr, ctypes.POINTER(ctypes.c_int64)))
         rc = B.lib().dqo_state_layout(ctx.h, ctypes.byref(d), cams, ctypes.byref(L))
         assert (rc == 0) == ok, seg
+
+
+def test_new_entry_points_validate_on_host():
+    """Incremental update, quadric refinement, pose gradient, fused backward +
+    Adam and association: bad arguments are rejected with EINVAL and a
+    message, before anything is launched."""
+    ctx = B.Context()
+    L = B.lib()
+    sc = scenes.single_view_scene(n=10)
+    cams = B.make_cameras(sc["cams"])
+    d = B.FrameDesc(n=10, n_views=1, K=3, pair_capacity=100, dtype=B.F32)
+    fake = ctypes.c_void_p(1)   # never dereferenced: validation fails first
+    cfg = B.IncrementCfg(**B.INCREMENT_DEFAULTS)
+    img, tgt = B.Images(), B.Targets()
+    assert L.dqo_incremental_masks(ctx.h, ctypes.byref(d), cams, ctypes.byref(img), ctypes.byref(tgt),
+                                   ctypes.byref(cfg), fake, fake, None) == B.EINVAL
+    bad = B.IncrementCfg(**{**B.INCREMENT_DEFAULTS, "og_opacity": 1.0})
+    assert L.dqo_densify(ctx.h, ctypes.byref(d), cams, ctypes.byref(B.Targets(fake, fake, fake)), fake,
+                         ctypes.byref(bad), 0, 10, fake, fake, fake, None) == B.EINVAL
+    assert b"opacit" in L.dqo_last_error(ctx.h)
+    assert L.dqo_densify(ctx.h, ctypes.byref(d), cams, ctypes.byref(B.Targets(fake, fake, fake)), fake,
+                         ctypes.byref(cfg), 10, 5, fake, fake, fake, None) == B.EINVAL   # n_cap < n_old
+    rc = B.RefineCfg(**{**B.REFINE_DEFAULTS, "iterations": -1})
+    assert L.dqo_refine_quadrics(ctx.h, 1, 1, fake, fake, fake, 1, fake, None, None, ctypes.byref(rc), fake, fake,
+                                 fake, None, fake, None, None) == B.EINVAL
+    rc = B.RefineCfg(**{**B.REFINE_DEFAULTS, "eps": 0.0})
+    assert L.dqo_refine_quadrics(ctx.h, 1, 1, fake, fake, fake, 1, fake, None, None, ctypes.byref(rc), fake, fake,
+                                 fake, None, fake, None, None) == B.EINVAL
+    assert L.dqo_quadric_iou_grad(ctx.h, 1, 1, fake, fake, fake, 1, fake, None, None, None, None, None,
+                                  None) == B.EINVAL
+    assert L.dqo_pose_backward(ctx.h, ctypes.byref(d), cams, fake, fake, None, None) == B.EINVAL
+    hp = B.AdamParams()
+    hp.beta1, hp.beta2, hp.eps = 0.9, 1.0, 1e-15      # beta2 outside [0, 1)
+    assert L.dqo_project_backward_adam(ctx.h, ctypes.byref(d), cams, fake, fake, fake, fake, ctypes.byref(hp),
+                                       fake, None, None) == B.EINVAL
+    assert L.dqo_associate(ctx.h, 1, fake, fake, fake, 2, fake, fake, 0, fake, fake, 0.3, fake, fake, None,
+                           None) == B.EINVAL           # detections without frames
+    assert L.dqo_quadric_distance(ctx.h, 1, fake, fake, fake, 1, fake, fake, fake, -1.0, fake, None) == B.EINVAL
