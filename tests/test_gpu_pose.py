@@ -97,3 +97,38 @@ def test_pose_descent_reduces_the_loss_on_the_device(oracle):
         cam = c
         w, tau = -0.001 * np.sign(g[:3]), -0.002 * np.sign(g[3:])
     assert min(losses[-5:]) < 0.8 * losses[0]
+
+
+def test_pose_gradient_full_size_descent_direction():
+    """At the tracking workload's size (200k Gaussians, 640x480) the device
+    pose gradient is a descent direction of the device loss: a small step
+    along -g lowers it and a step along +g raises it."""
+    sc = scenes.slam_view_scene(seed=0, n=200_000)
+    true_cam = sc["cams"][0]
+    n, K = sc["params"].shape[1], sc["K"]
+    p = to_dev(sc["params"])
+    ids = torch.tensor(sc["ids"], device="cuda")
+    r0 = B.Rasterizer([true_cam], n, K, ctx=B.Context(tile_w=8, tile_h=8))
+    t0 = r0.forward(p, ids, probs=True, id_map=True)
+    targets = dict(color=t0["color"].clone(), depth=t0["depth"].clone(), id=t0["id_map"].clone())
+    cam = OP.perturb_camera(true_cam, [0.004, -0.003, 0.002], [0.02, -0.015, 0.01])
+
+    def loss_and_grad(c, want_grad):
+        r = B.Rasterizer([c], n, K, ctx=B.Context(tile_w=8, tile_h=8))
+        img = r.forward(p, ids, target=targets["id"])
+        gi = dict(d_color=torch.empty_like(img["color"]), d_depth=torch.empty_like(img["depth"]),
+                  d_p_target=torch.empty_like(img["depth"]))
+        loss = torch.zeros(4, dtype=torch.float64, device="cuda")
+        r.frame.object_loss(img, targets, gi, loss)
+        g = None
+        if want_grad:
+            r.frame.render_backward(img, gi)
+            g = r.frame.pose_backward(p).cpu().numpy()[0]
+        return float(loss[0]), g
+
+    L0, g = loss_and_grad(cam, True)
+    assert np.isfinite(g).all() and np.abs(g).max() > 0
+    step = 2e-4 * g / np.linalg.norm(g)
+    Lm, _ = loss_and_grad(OP.perturb_camera(cam, -step[:3], -step[3:]), False)
+    Lp, _ = loss_and_grad(OP.perturb_camera(cam, step[:3], step[3:]), False)
+    assert Lm < L0 < Lp, (Lm, L0, Lp)
