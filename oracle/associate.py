@@ -95,3 +95,38 @@ def occlusion_ratio(det_boxes):
             if iw > 0 and ih > 0:
                 t[i, j] = iw * ih / area[j]
     return t
+
+
+def decide(match, qd_obs, occ, qd_det, label, qd_min=QD_MIN, t_occ=T_OCC, qd_occ=QD_OCC):
+    """The decisions taken from the scores (Sec. III-B, Eq. (5)-(6)).
+
+    fine[j]   = match[j] when QD(observation j, object match[j]) >= qd_min,
+                else -1 (the wrong match is dropped: j seeds a new object);
+    parent[j] = the detection i whose larger box holds j's (occ[i][j] >
+                t_occ) with the same label and QD(observation i,
+                observation j) > qd_occ: j is a piece of i's object and is
+                popped; among several, the largest ratio, then the lowest
+                index; -1 when there is none;
+    root[j]   = the end of j's chain of parents (j when not absorbed);
+    obj[j]    = fine[root[j]]: the object that j's observation updates, or
+                -1 for a new object seeded by detection root[j].
+    A parent's box is strictly larger (occ is 0 otherwise), so chains end."""
+    match = np.asarray(match)
+    n = len(match)
+    fine = np.full(n, -1, np.int32)
+    for j in range(n):
+        k = match[j]
+        if k >= 0 and qd_obs[j][k] >= qd_min:
+            fine[j] = k
+    parent = np.full(n, -1, np.int32)
+    for j in range(n):
+        best = -np.inf
+        for i in range(n):
+            if label[i] == label[j] and occ[i][j] > t_occ and qd_det[i][j] > qd_occ and occ[i][j] > best:
+                best, parent[j] = occ[i][j], i
+    root = np.arange(n, dtype=np.int32)
+    for j in range(n):
+        while parent[root[j]] >= 0:
+            root[j] = parent[root[j]]
+    obj = fine[root] if n else np.zeros(0, np.int32)
+    return dict(fine=fine, parent=parent, root=root, obj=obj.astype(np.int32))

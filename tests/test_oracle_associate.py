@@ -76,3 +76,45 @@ def test_detections_of_known_ellipsoids_match_their_objects():
     m = A.coarse_match(iou)
     np.testing.assert_array_equal(m, [2, -1, 0, 1])
     assert (iou[m[m >= 0], np.nonzero(m >= 0)[0]] > 0.99).all()
+
+
+def test_decide_hand_case():
+    """QD filter of the coarse matches and the occlusion merge on hand boxes
+    whose ratios follow from the geometry (worked out by hand below)."""
+    boxes = np.array([[0, 0, 100, 100],       # 0 large, label 1
+                      [10, 10, 105, 60],      # 1 t[0][1] = 4500/4750 = 0.947 -> piece of 0
+                      [98, 20, 104, 26],      # 2 inside 1 (t = 1); t[0][2] = 12/36 -> piece of 1 only
+                      [60, 60, 80, 80],       # 3 inside 0 but label 2
+                      [30, 70, 40, 80],       # 4 inside 0, but its quadric is too far from 0's
+                      [200, 200, 260, 260],   # 5 disjoint
+                      [12, 12, 14, 14],       # 6 inside 0 and 1 (t = 1 both): lower index 0
+                      [90, 30, 101, 40]],     # 7 t[0][7] = 100/110, t[1][7] = 1: the larger ratio, 1
+                     np.float64)
+    label = [1, 1, 1, 2, 1, 1, 1, 1]
+    occ = A.occlusion_ratio(boxes)
+    np.testing.assert_allclose([occ[0, 1], occ[1, 2], occ[0, 2], occ[0, 7], occ[1, 7]],
+                               [4500 / 4750, 1.0, 12 / 36, 100 / 110, 1.0])
+    qd_det = np.full((8, 8), 0.5)
+    qd_det[0, 4] = qd_det[4, 0] = 0.05
+    match = [0, 0, 1, 1, -1, 0, 0, 0]
+    qd_obs = np.array([[0.9, 0.0], [0.3, 0.0], [0.0, 0.6], [0.0, 0.5], [0.0, 0.0], [0.49, 0.0], [0.99, 0.0],
+                       [0.7, 0.0]])
+    d = A.decide(match, qd_obs, occ, qd_det, label)
+    assert d["fine"].tolist() == [0, -1, 1, 1, -1, -1, 0, 0]       # 0.3, 0.49 < 0.5 dropped; 0.5 kept
+    assert d["parent"].tolist() == [-1, 0, 1, -1, -1, -1, 0, 1]
+    assert d["root"].tolist() == [0, 0, 0, 3, 4, 5, 0, 0]
+    assert d["obj"].tolist() == [0, 0, 0, 1, -1, -1, 0, 0]
+
+
+def test_decide_thresholds_are_strict_and_empty():
+    occ = np.zeros((3, 3))
+    occ[0, 1], occ[0, 2] = 0.85, 0.9          # exactly at the ratio threshold: not a piece
+    qd_det = np.full((3, 3), 0.1)             # exactly at the QD threshold: not a piece
+    d = A.decide([-1, -1, -1], np.zeros((3, 0)), occ, qd_det, [0, 0, 0])
+    assert d["parent"].tolist() == [-1, -1, -1]
+    qd_det[0, 2] = np.nextafter(0.1, 1.0)
+    d = A.decide([-1, -1, -1], np.zeros((3, 0)), occ, qd_det, [0, 0, 0])
+    assert d["parent"].tolist() == [-1, -1, 0] and d["root"].tolist() == [0, 1, 0]
+    assert d["obj"].tolist() == [-1, -1, -1]
+    e = A.decide(np.zeros(0, np.int32), np.zeros((0, 0)), np.zeros((0, 0)), np.zeros((0, 0)), [])
+    assert all(len(v) == 0 for v in e.values())
