@@ -435,6 +435,29 @@ int dqo_quadric_distance(const dqo_ctx* ctx, int32_t na, const double* mu_a, con
                          int32_t nb, const double* mu_b, const double* R_b, const double* axes_b, double tau,
                          double* qd, void* stream);
 
+/* The decisions taken from the association scores (Sec. III-B, Eq. (5)-(6)).
+ * Inputs (device): match[n_det] from dqo_associate; qd_obs[n_det][n_obj] the
+ * QD between each detection's observed quadric and each object (NULL when
+ * n_obj == 0); occ[n_det][n_det] the overlap ratios from dqo_associate;
+ * qd_det[n_det][n_det] the QD between the detections' observed quadrics;
+ * label[n_det] the detector's class of each detection.  Outputs (device,
+ * overwritten):
+ *   fine[n_det]    match[j] when QD(observation j, object match[j]) >= qd_min,
+ *                  else -1 (a wrong match is dropped);
+ *   parent[n_det]  the detection i of the same label with occ[i][j] > t_occ
+ *                  and qd_det[i][j] > qd_occ (j is a piece of i's object and
+ *                  is popped), the largest ratio winning, then the lowest
+ *                  index; -1 when there is none;
+ *   root[n_det]    the end of j's chain of parents (j when not absorbed);
+ *   obj[n_det]     fine[root[j]]: the object j's observation updates, -1 for
+ *                  a new object seeded by detection root[j].
+ * Integer decisions on FP64 inputs, no rounding: equal inputs give equal
+ * outputs on any device.  DQO_EINVAL for negative sizes, n_det > 32768,
+ * non-finite thresholds or missing buffers. */
+int dqo_associate_decide(const dqo_ctx* ctx, int64_t n_det, int32_t n_obj, const int32_t* match, const double* qd_obs,
+                         const double* occ, const double* qd_det, const int32_t* label, double qd_min, double t_occ,
+                         double qd_occ, int32_t* fine, int32_t* parent, int32_t* root, int32_t* obj, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

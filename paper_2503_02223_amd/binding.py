@@ -31,7 +31,7 @@ EXPORTED = ["dqo_config_default", "dqo_ctx_create", "dqo_ctx_destroy", "dqo_last
             "dqo_project_cull_bin", "dqo_sort", "dqo_render_forward", "dqo_object_loss", "dqo_render_backward",
             "dqo_project_backward", "dqo_project_backward_adam", "dqo_pose_backward", "dqo_adam_step", "dqo_adam_step_counted", "dqo_fit_dual_quadric",
             "dqo_id_boxes", "dqo_incremental_masks", "dqo_densify", "dqo_quadric_iou_grad",
-            "dqo_refine_quadrics", "dqo_associate", "dqo_quadric_distance"]
+            "dqo_refine_quadrics", "dqo_associate", "dqo_quadric_distance", "dqo_associate_decide"]
 # include/dqo_learned.h
 EXPORTED_LEARNED = ["dqo_net_layout_get", "dqo_net_workspace_size", "dqo_net_pack", "dqo_net_forward", "dqo_net_loss",
                     "dqo_net_backward", "dqo_adam_flat", "dqo_init_gaussians", "dqo_init_labels", "dqo_net_fallback",
@@ -164,6 +164,7 @@ def lib():
     L.dqo_id_boxes.argtypes = [ctx, vp, i32, i32, i32, i32, vp, vp, vp, vp]
     L.dqo_associate.argtypes = [ctx, i32, vp, vp, vp, i64, vp, vp, i32, vp, vp, d, vp, vp, vp, vp]
     L.dqo_quadric_distance.argtypes = [ctx, i32, vp, vp, vp, i32, vp, vp, vp, d, vp, vp]
+    L.dqo_associate_decide.argtypes = [ctx, i64, i32, vp, vp, vp, vp, vp, d, d, d, vp, vp, vp, vp, vp]
     L.dqo_quadric_iou_grad.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.dqo_refine_quadrics.argtypes = [ctx, i32, i64, vp, vp, vp, i32, vp, vp, vp, P(RefineCfg), vp, vp, vp, vp, vp,
                                       vp, vp]
@@ -458,7 +459,7 @@ def fit_dual_quadric(ctx: Context, boxes, box_obj, box_view, Ps, n_obj, img_wh=N
 
 
 # association thresholds (the paper leaves tau and the IoU threshold unstated)
-ASSOC_DEFAULTS = dict(iou_min=0.3, tau=1.0)
+ASSOC_DEFAULTS = dict(iou_min=0.3, tau=1.0, qd_min=0.5, t_occ=0.85, qd_occ=0.1)
 
 
 def associate(ctx: Context, mu, R, axes, boxes, det_frame, Ps, img_wh, iou_min=ASSOC_DEFAULTS["iou_min"],
@@ -482,6 +483,19 @@ def quadric_distance(ctx: Context, a, b, tau=ASSOC_DEFAULTS["tau"], stream=None)
     ctx.check(lib().dqo_quadric_distance(ctx.h, na, _ptr(a["mu"]), _ptr(a["R"]), _ptr(a["axes"]), nb, _ptr(b["mu"]),
                                          _ptr(b["R"]), _ptr(b["axes"]), float(tau), _ptr(qd), _stream(stream)))
     return qd
+
+
+def associate_decide(ctx: Context, match, qd_obs, occ, qd_det, label, qd_min=ASSOC_DEFAULTS["qd_min"],
+                     t_occ=ASSOC_DEFAULTS["t_occ"], qd_occ=ASSOC_DEFAULTS["qd_occ"], stream=None):
+    """QD filter of the coarse matches and occlusion merge (device tensors):
+    returns fine, parent, root and obj, one int32 per detection."""
+    n_det = int(match.shape[0])
+    n_obj = int(qd_obs.shape[1]) if qd_obs is not None and qd_obs.dim() == 2 else 0
+    out = {k: torch.empty(n_det, dtype=torch.int32, device=match.device) for k in ("fine", "parent", "root", "obj")}
+    ctx.check(lib().dqo_associate_decide(ctx.h, n_det, n_obj, _ptr(match), _ptr(qd_obs), _ptr(occ), _ptr(qd_det),
+                                         _ptr(label), float(qd_min), float(t_occ), float(qd_occ), _ptr(out["fine"]),
+                                         _ptr(out["parent"]), _ptr(out["root"]), _ptr(out["obj"]), _stream(stream)))
+    return out
 
 
 def quadric_iou_grad(ctx: Context, boxes, box_obj, box_view, Ps, theta, img_wh=None, stream=None):

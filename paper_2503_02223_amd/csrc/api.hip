@@ -698,4 +698,20 @@ int dqo_quadric_distance(const dqo_ctx* ctx, int32_t na, const double* mu_a, con
     });
 }
 
+int dqo_associate_decide(const dqo_ctx* ctx, int64_t n_det, int32_t n_obj, const int32_t* match, const double* qd_obs,
+                         const double* occ, const double* qd_det, const int32_t* label, double qd_min, double t_occ,
+                         double qd_occ, int32_t* fine, int32_t* parent, int32_t* root, int32_t* obj, void* stream) {
+    if (!ctx) return DQO_EINVAL;
+    if (n_det < 0 || n_obj < 0 || n_det > (int64_t(1) << 15)) return fail(ctx, DQO_EINVAL, "bad sizes (n_det <= 32768)");
+    if ((int64_t)n_obj * n_det > (int64_t(1) << 31)) return fail(ctx, DQO_EINVAL, "n_obj * n_det must be < 2^31");
+    if (!isfinite(qd_min) || !isfinite(t_occ) || !isfinite(qd_occ)) return fail(ctx, DQO_EINVAL, "thresholds must be finite");
+    if (n_det > 0 && (!match || !occ || !qd_det || !label || !fine || !parent || !root || !obj))
+        return fail(ctx, DQO_EINVAL, "match, occ, qd_det, label and the four outputs are required");
+    if (n_det > 0 && n_obj > 0 && !qd_obs) return fail(ctx, DQO_EINVAL, "qd_obs is required when n_obj > 0");
+    return run(ctx, "associate_decide", [&] {
+        return launch_associate_decide(n_det, n_obj, match, qd_obs, occ, qd_det, label, qd_min, t_occ, qd_occ, fine,
+                                       parent, root, obj, (hipStream_t)stream);
+    });
+}
+
 }  // extern "C"

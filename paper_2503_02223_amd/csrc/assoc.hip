@@ -134,6 +134,53 @@ __global__ __launch_bounds__(256) void quadric_distance_kernel(int na, const dou
     qd[t] = exp(-tau * (sqrt(dm) + sqrt(ds)));
 }
 
+// The decisions of Sec. III-B: the QD filter of each coarse match (Eq. (5))
+// and the parent of each detection in the occlusion merge (Eq. (6)): the
+// same-label detection whose larger box holds it by a ratio above t_occ with
+// a QD above qd_occ, the largest ratio winning, then the lowest index.  One
+// thread per detection; for a fixed i the threads read consecutive columns.
+__global__ __launch_bounds__(256) void decide_parent_kernel(int64_t n_det, int n_obj, const int32_t* __restrict__ match,
+                                                            const double* __restrict__ qd_obs,
+                                                            const double* __restrict__ occ,
+                                                            const double* __restrict__ qd_det,
+                                                            const int32_t* __restrict__ label, double qd_min,
+                                                            double t_occ, double qd_occ, int32_t* __restrict__ fine,
+                                                            int32_t* __restrict__ parent) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n_det) return;
+    const int k = match[j];
+    fine[j] = (k >= 0 && k < n_obj && qd_obs[j * n_obj + k] >= qd_min) ? k : -1;
+    const int32_t lj = label[j];
+    double best = -1.0;
+    int32_t arg = -1;
+    for (int64_t i = 0; i < n_det; ++i) {
+        const double t = occ[i * n_det + j];
+        if (label[i] == lj && t > t_occ && qd_det[i * n_det + j] > qd_occ && t > best) {
+            best = t;
+            arg = (int32_t)i;
+        }
+    }
+    parent[j] = arg;
+}
+
+// The end of each detection's parent chain and the object it updates.  A
+// parent's box is strictly larger, so a chain has fewer than n_det links;
+// the loop is bounded by n_det all the same.
+__global__ __launch_bounds__(256) void decide_root_kernel(int64_t n_det, const int32_t* __restrict__ fine,
+                                                          const int32_t* __restrict__ parent,
+                                                          int32_t* __restrict__ root, int32_t* __restrict__ obj) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n_det) return;
+    int64_t r = j;
+    for (int64_t s = 0; s < n_det; ++s) {
+        const int32_t p = parent[r];
+        if (p < 0 || p >= n_det) break;
+        r = p;
+    }
+    root[j] = (int32_t)r;
+    obj[j] = fine[r];
+}
+
 static unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_associate(int n_obj, const double* mu, const double* R, const double* ax, int64_t n_det,
@@ -158,6 +205,18 @@ hipError_t launch_quadric_distance(int na, const double* mu_a, const double* R_a
     if ((int64_t)na * nb == 0) return hipSuccess;
     hipLaunchKernelGGL(quadric_distance_kernel, dim3(grid_of((int64_t)na * nb)), dim3(256), 0, st, na, mu_a, R_a,
                        ax_a, nb, mu_b, R_b, ax_b, tau, qd);
+    return hipGetLastError();
+}
+
+hipError_t launch_associate_decide(int64_t n_det, int n_obj, const int32_t* match, const double* qd_obs,
+                                   const double* occ, const double* qd_det, const int32_t* label, double qd_min,
+                                   double t_occ, double qd_occ, int32_t* fine, int32_t* parent, int32_t* root,
+                                   int32_t* obj, hipStream_t st) {
+    if (n_det == 0) return hipSuccess;
+    hipLaunchKernelGGL(decide_parent_kernel, dim3(grid_of(n_det)), dim3(256), 0, st, n_det, n_obj, match, qd_obs, occ,
+                       qd_det, label, qd_min, t_occ, qd_occ, fine, parent);
+    hipLaunchKernelGGL(decide_root_kernel, dim3(grid_of(n_det)), dim3(256), 0, st, n_det, (const int32_t*)fine,
+                       (const int32_t*)parent, root, obj);
     return hipGetLastError();
 }
 

@@ -283,6 +283,10 @@ hipError_t launch_associate(int n_obj, const double* mu, const double* R, const 
 hipError_t launch_quadric_distance(int na, const double* mu_a, const double* R_a, const double* ax_a, int nb,
                                    const double* mu_b, const double* R_b, const double* ax_b, double tau, double* qd,
                                    hipStream_t st);
+hipError_t launch_associate_decide(int64_t n_det, int n_obj, const int32_t* match, const double* qd_obs,
+                                   const double* occ, const double* qd_det, const int32_t* label, double qd_min,
+                                   double t_occ, double qd_occ, int32_t* fine, int32_t* parent, int32_t* root,
+                                   int32_t* obj, hipStream_t st);
 hipError_t launch_quadric_iou_grad(int n_obj, int n_views, int64_t n_boxes, const double* boxes,
                                    const int32_t* box_obj, const int32_t* box_view, const double* P,
                                    const int32_t* img_wh, const double* theta, double* loss, double* grad,

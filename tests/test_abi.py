@@ -166,3 +166,9 @@ def test_new_entry_points_validate_on_host():
     assert L.dqo_associate(ctx.h, 1, fake, fake, fake, 2, fake, fake, 0, fake, fake, 0.3, fake, fake, None,
                            None) == B.EINVAL           # detections without frames
     assert L.dqo_quadric_distance(ctx.h, 1, fake, fake, fake, 1, fake, fake, fake, -1.0, fake, None) == B.EINVAL
+    assert L.dqo_associate_decide(ctx.h, 40000, 0, fake, None, fake, fake, fake, 0.5, 0.85, 0.1, fake, fake, fake,
+                                  fake, None) == B.EINVAL   # too many detections
+    assert L.dqo_associate_decide(ctx.h, 3, 2, fake, None, fake, fake, fake, 0.5, 0.85, 0.1, fake, fake, fake, fake,
+                                  None) == B.EINVAL         # objects without their QD
+    assert L.dqo_associate_decide(ctx.h, 3, 0, fake, None, fake, fake, fake, 0.5, float("nan"), 0.1, fake, fake,
+                                  fake, fake, None) == B.EINVAL

@@ -105,3 +105,100 @@ def test_association_edge_cases():
                       wh)
     torch.cuda.synchronize()
     assert abs(float(out["iou"][0, 0]) - 1.0) < 1e-12 and out["match"].cpu().tolist() == [0]
+
+
+def _decide_dev(match, qd_obs, occ, qd_det, label):
+    d = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    out = B.associate_decide(B.Context(), d(match, torch.int32), d(qd_obs, torch.float64), d(occ, torch.float64),
+                             d(qd_det, torch.float64), d(label, torch.int32))
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _nested_frames(rng, n_frames, per_frame):
+    """Boxes of several frames, built so that many are pieces of larger ones
+    (chains of nested boxes, some only partly inside, some of another label)."""
+    boxes, frames, labels = [], [], []
+    for f in range(n_frames):
+        for _ in range(per_frame // 4):
+            x0, y0 = rng.uniform(0, 400), rng.uniform(0, 300)
+            w, h = rng.uniform(60, 200), rng.uniform(60, 160)
+            lab = int(rng.integers(3))
+            b = np.array([x0, y0, x0 + w, y0 + h])
+            for _ in range(4):
+                boxes.append(b.copy())
+                frames.append(f)
+                labels.append(lab if rng.random() < 0.8 else int(rng.integers(3)))
+                s = rng.uniform(0.4, 0.9)
+                w2, h2 = (b[2] - b[0]) * s, (b[3] - b[1]) * s
+                ox = rng.uniform(-0.15, 1.1) * (b[2] - b[0] - w2)     # sometimes sticks out
+                oy = rng.uniform(0.0, 1.0) * (b[3] - b[1] - h2)
+                b = np.array([b[0] + ox, b[1] + oy, b[0] + ox + w2, b[1] + oy + h2])
+    return np.array(boxes), np.array(frames, np.int32), np.array(labels, np.int32)
+
+
+@pytest.mark.parametrize("n_frames,per_frame,n_obj", [(1, 8, 2), (6, 40, 10), (10, 120, 25)])
+def test_decide_parity(n_frames, per_frame, n_obj):
+    rng = np.random.default_rng(per_frame)
+    boxes, frames, label = _nested_frames(rng, n_frames, per_frame)
+    n = len(boxes)
+    occ = np.zeros((n, n))
+    for f in range(n_frames):
+        idx = np.nonzero(frames == f)[0]
+        occ[np.ix_(idx, idx)] = A.occlusion_ratio(boxes[idx])
+    qd_det = rng.uniform(0.0, 0.3, (n, n))
+    qd_obs = rng.uniform(0.2, 1.0, (n, n_obj))
+    match = rng.integers(-1, n_obj, n).astype(np.int32)
+    want = A.decide(match, qd_obs, occ, qd_det, label)
+    absorbed = want["parent"] >= 0
+    assert absorbed.sum() > n // 8 and (absorbed & (want["root"] != want["parent"])).any()     # chains of 2+
+    got = _decide_dev(match, qd_obs, occ, qd_det, label)
+    for k in ("fine", "parent", "root", "obj"):
+        np.testing.assert_array_equal(got[k], want[k], err_msg=k)
+
+
+def test_decide_edge_cases():
+    # no objects: every fine match is -1, pieces still merge
+    occ = np.array([[0.0, 0.9], [0.0, 0.0]])
+    got = _decide_dev([-1, -1], np.zeros((2, 0)), occ, np.full((2, 2), 0.5), [3, 3])
+    assert got["parent"].tolist() == [-1, 0] and got["root"].tolist() == [0, 0] and got["obj"].tolist() == [-1, -1]
+    # thresholds are strict for the merge and inclusive for the filter
+    got = _decide_dev([0, 0], np.array([[0.5], [0.4999]]), np.array([[0.0, 0.85], [0.0, 0.0]]),
+                      np.full((2, 2), 0.5), [1, 1])
+    assert got["fine"].tolist() == [0, -1] and got["parent"].tolist() == [-1, -1]
+    # no detections
+    e = B.associate_decide(B.Context(), torch.zeros(0, dtype=torch.int32, device="cuda"),
+                           torch.zeros(0, 0, dtype=torch.float64, device="cuda"),
+                           torch.zeros(0, 0, dtype=torch.float64, device="cuda"),
+                           torch.zeros(0, 0, dtype=torch.float64, device="cuda"),
+                           torch.zeros(0, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    assert all(v.numel() == 0 for v in e.values())
+
+
+def test_decide_max_detections_known_chains():
+    """32768 detections (the largest batch), as chains of 4 nested pieces of
+    one label, each chain in a frame of its own: every piece's parent is the
+    one before it, its root the chain's head, its object the head's match."""
+    n = 1 << 15
+    dev = "cuda"
+    j = torch.arange(n, device=dev)
+    head = j - j % 4
+    occ = torch.zeros(n, n, dtype=torch.float64, device=dev)
+    qd_det = torch.full((n, n), 0.5, dtype=torch.float64, device=dev)
+    piece = j % 4 != 0
+    occ[(j - 1)[piece], j[piece]] = 0.95          # the previous piece holds this one
+    occ[head[piece], j[piece]] = torch.where(j[piece] % 4 == 1, 0.95, 0.9).to(torch.float64)
+    n_obj = 64
+    match = (head // 4 % n_obj).to(torch.int32)
+    qd_obs = torch.full((n, n_obj), 0.9, dtype=torch.float64, device=dev)
+    label = torch.zeros(n, dtype=torch.int32, device=dev)
+    out = B.associate_decide(B.Context(), match, qd_obs, occ, qd_det, label)
+    torch.cuda.synchronize()
+    jj = j.cpu().numpy()
+    hh = jj - jj % 4
+    want_parent = np.where(jj % 4 == 0, -1, jj - 1)
+    np.testing.assert_array_equal(out["parent"].cpu().numpy(), want_parent)
+    np.testing.assert_array_equal(out["root"].cpu().numpy(), hh)
+    np.testing.assert_array_equal(out["obj"].cpu().numpy(), hh // 4 % n_obj)
+    np.testing.assert_array_equal(out["fine"].cpu().numpy(), match.cpu().numpy())
