@@ -39,6 +39,11 @@ __device__ __forceinline__ T quad_form(const T* sp, T sx, T sy, T& dx, T& dy) {
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
+// The Gaussian falloff exp(-Q/2), one expression for the forward and the
+// backward so that both take bitwise identical decisions.
+template <typename T>
+__device__ __forceinline__ T falloff(T Q) { return fast_exp<T>(T(-0.5) * Q); }
+
 template <typename T>
 __device__ __forceinline__ void copy_splat(T* dst, const T* src) {
 #pragma unroll
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
             for (int k = 0; k < kFwdGroup; ++k) {
                 T dx, dy;
                 const T Q = quad_form(rec[k], sx, sy, dx, dy);
-                a0[k] = min(rec[k][5] * fast_exp<T>(T(-0.5) * Q), cs.alpha_max);
+                a0[k] = min(rec[k][5] * falloff<T>(Q), cs.alpha_max);
                 c0k[k] = (j0 + k < nb) && (Q <= cs.q_max) && (a0[k] >= cs.alpha_min);
                 any = any || c0k[k];
             }
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     __syncthreads();
     if (lastp >= 0) atomicMax(&s_maxlast, lastp);
     __syncthreads();
-    const int maxlast = s_maxlast;
+    const int maxlast = __builtin_amdgcn_readfirstlane(s_maxlast);  // uniform: scalar walk bounds
     // Pairs behind every pixel's last blended Gaussian keep the zero partials
     // written before this kernel.
     const uint32_t hi = (maxlast >= (int)rs) ? (uint32_t)(maxlast + 1) : rs;
@@ -369,10 +374,10 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
                 const T Q = quad_form(sp, sx, sy, dx, dy);
                 const bool in = (Q <= cs.q_max) && ((int)(bstart + jl) <= lastp);
                 if (!wave_any(in)) continue;
-                const T G = fast_exp<T>(T(-0.5) * Q);
+                const T G = falloff<T>(Q);
                 const T araw = sp[5] * G;
                 const bool clamped = !(araw < cs.alpha_max);
-                const T a0 = min(araw, cs.alpha_max);
+                const T a0 = clamped ? cs.alpha_max : araw;
                 const bool contrib = in && (a0 >= cs.alpha_min);
                 if (!wave_any(contrib)) continue;
                 any = true;
@@ -500,6 +505,10 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     int maxlast = lastp;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d));
+    // Equal in every lane; said so, the walk state derived from it lives in
+    // scalar registers and the loop control is scalar branches (measured
+    // 10% faster than the same walk with its state in vector registers).
+    maxlast = __builtin_amdgcn_readfirstlane(maxlast);
     // Pairs behind every pixel's last blended Gaussian, and pairs that
     // contribute nowhere in the tile, keep the zero partials written before
     // this kernel.
@@ -532,8 +541,30 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     uint32_t b_e = a_s, b_s = batch_lo(a_s);
     uint32_t rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
 
+    // The record of the Gaussian being tested, read from LDS in one go (three
+    // 16-byte broadcast reads at a 24-bit multiply of its index).
+    T cur[kSplatWords];
+    auto lds_rec = [&](int j) {
+        if constexpr (sizeof(T) == 4) {
+            const float4* s4 = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_sp) +
+                                                               __mul24(j, (int)(kSplatWords * sizeof(T))));
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const float4 a = s4[q];
+                cur[4 * q] = a.x;
+                cur[4 * q + 1] = a.y;
+                cur[4 * q + 2] = a.z;
+                cur[4 * q + 3] = a.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSplatWords; ++k) cur[k] = s_sp[j * kSplatWords + k];
+        }
+    };
     // Advances to the next Gaussian (descending) that contributes at some pixel
-    // of the tile; false at the end of the range.
+    // of the tile; false at the end of the range.  The two wave-wide tests are
+    // ballots of single comparisons combined as masks, which keeps them in
+    // scalar instructions.
     auto next = [&]() -> bool {
         for (;;) {
             if (jl < 0) {
@@ -558,22 +589,25 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
                 b_s = batch_lo(a_s);
                 rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
             }
-            sp = s_sp + jl * kSplatWords;
+            lds_rec(jl);
+            sp = cur;
             const T Q = quad_form(sp, sx, sy, dx, dy);
-            const bool in = (Q <= cs.q_max) && ((int)(bstart + jl) <= lastp);
-            if (!wave_any(in)) {
+            const bool in_q = Q <= cs.q_max, in_l = (int)(bstart + jl) <= lastp;
+            const uint64_t m_in = __builtin_amdgcn_ballot_w64(in_q) & __builtin_amdgcn_ballot_w64(in_l);
+            if (m_in == 0ull) {
                 --jl;
                 continue;
             }
-            G = fast_exp<T>(T(-0.5) * Q);
+            G = falloff<T>(Q);
             const T araw = sp[5] * G;
             clamped = !(araw < cs.alpha_max);
-            a0 = min(araw, cs.alpha_max);
-            contrib = in && (a0 >= cs.alpha_min);
-            if (!wave_any(contrib)) {
+            a0 = clamped ? cs.alpha_max : araw;  // min(araw, alpha_max), one select
+            const bool in_a = a0 >= cs.alpha_min;
+            if ((m_in & __builtin_amdgcn_ballot_w64(in_a)) == 0ull) {
                 --jl;
                 continue;
             }
+            contrib = in_q && in_l && in_a;
             return true;
         }
     };
