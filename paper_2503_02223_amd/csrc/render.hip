@@ -440,18 +440,21 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
 // reduction slot: the walk finds the next contributing Gaussian, fills slot c
 // (c = 0..5, a separate statically indexed code section each, so the slot
 // values stay in fixed registers), and after six slots the wave transposes and
-// sums them.  Pairs that take no slot get zero partials.
-template <typename T>
-__device__ __forceinline__ void flush_slots(T (&v)[64], int nslot, int lane, const uint32_t* s_chunk,
+// sums them.  Pairs that take no slot get zero partials.  Every take writes all
+// ten values of its slot, so nothing is cleared between chunks: the values
+// past the NS filled slots are set to zero here, as constants.
+template <int NS, typename T>
+__device__ __forceinline__ void flush_slots(T (&v)[64], int lane, int lane_slot, const uint32_t (&chunk)[kChunk],
                                             T* __restrict__ partials, uint32_t cap) {
-    wave_transpose_sum<T>(v, lane);
-    if (lane < nslot * kGradWords) {
-        const int c = lane / kGradWords;
-        const uint32_t slot = s_chunk[c];
-        if (slot < cap) partials[(size_t)slot * kGradWords + (lane - c * kGradWords)] = v[0];
-    }
 #pragma unroll
-    for (int k = 0; k < 64; ++k) v[k] = T(0);
+    for (int k = NS * kGradWords; k < 64; ++k) v[k] = T(0);
+    wave_transpose_sum<T>(v, lane);
+    if (lane < NS * kGradWords) {
+        uint32_t slot = chunk[0];
+#pragma unroll
+        for (int c = 1; c < NS; ++c) slot = (lane_slot == c) ? chunk[c] : slot;
+        if (slot < cap) partials[(size_t)slot * kGradWords + (lane - lane_slot * kGradWords)] = v[0];
+    }
 }
 
 template <int C>
@@ -469,7 +472,6 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     static_assert(TW * TH == kWave, "one wavefront per tile");
     __shared__ __align__(16) T s_sp[kWave * kSplatWords];
     __shared__ uint32_t s_slot[kWave];
-    __shared__ uint32_t s_chunk[kChunk];
 
     const int lane = threadIdx.x;
     const int tile = (int)min(schedule[blockIdx.x], (uint32_t)(gridDim.x - 1));
@@ -517,6 +519,8 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     T v[64];
 #pragma unroll
     for (int k = 0; k < 64; ++k) v[k] = T(0);
+    uint32_t chunk[kChunk] = {};              // pair slot of the Gaussian in each reduction slot
+    const int lane_slot = lane / kGradWords;  // the reduction slot whose sum this lane stores
 
     // walk state (wave-uniform): the LDS batch holds positions [bstart, bend)
     uint32_t bend = hi, bstart = hi;
@@ -636,23 +640,35 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
         v[C * kGradWords + 7] = gc1 * w;
         v[C * kGradWords + 8] = gc2 * w;
         v[C * kGradWords + 9] = gd * w;
-        if (lane == 0) s_chunk[C] = s_slot[jl];
+        chunk[C] = s_slot[jl];
         --jl;
     };
+    // Six slots: four and five (fewer registers, five waves per SIMD with
+    // four) measured slower, the transposed sums then costing more per slot.
+    constexpr int NS = kChunk;
+    static_assert(NS >= 2 && NS <= 6, "reduction slots");
     for (;;) {
         if (!next()) break;
         take(SlotIdx<0>{});
-        if (!next()) { flush_slots<T>(v, 1, lane, s_chunk, partials, cap); break; }
+        if (!next()) { flush_slots<1>(v, lane, lane_slot, chunk, partials, cap); break; }
         take(SlotIdx<1>{});
-        if (!next()) { flush_slots<T>(v, 2, lane, s_chunk, partials, cap); break; }
-        take(SlotIdx<2>{});
-        if (!next()) { flush_slots<T>(v, 3, lane, s_chunk, partials, cap); break; }
-        take(SlotIdx<3>{});
-        if (!next()) { flush_slots<T>(v, 4, lane, s_chunk, partials, cap); break; }
-        take(SlotIdx<4>{});
-        if (!next()) { flush_slots<T>(v, 5, lane, s_chunk, partials, cap); break; }
-        take(SlotIdx<5>{});
-        flush_slots<T>(v, 6, lane, s_chunk, partials, cap);
+        if constexpr (NS > 2) {
+            if (!next()) { flush_slots<2>(v, lane, lane_slot, chunk, partials, cap); break; }
+            take(SlotIdx<2>{});
+        }
+        if constexpr (NS > 3) {
+            if (!next()) { flush_slots<3>(v, lane, lane_slot, chunk, partials, cap); break; }
+            take(SlotIdx<3>{});
+        }
+        if constexpr (NS > 4) {
+            if (!next()) { flush_slots<4>(v, lane, lane_slot, chunk, partials, cap); break; }
+            take(SlotIdx<4>{});
+        }
+        if constexpr (NS > 5) {
+            if (!next()) { flush_slots<5>(v, lane, lane_slot, chunk, partials, cap); break; }
+            take(SlotIdx<5>{});
+        }
+        flush_slots<NS>(v, lane, lane_slot, chunk, partials, cap);
     }
 }
 
