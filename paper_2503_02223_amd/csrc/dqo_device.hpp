@@ -16,18 +16,18 @@ constexpr int kGradWords = 10;    // dmx,dmy,dA,dB,dC,do,dr,dg,db,dz
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
-// Items per thread of a radix pass (4096-item blocks).  Shorter blocks were
-// measured no faster at 200k items and 22% slower at 9.6M (8 keyframes): with
-// more blocks resident at once the look-back chain grows.
-#ifndef DQO_DEPTH_IPT
-#define DQO_DEPTH_IPT 16
-#endif
-#ifndef DQO_PAIR_IPT
-#define DQO_PAIR_IPT 16
-#endif
-constexpr int kDepthIpt = DQO_DEPTH_IPT;
-constexpr int kPairIpt = DQO_PAIR_IPT;
-constexpr int kDepthTile = kSortThreads * kDepthIpt;
+// Items per thread of a radix pass.  The decoupled look-back costs one memory
+// latency per window of preceding blocks, so longer blocks shorten the chain
+// but lengthen each block's own ranking.  Measured on one MI355X: the pair
+// passes (1.6M pairs of one 640x480 view, 9.6M of eight) are as fast or faster
+// with 8192-item blocks (eight keyframes: 163 -> 175 it/s); the depth passes
+// are faster with 4096-item blocks at 200k items (8192: 1650 -> 1573 it/s) and
+// with 8192-item blocks from about a million (175 -> 180 it/s at 9.6M).
+constexpr int kSortIptMin = 16;  // the shortest blocks: sizes the look-back arrays
+constexpr int kPairIpt = 32;
+constexpr int64_t kDepthLongBlocks = int64_t(1) << 19;  // items from which depth passes use 8192-item blocks
+inline int depth_ipt(int64_t items) { return items >= kDepthLongBlocks ? 32 : kSortIptMin; }
+constexpr int kDepthTile = kSortThreads * kSortIptMin;
 constexpr int kPairTile = kSortThreads * kPairIpt;
 // Scan + emission: one record per thread, 1024 per block, so that each of the
 // 16 wavefronts emits the pairs of its own 64 records.

@@ -326,7 +326,7 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
                                          s.depth_vals[src ^ 1], nullptr, (uint32_t)M, p * kRadixBits,
                                          &s.ctrl->hist_depth[0][p][0], kMaxDepthPasses * kRadixBins, s.hist_copies_depth,
                                          s.lb_depth + (size_t)p * s.depth_blocks * kRadixBins,
-                                         &s.ctrl->counters[kCounterDepth + p], s.ctrl, st, kDepthIpt);
+                                         &s.ctrl->counters[kCounterDepth + p], s.ctrl, st, depth_ipt(M));
         if (e != hipSuccess) return e;
         src ^= 1;
     }

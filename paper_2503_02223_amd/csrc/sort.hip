@@ -175,14 +175,11 @@ hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
                              hipStream_t st, int ipt) {
     if (n_host == 0) return hipSuccess;
     const int blocks = (int)((n_host + kSortThreads * ipt - 1) / (kSortThreads * ipt));
-    if (ipt == 4)
-        hipLaunchKernelGGL(radix_pass_kernel<4>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
-    else if (ipt == 8)
-        hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
-    else if (ipt == 16)
+    if (ipt == 16)
         hipLaunchKernelGGL(radix_pass_kernel<16>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
+                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
+    else if (ipt == 32)
+        hipLaunchKernelGGL(radix_pass_kernel<32>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
                            n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
     else
         return hipErrorInvalidValue;
