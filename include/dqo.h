@@ -121,7 +121,8 @@ enum dqo_buf {
     DQO_BUF_PAIR_KEYS,   /* [cap] uint32 sorted global tile id (view*tiles + tile) */
     DQO_BUF_PAIR_VALS,   /* [cap] uint32 item index, in (tile, depth, index) order */
     DQO_BUF_RANGES,      /* [V*tiles][2] uint32 [start, end) of each tile in the sorted pairs */
-    DQO_BUF_PARTIALS,    /* [cap][10] per-pair gradient partials (render backward) */
+    DQO_BUF_PARTIALS,    /* [cap][10] per-pair gradient partials (render backward; valid only for the pairs
+                            it marks written, the others are left as they were and count as zero) */
     DQO_BUF_CONTROL,     /* status word, pair count, counters, histograms, loss partials */
     DQO_BUF_SCRATCH,     /* sort double buffers and wait state */
     DQO_BUF_COUNT

@@ -33,7 +33,7 @@ struct Geo {
     int depth_blocks, scan_blocks, pair_blocks, pair_passes, pair_first_buf;
     int64_t lb_words;
     // scratch sub-offsets (relative to DQO_BUF_SCRATCH)
-    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_lbd, off_lbs, off_lbp;
+    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_lbd, off_lbs, off_lbp;
 };
 
 int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams) {
@@ -108,6 +108,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.off_sched = so; so = align256(so + tiles_total * 4);
     g.off_sums = so; so = align256(so + M * kGradWords * ts);
     g.off_pose = so; so = align256(so + (int64_t)d->n_views * ((d->n + 255) / 256) * 6 * 8);
+    g.off_written = so; so = align256(so + cap);
     g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * g.depth_blocks * kRadixBins * 8);
     g.off_lbs = so; so = align256(so + (int64_t)g.scan_blocks * 8);
     g.off_lbp = so; so = align256(so + (int64_t)kMaxPairPasses * g.pair_blocks * kRadixBins * 8);
@@ -144,6 +145,7 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.schedule = (uint32_t*)(sc + g.off_sched);
     s.sums = sc + g.off_sums;
     s.pose_partials = (double*)(sc + g.off_pose);
+    s.written = (uint8_t*)(sc + g.off_written);
     s.ctrl = (Ctrl*)(b + g.L.offset[DQO_BUF_CONTROL]);
     s.lb_depth = (uint64_t*)(sc + g.off_lbd);
     s.lb_scan = (uint64_t*)(sc + g.off_lbs);
@@ -380,9 +382,9 @@ int dqo_sort(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     return run(ctx, "sort", [&] {
         hipError_t e = launch_pair_sort(s, tiles_total, (hipStream_t)stream);
         if (e != hipSuccess) return e;
-        // the render backward writes only the pairs that contribute in their tile
-        return d->dtype == DQO_F64 ? launch_zero_partials<double>(s, (hipStream_t)stream)
-                                   : launch_zero_partials<float>(s, (hipStream_t)stream);
+        // the render backward writes only the pairs that contribute in their
+        // tile, and marks them: the marks start cleared
+        return launch_clear_written(s, (hipStream_t)stream);
     });
 }
 

@@ -224,6 +224,7 @@ struct StatePtrs {
     void* partials;
     void* sums;           // [V*n][kGradWords] per-item totals of the pair partials
     double* pose_partials;  // [V][ceil(n/256)][6] per-block camera-pose gradient sums
+    uint8_t* written;     // [cap] 1 where the render backward wrote the pair's partials
     Ctrl* ctrl;
     uint64_t* lb_depth;   // [kMaxDepthPasses][blocks][256]
     uint64_t* lb_scan;    // [blocks]
@@ -274,8 +275,7 @@ hipError_t launch_fit_quadric(int n_obj, int64_t n_boxes, const double* boxes, c
 hipError_t launch_clear_ctrl(Ctrl* ctrl, uint64_t* lb, int64_t lb_words, hipStream_t st);
 hipError_t launch_clear_status(Ctrl* ctrl, hipStream_t st);
 hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t st);
-template <typename T>
-hipError_t launch_zero_partials(const StatePtrs& s, hipStream_t st);
+hipError_t launch_clear_written(const StatePtrs& s, hipStream_t st);
 hipError_t launch_associate(int n_obj, const double* mu, const double* R, const double* ax, int64_t n_det,
                             const double* boxes, const int32_t* det_frame, int n_frames, const double* P,
                             const int32_t* img_wh, double iou_min, double* iou, int32_t* match, double* occ,

@@ -339,36 +339,25 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
 }
 
 // ---------------------------------------------------------------- backward
-// Zeroes the partials of the pairs of this frame (the render backward writes
-// only the pairs that contribute somewhere in their tile).
-template <typename T>
-__global__ __launch_bounds__(256) void zero_partials_kernel(T* __restrict__ partials, const Ctrl* __restrict__ ctrl,
-                                                            uint32_t cap) {
-    const uint64_t n = (uint64_t)min(ctrl->num_pairs, cap) * kGradWords;
-    const uint64_t stride = (uint64_t)gridDim.x * 256 * 4;
-    for (uint64_t i = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * 4; i < n; i += stride) {
-        if (i + 4 <= n) {
-            partials[i] = T(0);
-            partials[i + 1] = T(0);
-            partials[i + 2] = T(0);
-            partials[i + 3] = T(0);
-        } else {
-            for (uint64_t k = i; k < n; ++k) partials[k] = T(0);
-        }
-    }
+// Clears the written marks of the pairs of this frame.  The render backward
+// writes the partials of the pairs that contribute somewhere in their tile and
+// marks them; the per-item sums read the partials of marked pairs only, so the
+// partials themselves are never cleared.
+__global__ __launch_bounds__(256) void clear_written_kernel(uint32_t* __restrict__ words,
+                                                            const Ctrl* __restrict__ ctrl, uint32_t cap) {
+    const uint32_t n = (min(ctrl->num_pairs, cap) + 3u) / 4u;  // marks are bytes, cleared four at a time
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) words[i] = 0u;
 }
 
-template <typename T>
-hipError_t launch_zero_partials(const StatePtrs& s, hipStream_t st) {
+hipError_t launch_clear_written(const StatePtrs& s, hipStream_t st) {
     if (s.capacity == 0) return hipSuccess;
-    hipLaunchKernelGGL(zero_partials_kernel<T>, dim3(1024), dim3(256), 0, st, (T*)s.partials, s.ctrl,
+    hipLaunchKernelGGL(clear_written_kernel, dim3(256), dim3(256), 0, st, (uint32_t*)s.written, s.ctrl,
                        (uint32_t)s.capacity);
     return hipGetLastError();
 }
-template hipError_t launch_zero_partials<float>(const StatePtrs&, hipStream_t);
-template hipError_t launch_zero_partials<double>(const StatePtrs&, hipStream_t);
 
-// Per-item totals of the pair partials.  An item's (tile, Gaussian)
+// Per-item totals of the pair partials (those of pairs the render backward
+// marked written; the others count as zero).  An item's (tile, Gaussian)
 // partials occupy consecutive slots, and items that are consecutive in depth
 // order occupy consecutive slot ranges, so one wavefront takes 64 consecutive
 // items and reads their slots 64 at a time, coalesced.  Each round sums the
@@ -410,7 +399,8 @@ template <typename T>
 __global__ __launch_bounds__(kSlotWaves * kWave) void slot_sum_kernel(const uint32_t* __restrict__ order,
                                                                       const uint32_t* __restrict__ counts,
                                                                       const uint32_t* __restrict__ offsets,
-                                                                      const T* __restrict__ partials, uint32_t M,
+                                                                      const T* __restrict__ partials,
+                                                                      const uint8_t* __restrict__ written, uint32_t M,
                                                                       uint32_t cap, T* __restrict__ sums) {
     __shared__ T s_acc[kSlotWaves][kWave][kGradWords + 1];
     __shared__ uint16_t s_nz[kSlotWaves][kWave];
@@ -446,8 +436,8 @@ __global__ __launch_bounds__(kSlotWaves * kWave) void slot_sum_kernel(const uint
         const uint64_t upto = marks & ((2ull << lane) - 1ull);
         T v[kGradWords];
         int owner = 0;
-        if (live) {
-            owner = s_nz[wave][before + (uint32_t)__popcll(upto) - 1u];
+        if (live) owner = s_nz[wave][before + (uint32_t)__popcll(upto) - 1u];
+        if (live && written[s]) {
 #pragma unroll
             for (int k = 0; k < kGradWords; ++k) v[k] = partials[(size_t)s * kGradWords + k];
         } else {
@@ -687,7 +677,7 @@ hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads,
     const int64_t M = f.s.items;
     hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
                        dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
-                       (const T*)f.s.partials, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
+                       (const T*)f.s.partials, f.s.written, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
     hipLaunchKernelGGL((project_backward_kernel<T>), dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st,
                        f.views, f.consts, f.n, const_cast<T*>(params), f.s.counts, f.s.offsets, (const T*)f.s.sums,
                        (uint32_t)f.s.capacity, grads, (T*)nullptr, (T*)nullptr, AdamArgs<T>{}, (int64_t*)nullptr,
@@ -779,7 +769,7 @@ hipError_t launch_pose_backward(const Frame<T>& f, const T* params, double* pose
     const int64_t M = f.s.items;
     hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
                        dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
-                       (const T*)f.s.partials, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
+                       (const T*)f.s.partials, f.s.written, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
     const int blocks = (int)((f.n + 255) / 256);
     hipLaunchKernelGGL(pose_grad_kernel<T>, dim3((unsigned)blocks, (unsigned)V), dim3(256), 0, st, f.views, f.consts,
                        f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.sums, (uint32_t)f.s.capacity,
@@ -796,7 +786,7 @@ hipError_t launch_project_backward_adam(const Frame<T>& f, T* params, T* grads, 
     const int64_t M = f.s.items;
     hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
                        dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
-                       (const T*)f.s.partials, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
+                       (const T*)f.s.partials, f.s.written, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
     hipLaunchKernelGGL((project_backward_kernel<T>), dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st,
                        f.views, f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.sums,
                        (uint32_t)f.s.capacity, grads, m, v, make_adam_args<T>(hp, 1), d_step,

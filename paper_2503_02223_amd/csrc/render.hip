@@ -18,9 +18,10 @@
 // reduces the per-pixel gradients of each Gaussian over the workgroup: six
 // Gaussians x ten values are transposed-and-summed across the 64 lanes of a
 // wave (each lane ends up owning one value), then summed over the waves in
-// LDS, and written once per (tile, Gaussian) pair to its own slot; the
-// per-Gaussian totals are formed later in a fixed order, so no atomics are
-// needed and the result is deterministic.
+// LDS, and written once per (tile, Gaussian) pair to its own slot, which is
+// marked written (pairs left unwritten count as zero); the per-Gaussian
+// totals are formed later in a fixed order, so no atomics are needed and the
+// result is deterministic.
 #include "dqo_device.hpp"
 
 namespace dqo {
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
     const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
     const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
-    const T* __restrict__ dPt, T* __restrict__ partials, uint32_t cap, uint32_t M) {
+    const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap, uint32_t M) {
     constexpr int BLOCK = TW * TH;
     constexpr int NW = BLOCK / kWave;
     __shared__ __align__(16) T s_sp[BLOCK * kSplatWords];
@@ -345,8 +346,8 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     if (lastp >= 0) atomicMax(&s_maxlast, lastp);
     __syncthreads();
     const int maxlast = __builtin_amdgcn_readfirstlane(s_maxlast);  // uniform: scalar walk bounds
-    // Pairs behind every pixel's last blended Gaussian keep the zero partials
-    // written before this kernel.
+    // Pairs behind every pixel's last blended Gaussian are not written and
+    // stay unmarked (their partials count as zero).
     const uint32_t hi = (maxlast >= (int)rs) ? (uint32_t)(maxlast + 1) : rs;
     T S = Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
     int buf = 0;
@@ -411,7 +412,10 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
                 const int jl = c0 - c;
                 if (lane < kChunk * kGradWords && jl >= 0) {
                     const uint32_t slot = s_slot[jl];
-                    if (slot < cap) partials[(size_t)slot * kGradWords + (lane - c * kGradWords)] = v[0];
+                    if (slot < cap) {
+                        partials[(size_t)slot * kGradWords + (lane - c * kGradWords)] = v[0];
+                        if (lane == c * kGradWords) written[slot] = 1;
+                    }
                 }
                 continue;
             }
@@ -425,7 +429,10 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
 #pragma unroll
                     for (int w2 = 0; w2 < NW; ++w2) sum += s_red[buf][w2][tid];
                     const uint32_t slot = s_slot[jl];
-                    if (slot < cap) partials[(size_t)slot * kGradWords + (tid - c * kGradWords)] = sum;
+                    if (slot < cap) {
+                        partials[(size_t)slot * kGradWords + (tid - c * kGradWords)] = sum;
+                        if (tid == c * kGradWords) written[slot] = 1;
+                    }
                 }
             }
             buf ^= 1;
@@ -440,12 +447,13 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
 // reduction slot: the walk finds the next contributing Gaussian, fills slot c
 // (c = 0..5, a separate statically indexed code section each, so the slot
 // values stay in fixed registers), and after six slots the wave transposes and
-// sums them.  Pairs that take no slot get zero partials.  Every take writes all
+// sums them.  Pairs that take no slot are not written (unmarked: zero
+// partials).  Every take writes all
 // ten values of its slot, so nothing is cleared between chunks: the values
 // past the NS filled slots are set to zero here, as constants.
 template <int NS, typename T>
 __device__ __forceinline__ void flush_slots(T (&v)[64], int lane, int lane_slot, const uint32_t (&chunk)[kChunk],
-                                            T* __restrict__ partials, uint32_t cap) {
+                                            T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap) {
 #pragma unroll
     for (int k = NS * kGradWords; k < 64; ++k) v[k] = T(0);
     wave_transpose_sum<T>(v, lane);
@@ -453,7 +461,10 @@ __device__ __forceinline__ void flush_slots(T (&v)[64], int lane, int lane_slot,
         uint32_t slot = chunk[0];
 #pragma unroll
         for (int c = 1; c < NS; ++c) slot = (lane_slot == c) ? chunk[c] : slot;
-        if (slot < cap) partials[(size_t)slot * kGradWords + (lane - lane_slot * kGradWords)] = v[0];
+        if (slot < cap) {
+            partials[(size_t)slot * kGradWords + (lane - lane_slot * kGradWords)] = v[0];
+            if (lane == lane_slot * kGradWords) written[slot] = 1;
+        }
     }
 }
 
@@ -468,7 +479,7 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
     const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
     const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
-    const T* __restrict__ dPt, T* __restrict__ partials, uint32_t cap, uint32_t M) {
+    const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap, uint32_t M) {
     static_assert(TW * TH == kWave, "one wavefront per tile");
     __shared__ __align__(16) T s_sp[kWave * kSplatWords];
     __shared__ uint32_t s_slot[kWave];
@@ -512,8 +523,8 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     // 10% faster than the same walk with its state in vector registers).
     maxlast = __builtin_amdgcn_readfirstlane(maxlast);
     // Pairs behind every pixel's last blended Gaussian, and pairs that
-    // contribute nowhere in the tile, keep the zero partials written before
-    // this kernel.
+    // contribute nowhere in the tile, are not written and stay unmarked
+    // (their partials count as zero).
     const uint32_t hi = (maxlast >= (int)rs) ? (uint32_t)(maxlast + 1) : rs;
     T S = Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
     T v[64];
@@ -650,25 +661,25 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     for (;;) {
         if (!next()) break;
         take(SlotIdx<0>{});
-        if (!next()) { flush_slots<1>(v, lane, lane_slot, chunk, partials, cap); break; }
+        if (!next()) { flush_slots<1>(v, lane, lane_slot, chunk, partials, written, cap); break; }
         take(SlotIdx<1>{});
         if constexpr (NS > 2) {
-            if (!next()) { flush_slots<2>(v, lane, lane_slot, chunk, partials, cap); break; }
+            if (!next()) { flush_slots<2>(v, lane, lane_slot, chunk, partials, written, cap); break; }
             take(SlotIdx<2>{});
         }
         if constexpr (NS > 3) {
-            if (!next()) { flush_slots<3>(v, lane, lane_slot, chunk, partials, cap); break; }
+            if (!next()) { flush_slots<3>(v, lane, lane_slot, chunk, partials, written, cap); break; }
             take(SlotIdx<3>{});
         }
         if constexpr (NS > 4) {
-            if (!next()) { flush_slots<4>(v, lane, lane_slot, chunk, partials, cap); break; }
+            if (!next()) { flush_slots<4>(v, lane, lane_slot, chunk, partials, written, cap); break; }
             take(SlotIdx<4>{});
         }
         if constexpr (NS > 5) {
-            if (!next()) { flush_slots<5>(v, lane, lane_slot, chunk, partials, cap); break; }
+            if (!next()) { flush_slots<5>(v, lane, lane_slot, chunk, partials, written, cap); break; }
             take(SlotIdx<5>{});
         }
-        flush_slots<NS>(v, lane, lane_slot, chunk, partials, cap);
+        flush_slots<NS>(v, lane, lane_slot, chunk, partials, written, cap);
     }
 }
 
@@ -702,14 +713,14 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
         hipLaunchKernelGGL((render_backward_wave_kernel<T, TW, TH>), dim3(blocks), dim3(kWave), 0, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.rects, s.offsets, s.pair_vals[0], s.ranges, s.schedule,
                            (const T*)img.t_final, img.last, img.target, (const T*)g.d_color, (const T*)g.d_depth,
-                           (const T*)g.d_t_final, (const T*)g.d_probs, (const T*)g.d_p_target, (T*)s.partials,
+                           (const T*)g.d_t_final, (const T*)g.d_probs, (const T*)g.d_p_target, (T*)s.partials, s.written,
                            (uint32_t)s.capacity, (uint32_t)s.items);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((render_backward_kernel<T, TW, TH>), dim3(blocks), dim3(TW * TH), 0, st, f.views, f.consts,
                        f.K, (const T*)s.splats, s.rects, s.offsets, s.pair_vals[0], s.ranges, s.schedule,
                        (const T*)img.t_final, img.last, img.target, (const T*)g.d_color, (const T*)g.d_depth,
-                       (const T*)g.d_t_final, (const T*)g.d_probs, (const T*)g.d_p_target, (T*)s.partials,
+                       (const T*)g.d_t_final, (const T*)g.d_probs, (const T*)g.d_p_target, (T*)s.partials, s.written,
                        (uint32_t)s.capacity, (uint32_t)s.items);
     return hipGetLastError();
 }
