@@ -30,7 +30,7 @@ FLOP_PER_BLENDED = 46.0    # gradient of one blended (pixel, Gaussian) incl. its
 # HBM bytes per launch of the render backward from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (scaled by a 256 MiB copy: x2.000 and x1.000), valid only for the kernel source
 # they were taken with (see profiles/); reported as null otherwise.
-MEASURED_TRAFFIC = {"render_src_sha256_16": "0ca37abb87a4c9f7", "bytes_per_launch": 182117717}
+MEASURED_TRAFFIC = {"render_src_sha256_16": "2e06520c67374b27", "bytes_per_launch": 203259050}
 
 
 def measured_traffic():
@@ -500,7 +500,8 @@ def main():
     E, Bn = backward_work(tr)
     flops = FLOP_PER_EXAMINED * E + FLOP_PER_BLENDED * Bn
     achieved = flops / (bwd_ms * 1e-3) / 1e12
-    roof = dict(bound="alu", kernel=f"render_backward_kernel<float,{tw},{th}>", achieved=round(achieved, 3),
+    roof = dict(bound="alu", kernel=(f"render_backward_wave_kernel<float,{tw},{th}>" if tw * th == 64
+                                     else f"render_backward_kernel<float,{tw},{th}>"), achieved=round(achieved, 3),
                 peak=MI355X_FP32_VECTOR_TFLOPS, unit="TFLOP/s", frac=round(achieved / MI355X_FP32_VECTOR_TFLOPS, 4),
                 traffic=measured_traffic(), avg_ms=round(bwd_ms, 4), examined_pairs=E, blended_pairs=Bn,
                 flop_per_examined=FLOP_PER_EXAMINED, flop_per_blended=FLOP_PER_BLENDED)

@@ -32,7 +32,10 @@ constexpr int kPairTile = kSortThreads * kPairIpt;
 // Scan + emission: one record per thread, 1024 per block, so that each of the
 // 16 wavefronts emits the pairs of its own 64 records.
 constexpr int kScanThreads = 1024;
-constexpr int kScanIpt = 1;
+#ifndef DQO_SCAN_IPT
+#define DQO_SCAN_IPT 1
+#endif
+constexpr int kScanIpt = DQO_SCAN_IPT;
 constexpr int kScanTile = kScanThreads * kScanIpt;
 constexpr int kMaxDepthPasses = 4;
 constexpr int kMaxPairPasses = 4;
