@@ -85,7 +85,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.items = (int64_t)d->n * d->n_views;
     const int64_t M = g.items, cap = d->pair_capacity;
     const int64_t ts = d->dtype == DQO_F64 ? 8 : 4;
-    g.depth_blocks = (int)((M + kDepthTile - 1) / kDepthTile);
+    g.depth_blocks = (int)((M + kSortThreads * depth_ipt(M) - 1) / (kSortThreads * depth_ipt(M)));
     g.scan_blocks = (int)((M + kScanTile - 1) / kScanTile);
     g.pair_blocks = (int)((cap + kPairTile - 1) / kPairTile);
     int64_t sz[DQO_BUF_COUNT];

@@ -19,23 +19,18 @@ constexpr int kSortThreads = 256;
 // Items per thread of a radix pass.  The decoupled look-back costs one memory
 // latency per window of preceding blocks, so longer blocks shorten the chain
 // but lengthen each block's own ranking.  Measured on one MI355X: the pair
-// passes (1.6M pairs of one 640x480 view, 9.6M of eight) are as fast or faster
+// passes (1.5M pairs of one 640x480 view, 49M of eight) are as fast or faster
 // with 8192-item blocks (eight keyframes: 163 -> 175 it/s); the depth passes
-// are faster with 4096-item blocks at 200k items (8192: 1650 -> 1573 it/s) and
-// with 8192-item blocks from about a million (175 -> 180 it/s at 9.6M).
-constexpr int kSortIptMin = 16;  // the shortest blocks: sizes the look-back arrays
+// are fastest with 2048-item blocks at 200k items (4096: 1700 -> 1672 it/s,
+// 8192: slower still) and with 8192-item blocks from about a million (175 ->
+// 180 it/s at 9.6M); 4096 in between.
 constexpr int kPairIpt = 32;
-constexpr int64_t kDepthLongBlocks = int64_t(1) << 19;  // items from which depth passes use 8192-item blocks
-inline int depth_ipt(int64_t items) { return items >= kDepthLongBlocks ? 32 : kSortIptMin; }
-constexpr int kDepthTile = kSortThreads * kSortIptMin;
+inline int depth_ipt(int64_t items) { return items < (int64_t(1) << 18) ? 8 : items < (int64_t(1) << 19) ? 16 : 32; }
 constexpr int kPairTile = kSortThreads * kPairIpt;
 // Scan + emission: one record per thread, 1024 per block, so that each of the
 // 16 wavefronts emits the pairs of its own 64 records.
 constexpr int kScanThreads = 1024;
-#ifndef DQO_SCAN_IPT
-#define DQO_SCAN_IPT 1
-#endif
-constexpr int kScanIpt = DQO_SCAN_IPT;
+constexpr int kScanIpt = 1;  // 2 and 4 measured slower at 200k items (1646 -> 1627 / 1573 it/s)
 constexpr int kScanTile = kScanThreads * kScanIpt;
 constexpr int kMaxDepthPasses = 4;
 constexpr int kMaxPairPasses = 4;
@@ -278,6 +273,20 @@ hipError_t launch_fit_quadric(int n_obj, int64_t n_boxes, const double* boxes, c
 hipError_t launch_clear_ctrl(Ctrl* ctrl, uint64_t* lb, int64_t lb_words, hipStream_t st);
 hipError_t launch_clear_status(Ctrl* ctrl, hipStream_t st);
 hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t st);
+
+// Workgroups of Kernel (at Threads per group, no dynamic LDS) that the
+// current device holds at once, computed once per kernel; 0 if unknown.
+template <auto Kernel, int Threads>
+inline int resident_blocks() {
+    static const int n = [] {
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, Kernel, Threads, 0) != hipSuccess) return 0;
+        return per_cu * prop.multiProcessorCount;
+    }();
+    return n;
+}
 hipError_t launch_clear_written(const StatePtrs& s, hipStream_t st);
 hipError_t launch_associate(int n_obj, const double* mu, const double* R, const double* ax, int64_t n_det,
                             const double* boxes, const int32_t* det_frame, int n_frames, const double* P,

@@ -181,10 +181,13 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
 }
 
 // Scan of the tile counts in depth order and emission of (tile, item) pairs.
+// The scan's look-back orders blocks by workgroup index when the grid is
+// resident at once, else by an atomic ticket (as the radix passes do).
 __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts, const short4* __restrict__ rects,
     uint32_t* __restrict__ offsets, uint32_t* __restrict__ pkeys, uint32_t* __restrict__ pvals, uint32_t M,
-    uint32_t cap, int64_t n, int tiles_x, int tiles_per_view, int pair_passes, int copies, uint64_t* lb, Ctrl* ctrl) {
+    uint32_t cap, int64_t n, int tiles_x, int tiles_per_view, int pair_passes, int copies, uint64_t* lb, Ctrl* ctrl,
+    bool ticket) {
     __shared__ uint32_t s_incl[kScanTile];
     __shared__ uint32_t s_rec[kScanTile];
     __shared__ uint32_t s_tbase[kScanTile];
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     __shared__ uint32_t s_tmp[kScanThreads / kWave];
     __shared__ uint32_t s_base, s_bid, s_agg;
     const int tid = threadIdx.x;
-    if (tid == 0) s_bid = atomicAdd(&ctrl->counters[kCounterScan], 1u);
+    if (tid == 0) s_bid = ticket ? atomicAdd(&ctrl->counters[kCounterScan], 1u) : blockIdx.x;
     if (tid < kRadixBins) {
         for (int p = 0; p < kMaxPairPasses; ++p) s_hist[p][tid] = 0u;
     }
@@ -334,7 +337,8 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
     hipLaunchKernelGGL(scan_emit_kernel, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st, s.depth_vals[0],
                        s.counts, s.rects, s.offsets, s.pair_keys[pf], s.pair_vals[pf], (uint32_t)M,
                        (uint32_t)s.capacity, f.n, f.views.tiles_x, f.views.tiles_per_view, s.pair_passes,
-                       s.hist_copies_pair, s.lb_scan, s.ctrl);
+                       s.hist_copies_pair, s.lb_scan, s.ctrl,
+                       s.scan_blocks > resident_blocks<scan_emit_kernel, kScanThreads>());  // order as the radix passes
     return hipGetLastError();
 }
 

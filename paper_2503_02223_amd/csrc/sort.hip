@@ -2,9 +2,12 @@
 //
 // A pass reads 256 x IPT (key, value) items per block, ranks them stably inside the
 // block with wave-wide match ballots, obtains the block's global offset per
-// digit by decoupled look-back over the preceding blocks (block order is taken
-// from an atomic ticket, so every block it waits on is already running), then
-// writes the items out digit-sorted through LDS so stores are coalesced.
+// digit by decoupled look-back over the preceding blocks, then writes the
+// items out digit-sorted through LDS so stores are coalesced.  Block order is
+// the workgroup index when the whole grid fits on the device at once (every
+// block it waits on is then running); otherwise it is taken from an atomic
+// ticket, so that every block waited on has started.  The ticket costs a
+// contended global atomic per block (2.5 us at 383 blocks, measured).
 // Digit histograms of every pass are accumulated before the first pass by the
 // kernel that produced the keys.
 #include <algorithm>
@@ -32,7 +35,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
-    if (tid == 0) s_bid = atomicAdd(counter, 1u);
+    if (tid == 0) s_bid = counter ? atomicAdd(counter, 1u) : blockIdx.x;
 #pragma unroll
     for (int w = 0; w < kSortThreads / kWave; ++w) s_wcnt[w][tid] = 0;
     __syncthreads();
@@ -175,7 +178,16 @@ hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
                              hipStream_t st, int ipt) {
     if (n_host == 0) return hipSuccess;
     const int blocks = (int)((n_host + kSortThreads * ipt - 1) / (kSortThreads * ipt));
-    if (ipt == 16)
+    if (ipt != 8 && ipt != 16 && ipt != 32) return hipErrorInvalidValue;
+    const int resident = ipt == 8    ? resident_blocks<radix_pass_kernel<8>, kSortThreads>()
+                         : ipt == 16 ? resident_blocks<radix_pass_kernel<16>, kSortThreads>()
+                                     : resident_blocks<radix_pass_kernel<32>, kSortThreads>();
+    if (blocks <= resident)
+        counter = nullptr;  // the whole grid is resident: workgroup index order
+    if (ipt == 8)
+        hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
+                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
+    else if (ipt == 16)
         hipLaunchKernelGGL(radix_pass_kernel<16>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
                            n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
     else if (ipt == 32)
