@@ -136,40 +136,48 @@ __global__ __launch_bounds__(256) void tile_bounds_kernel(const uint32_t* __rest
     }
 }
 
-// Launch order of the render workgroups: tiles by decreasing pair count (in
-// power-of-two classes).  Workgroups are dispatched in index order and spread
-// round-robin over the XCDs and CUs, so the heaviest tiles, which are
-// spatially clustered, start first and on different compute units instead of
-// queueing on the same ones.  Order inside a class is arbitrary; results do
-// not depend on it (every tile writes only its own pixels and pair slots).
+// Launch order of the render workgroups: tiles by decreasing pair count.
+// Workgroups are dispatched in index order and spread round-robin over the
+// XCDs and CUs, so the heaviest tiles, which are spatially clustered, start
+// first and on different compute units instead of queueing on the same ones,
+// and the launch ends with the lightest.  Counts are exact up to 4095 (larger
+// ones share the top bin).  Against power-of-two classes of the count (tiles
+// of a class in index order), the exact order made the backward replayed on
+// its own at the 200k view 5% faster and the forward 6%; inside the whole
+// training step the difference was within run-to-run noise.  Order among
+// equal counts is arbitrary; results do not depend on the order (every tile
+// writes only its own pixels and pair slots).
 constexpr int kSchedThreads = 1024;
-constexpr int kSchedClasses = 33;
+constexpr int kSchedBins = 4096;
 
 __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint32_t* __restrict__ ranges,
                                                                      int tiles, uint32_t* __restrict__ schedule) {
-    __shared__ uint32_t s_cnt[kSchedClasses];
-    __shared__ uint32_t s_off[kSchedClasses];
+    __shared__ uint32_t s_cnt[kSchedBins];  // bin b holds count kSchedBins - 1 - b (descending order)
+    __shared__ uint32_t s_tmp[kSchedThreads / kWave];
+    constexpr int kPer = kSchedBins / kSchedThreads;
     const int tid = threadIdx.x;
-    if (tid < kSchedClasses) s_cnt[tid] = 0u;
+    for (int b = tid; b < kSchedBins; b += kSchedThreads) s_cnt[b] = 0u;
     __syncthreads();
-    for (int t = tid; t < tiles; t += kSchedThreads) {
+    auto bin_of = [&](int t) {
         const uint32_t w = ranges[2 * t + 1] - ranges[2 * t];
-        atomicAdd(&s_cnt[w ? 32 - __clz(w) : 0], 1u);
+        return kSchedBins - 1 - (int)min(w, (uint32_t)(kSchedBins - 1));
+    };
+    for (int t = tid; t < tiles; t += kSchedThreads) atomicAdd(&s_cnt[bin_of(t)], 1u);
+    __syncthreads();
+    uint32_t c[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        c[k] = s_cnt[tid * kPer + k];
+        sum += c[k];
+    }
+    uint32_t off = block_exclusive_scan<kSchedThreads>(sum, s_tmp);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        s_cnt[tid * kPer + k] = off;
+        off += c[k];
     }
     __syncthreads();
-    if (tid == 0) {
-        uint32_t off = 0;
-        for (int c = kSchedClasses - 1; c >= 0; --c) {
-            s_off[c] = off;
-            off += s_cnt[c];
-        }
-    }
-    __syncthreads();
-    for (int t = tid; t < tiles; t += kSchedThreads) {
-        const uint32_t w = ranges[2 * t + 1] - ranges[2 * t];
-        const uint32_t pos = atomicAdd(&s_off[w ? 32 - __clz(w) : 0], 1u);
-        schedule[pos] = (uint32_t)t;
-    }
+    for (int t = tid; t < tiles; t += kSchedThreads) schedule[atomicAdd(&s_cnt[bin_of(t)], 1u)] = (uint32_t)t;
 }
 
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
