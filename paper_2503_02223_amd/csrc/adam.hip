@@ -9,57 +9,65 @@
 
 namespace dqo {
 
-// Step size and 1/sqrt(bc2) of this row: from the host, or from the device
-// step counter (computed once per workgroup).
+// One thread per column (four columns with float4 when the rows allow it),
+// all rows of that column in an unrolled loop, so that every per-row value is
+// read at a constant index.  The step sizes come from the host, or from the
+// device step counter (computed once per workgroup into LDS).
 template <typename T>
-__device__ __forceinline__ void step_factors(const AdamArgs<T>& a, const int64_t* d_step, int row, T& ss, T& isb) {
-    if (!d_step) {
-        ss = a.step_size[row];
-        isb = a.inv_sqrt_bc2;
-        return;
-    }
-    __shared__ T s_f[2];
-    if (threadIdx.x == 0) device_step_factors<T>(a, *d_step, row, s_f[0], s_f[1]);
+__device__ __forceinline__ void row_factors(const AdamArgs<T>& a, const int64_t* d_step, T* s_ss, T* s_isb) {
+    if (!d_step) return;
+    if (threadIdx.x == 0) device_step_table<T>(a, *d_step, s_ss, s_isb);
     __syncthreads();
-    ss = s_f[0];
-    isb = s_f[1];
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void adam_kernel(T* __restrict__ p, const T* __restrict__ g, T* __restrict__ m,
-                                                   T* __restrict__ v, int64_t n, AdamArgs<T> a,
+                                                   T* __restrict__ v, int64_t n, int rows, AdamArgs<T> a,
                                                    const int64_t* __restrict__ d_step) {
-    const int row = blockIdx.y;
-    T ss, isb;
-    step_factors(a, d_step, row, ss, isb);
-    const int64_t base = (int64_t)row * n;
+    __shared__ T s_ss[kParams];
+    __shared__ T s_isb;
+    row_factors(a, d_step, s_ss, &s_isb);
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        T pp = p[base + i], mm = m[base + i], vv = v[base + i];
-        adam_one(pp, g[base + i], mm, vv, ss, isb, a);
-        p[base + i] = pp;
-        m[base + i] = mm;
-        v[base + i] = vv;
+#pragma unroll
+        for (int r = 0; r < kParams; ++r) {
+            if (r >= rows) break;
+            const T ss = d_step ? s_ss[r] : a.step_size[r];
+            const T isb = d_step ? s_isb : a.inv_sqrt_bc2;
+            const int64_t k = (int64_t)r * n + i;
+            T pp = p[k], mm = m[k], vv = v[k];
+            adam_one(pp, g[k], mm, vv, ss, isb, a);
+            p[k] = pp;
+            m[k] = mm;
+            v[k] = vv;
+        }
     }
 }
 
-// float4 path when rows are 16-byte aligned (n % 4 == 0).
+// float4 path when rows are 16-byte aligned (n % 4 == 0); n4 = n / 4.
 __global__ __launch_bounds__(256) void adam_kernel_vec4(float4* __restrict__ p, const float4* __restrict__ g,
                                                         float4* __restrict__ m, float4* __restrict__ v, int64_t n4,
-                                                        AdamArgs<float> a, const int64_t* __restrict__ d_step) {
-    const int row = blockIdx.y;
-    float ss, isb;
-    step_factors(a, d_step, row, ss, isb);
-    const int64_t base = (int64_t)row * n4;
+                                                        int rows, AdamArgs<float> a,
+                                                        const int64_t* __restrict__ d_step) {
+    __shared__ float s_ss[kParams];
+    __shared__ float s_isb;
+    row_factors(a, d_step, s_ss, &s_isb);
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256) {
-        float4 pp = p[base + i], mm = m[base + i], vv = v[base + i];
-        const float4 gg = g[base + i];
-        adam_one(pp.x, gg.x, mm.x, vv.x, ss, isb, a);
-        adam_one(pp.y, gg.y, mm.y, vv.y, ss, isb, a);
-        adam_one(pp.z, gg.z, mm.z, vv.z, ss, isb, a);
-        adam_one(pp.w, gg.w, mm.w, vv.w, ss, isb, a);
-        p[base + i] = pp;
-        m[base + i] = mm;
-        v[base + i] = vv;
+#pragma unroll
+        for (int r = 0; r < kParams; ++r) {
+            if (r >= rows) break;
+            const float ss = d_step ? s_ss[r] : a.step_size[r];
+            const float isb = d_step ? s_isb : a.inv_sqrt_bc2;
+            const int64_t k = (int64_t)r * n4 + i;
+            float4 pp = p[k], mm = m[k], vv = v[k];
+            const float4 gg = g[k];
+            adam_one(pp.x, gg.x, mm.x, vv.x, ss, isb, a);
+            adam_one(pp.y, gg.y, mm.y, vv.y, ss, isb, a);
+            adam_one(pp.z, gg.z, mm.z, vv.z, ss, isb, a);
+            adam_one(pp.w, gg.w, mm.w, vv.w, ss, isb, a);
+            p[k] = pp;
+            m[k] = mm;
+            v[k] = vv;
+        }
     }
 }
 
@@ -76,18 +84,19 @@ hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, const dqo_adam& 
     bool vec = sizeof(T) == 4 && (n % 4) == 0 && ((uintptr_t)p % 16) == 0 && ((uintptr_t)g % 16) == 0 &&
                ((uintptr_t)m % 16) == 0 && ((uintptr_t)v % 16) == 0;
     const int64_t len = vec ? n / 4 : n;
+    if (rows < 1 || rows > kParams) return hipErrorInvalidValue;
     int gx = (int)((len + 255) / 256);
-    if (gx > 4096) gx = 4096;
+    if (gx > 8192) gx = 8192;
     bool done = false;
     if constexpr (sizeof(T) == 4) {
         if (vec) {
-            hipLaunchKernelGGL(adam_kernel_vec4, dim3(gx, rows), dim3(256), 0, st, (float4*)p, (const float4*)g,
-                               (float4*)m, (float4*)v, len, a, (const int64_t*)d_step);
+            hipLaunchKernelGGL(adam_kernel_vec4, dim3(gx), dim3(256), 0, st, (float4*)p, (const float4*)g,
+                               (float4*)m, (float4*)v, len, rows, a, (const int64_t*)d_step);
             done = true;
         }
     }
     if (!done)
-        hipLaunchKernelGGL(adam_kernel<T>, dim3(gx, rows), dim3(256), 0, st, p, g, m, v, n, a,
+        hipLaunchKernelGGL(adam_kernel<T>, dim3(gx), dim3(256), 0, st, p, g, m, v, n, rows, a,
                            (const int64_t*)d_step);
     if (d_step) hipLaunchKernelGGL(step_increment_kernel, dim3(1), dim3(1), 0, st, d_step);
     return hipGetLastError();

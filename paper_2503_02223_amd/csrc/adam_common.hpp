@@ -47,14 +47,18 @@ __device__ __forceinline__ void adam_one(T& p, T g, T& m, T& v, T ss, T isb, con
     p = p - ss * (m / denom);
 }
 
-// Step size of `row` and 1/sqrt(bc2) for step t = prev + 1 (device step counter).
+// Step sizes of every row and 1/sqrt(bc2) for step t = prev + 1 (device step
+// counter), computed by one thread.  Rows are indexed with constants only: a
+// kernel argument array indexed at run time is copied to per-thread scratch
+// by every thread (216 bytes each, measured to nearly triple the Adam time).
 template <typename T>
-__device__ __forceinline__ void device_step_factors(const AdamArgs<T>& a, int64_t prev, int row, T& ss, T& isb) {
+__device__ __forceinline__ void device_step_table(const AdamArgs<T>& a, int64_t prev, T* ss, T* isb) {
     const double t = (double)(prev + 1);
     const double bc1 = 1.0 - pow(a.beta1, t);
     const double bc2 = 1.0 - pow(a.beta2, t);
-    ss = (T)(a.lr[row] / bc1);
-    isb = (T)(1.0 / sqrt(bc2));
+#pragma unroll
+    for (int r = 0; r < kParams; ++r) ss[r] = (T)(a.lr[r] / bc1);
+    *isb = (T)(1.0 / sqrt(bc2));
 }
 
 }  // namespace dqo
