@@ -380,11 +380,9 @@ int dqo_sort(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     StatePtrs s = state_ptrs(g, state);
     const int tiles_total = g.L.tiles_x * g.L.tiles_y * d->n_views;
     return run(ctx, "sort", [&] {
-        hipError_t e = launch_pair_sort(s, tiles_total, (hipStream_t)stream);
-        if (e != hipSuccess) return e;
-        // the render backward writes only the pairs that contribute in their
-        // tile, and marks them: the marks start cleared
-        return launch_clear_written(s, (hipStream_t)stream);
+        // also clears the written marks of the pairs (the render backward
+        // writes only the pairs that contribute in their tile, and marks them)
+        return launch_pair_sort(s, tiles_total, (hipStream_t)stream);
     });
 }
 

@@ -124,16 +124,20 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
 
 // [start, end) of every tile that holds pairs, from the boundaries of the
 // sorted pair keys (tiles without pairs keep the empty range written when the
-// frame was projected).
+// frame was projected).  The same pass clears the written marks of the pairs
+// (four one-byte marks per word), which the render backward sets.
 __global__ __launch_bounds__(256) void tile_bounds_kernel(const uint32_t* __restrict__ keys,
                                                           const uint32_t* __restrict__ n_dev, uint32_t n_host,
-                                                          uint32_t* __restrict__ ranges) {
+                                                          uint32_t* __restrict__ ranges,
+                                                          uint32_t* __restrict__ written_words) {
     const uint32_t n = min(*n_dev, n_host);
     for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
         const uint32_t t = keys[i];
         if (i == 0 || keys[i - 1] != t) ranges[2 * t] = i;
         if (i + 1 == n || keys[i + 1] != t) ranges[2 * t + 1] = i + 1;
     }
+    const uint32_t nw = (n + 3u) / 4u;
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < nw; i += gridDim.x * 256u) written_words[i] = 0u;
 }
 
 // Launch order of the render workgroups: tiles by decreasing pair count.
@@ -220,11 +224,13 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
     }
     if (tiles_total > 0) {
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ((int64_t)cap + 255) / 256));
-        hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges);
+        hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges,
+                           (uint32_t*)s.written);
         hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
                            s.schedule);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    return launch_clear_written(s, st);
 }
 
 }  // namespace dqo
