@@ -14,20 +14,26 @@
 // the (tile, depth, index) order with far fewer bytes than sorting 64-bit
 // (tile, depth) keys over all pairs.
 #include "adam_common.hpp"
+#include <algorithm>
+
 #include "dqo_device.hpp"
 #include "sort_common.hpp"
 
 namespace dqo {
 
-__global__ void prep_kernel(Ctrl* ctrl) {
-    const int t = threadIdx.x;
-    if (t == 0) ctrl->epoch = ctrl->epoch + 1u;
-    if (t < kNumCounters) ctrl->counters[t] = 0u;
-    for (int c = 0; c < kHistCopies; ++c) {
-        for (int p = 0; p < kMaxDepthPasses; ++p) ctrl->hist_depth[c][p][t] = 0u;
-        for (int p = 0; p < kMaxPairPasses; ++p) ctrl->hist_pair[c][p][t] = 0u;
+// Starts a frame: new look-back epoch, counters and the histogram copies in
+// use cleared (workgroup c clears copy c of each).
+__global__ __launch_bounds__(256) void prep_kernel(Ctrl* ctrl, int copies_depth, int copies_pair) {
+    const int t = threadIdx.x, c = blockIdx.x;
+    if (c == 0) {
+        if (t == 0) ctrl->epoch = ctrl->epoch + 1u;
+        if (t < kNumCounters) ctrl->counters[t] = 0u;
+        if (t == 0) ctrl->num_pairs = 0u;
     }
-    if (t == 0) ctrl->num_pairs = 0u;
+    if (c < copies_depth)
+        for (int p = 0; p < kMaxDepthPasses; ++p) ctrl->hist_depth[c][p][t] = 0u;
+    if (c < copies_pair)
+        for (int p = 0; p < kMaxPairPasses; ++p) ctrl->hist_pair[c][p][t] = 0u;
 }
 
 template <typename T>
@@ -315,7 +321,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
 template <typename T>
 hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t* ids, hipStream_t st) {
     const StatePtrs& s = f.s;
-    hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(256), 0, st, s.ctrl);
+    hipLaunchKernelGGL(prep_kernel, dim3((unsigned)std::max(1, std::max(s.hist_copies_depth, s.hist_copies_pair))),
+                       dim3(256), 0, st, s.ctrl, s.hist_copies_depth, s.hist_copies_pair);
     const int64_t M = s.items;
     const int64_t range_words = 2 * (int64_t)f.views.tiles_per_view * f.views.n_views;
     if (M == 0) return launch_zero_words(s.ranges, range_words, st);
