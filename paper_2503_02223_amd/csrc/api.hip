@@ -87,7 +87,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     const int64_t ts = d->dtype == DQO_F64 ? 8 : 4;
     g.depth_blocks = (int)((M + kSortThreads * depth_ipt(M) - 1) / (kSortThreads * depth_ipt(M)));
     g.scan_blocks = (int)((M + kScanTile - 1) / kScanTile);
-    g.pair_blocks = (int)((cap + kPairTile - 1) / kPairTile);
+    g.pair_blocks = (int)((cap + kPairTileMin - 1) / kPairTileMin);
     int64_t sz[DQO_BUF_COUNT];
     sz[DQO_BUF_SPLATS] = M * kSplatWords * ts;
     sz[DQO_BUF_RECTS] = M * 8;

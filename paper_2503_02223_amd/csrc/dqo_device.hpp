@@ -18,15 +18,16 @@ constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
 // Items per thread of a radix pass.  The decoupled look-back costs one memory
 // latency per window of preceding blocks, so longer blocks shorten the chain
-// but lengthen each block's own ranking.  Measured on one MI355X: the pair
-// passes (1.5M pairs of one 640x480 view, 49M of eight) are as fast or faster
-// with 8192-item blocks (eight keyframes: 163 -> 175 it/s); the depth passes
-// are fastest with 2048-item blocks at 200k items (4096: 1700 -> 1672 it/s,
-// 8192: slower still) and with 8192-item blocks from about a million (175 ->
-// 180 it/s at 9.6M); 4096 in between.
-constexpr int kPairIpt = 32;
+// but lengthen each block's own ranking and scatter.  Measured on one MI355X:
+// the pair passes take 4096-item blocks while that grid fits on the device at
+// once (1.5M pairs of the 640x480 view: 1761 -> 1788 it/s against 8192) and
+// 8192-item blocks beyond (49M pairs of eight keyframes: 163 -> 175 it/s); the
+// depth passes are fastest with 2048-item blocks at 200k items (4096: 1700 ->
+// 1672 it/s, 8192 slower still) and with 8192-item blocks from about a
+// million (175 -> 180 it/s at 9.6M); 4096 in between.
+constexpr int kPairIptShort = 16, kPairIptLong = 32;
+constexpr int kPairTileMin = kSortThreads * kPairIptShort;  // sizes the pair look-back arrays
 inline int depth_ipt(int64_t items) { return items < (int64_t(1) << 18) ? 8 : items < (int64_t(1) << 19) ? 16 : 32; }
-constexpr int kPairTile = kSortThreads * kPairIpt;
 // Scan + emission: one record per thread, 1024 per block, so that each of the
 // 16 wavefronts emits the pairs of its own 64 records.
 constexpr int kScanThreads = 1024;

@@ -213,12 +213,16 @@ hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
 hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st) {
     const uint32_t cap = (uint32_t)s.capacity;
     const uint32_t* n_dev = &s.ctrl->num_pairs;
+    // 4096-item blocks while that grid is resident at once, else 8192
+    const int64_t short_blocks = ((int64_t)cap + kPairTileMin - 1) / kPairTileMin;
+    const int ipt = short_blocks <= resident_blocks<radix_pass_kernel<kPairIptShort>, kSortThreads>() ? kPairIptShort
+                                                                                                       : kPairIptLong;
     int src = s.pair_first_buf;
     for (int p = 0; p < s.pair_passes; ++p) {
         hipError_t e = launch_radix_pass(s.pair_keys[src], s.pair_vals[src], s.pair_keys[src ^ 1],
                                          s.pair_vals[src ^ 1], n_dev, cap, p * kRadixBits,
                                          &s.ctrl->hist_pair[0][p][0], kMaxPairPasses * kRadixBins, s.hist_copies_pair, s.lb_pair + (size_t)p * s.pair_blocks * kRadixBins,
-                                         &s.ctrl->counters[kCounterPair + p], s.ctrl, st, kPairIpt);
+                                         &s.ctrl->counters[kCounterPair + p], s.ctrl, st, ipt);
         if (e != hipSuccess) return e;
         src ^= 1;
     }
