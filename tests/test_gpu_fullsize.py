@@ -86,3 +86,42 @@ def test_fullsize_sampled_backward(oracle, room):
     assert touched.sum() > 500
     close(g[:, touched], go[:, touched], GRAD_RTOL, what="sampled-pixel grads")
     assert np.abs(g[:, ~touched]).max() == 0.0
+
+
+def test_sort_order_on_grids_too_large_to_be_resident():
+    """Eight keyframes over 1.2M Gaussians (9.6M items, tens of millions of
+    pairs): the radix passes and the scan run more workgroups than the device
+    holds at once, so blocks take their order from the atomic ticket.  The
+    depth order must be the stable sort of the depth keys, and the pair list
+    the stable (tile, depth bits, index) order with exact tile ranges."""
+    sc = scenes.keyframe_scene(seed=0)
+    n, V = sc["params"].shape[1], len(sc["cams"])
+    r = B.Rasterizer(sc["cams"], n, sc["K"], ctx=B.Context(tile_w=16, tile_h=8))
+    p = to_dev(sc["params"])
+    ids = torch.tensor(sc["ids"], device="cuda")
+    r.bin(p, ids, grow=True)
+    f = r.frame
+    torch.cuda.synchronize()
+    rc, st, P = f.read_status()
+    M = n * V
+    assert rc == 0 and st == 0 and P > 8 * 1024 * 1024      # far beyond one resident grid
+    dk = f.buf("depth_keys", torch.int32, M).cpu().numpy().view(np.uint32).astype(np.int64)
+    do = f.buf("depth_order", torch.int32, M).cpu().numpy().astype(np.int64)
+    assert (np.sort(do) == np.arange(M)).all()
+    assert (np.diff(dk) >= 0).all()
+    ties = np.diff(dk) == 0
+    assert (np.diff(do)[ties] > 0).all()                     # stable: equal keys keep item order
+    keys = f.buf("pair_keys", torch.int32, P).cpu().numpy().astype(np.int64)
+    vals = f.buf("pair_vals", torch.int32, P).cpu().numpy().astype(np.int64)
+    assert (np.diff(keys) >= 0).all()
+    rank = np.empty(M, np.int64)
+    rank[do] = np.arange(M)                                  # position of each item in depth order
+    same = np.diff(keys) == 0
+    assert (np.diff(rank[vals])[same] > 0).all()             # within a tile: depth order, ties by index
+    rng = f.buf("ranges", torch.int32).cpu().numpy().reshape(-1, 2).astype(np.int64)
+    starts = np.flatnonzero(np.r_[True, keys[1:] != keys[:-1]])
+    ends = np.r_[starts[1:], P]
+    t = keys[starts]
+    assert (rng[t, 0] == starts).all() and (rng[t, 1] == ends).all()
+    empty = np.setdiff1d(np.arange(rng.shape[0]), t)
+    assert (rng[empty, 0] == rng[empty, 1]).all()
