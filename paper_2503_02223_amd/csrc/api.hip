@@ -33,7 +33,8 @@ struct Geo {
     int depth_blocks, scan_blocks, pair_blocks, pair_passes, pair_first_buf;
     int64_t lb_words;
     // scratch sub-offsets (relative to DQO_BUF_SCRATCH)
-    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_lbd, off_lbs, off_lbp;
+    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_sbase, off_lbd, off_lbs,
+        off_lbp;
 };
 
 int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams) {
@@ -109,6 +110,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.off_sums = so; so = align256(so + M * kGradWords * ts);
     g.off_pose = so; so = align256(so + (int64_t)d->n_views * ((d->n + 255) / 256) * 6 * 8);
     g.off_written = so; so = align256(so + cap);
+    g.off_sbase = so; so = align256(so + (int64_t)g.scan_blocks * 4);
     g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * g.depth_blocks * kRadixBins * 8);
     g.off_lbs = so; so = align256(so + (int64_t)g.scan_blocks * 8);
     g.off_lbp = so; so = align256(so + (int64_t)kMaxPairPasses * g.pair_blocks * kRadixBins * 8);
@@ -146,6 +148,7 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.sums = sc + g.off_sums;
     s.pose_partials = (double*)(sc + g.off_pose);
     s.written = (uint8_t*)(sc + g.off_written);
+    s.scan_base = (uint32_t*)(sc + g.off_sbase);
     s.ctrl = (Ctrl*)(b + g.L.offset[DQO_BUF_CONTROL]);
     s.lb_depth = (uint64_t*)(sc + g.off_lbd);
     s.lb_scan = (uint64_t*)(sc + g.off_lbs);

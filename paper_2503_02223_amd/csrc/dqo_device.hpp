@@ -39,7 +39,6 @@ constexpr int kLossBlocks = 512;
 
 // Counter slots in the control block (dynamic block index per look-back chain).
 constexpr int kCounterDepth = 0;   // + pass
-constexpr int kCounterScan = 4;
 constexpr int kCounterPair = 5;    // + pass
 constexpr int kCounterAdam = 12;   // workgroups done in the fused project-backward + Adam
 constexpr int kNumCounters = 16;
@@ -224,6 +223,7 @@ struct StatePtrs {
     void* sums;           // [V*n][kGradWords] per-item totals of the pair partials
     double* pose_partials;  // [V][ceil(n/256)][6] per-block camera-pose gradient sums
     uint8_t* written;     // [cap] 1 where the render backward wrote the pair's partials
+    uint32_t* scan_base;  // [scan blocks] pair offset of each scan block (two-level scan)
     Ctrl* ctrl;
     uint64_t* lb_depth;   // [kMaxDepthPasses][blocks][256]
     uint64_t* lb_scan;    // [blocks]

@@ -187,13 +187,59 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
 }
 
 // Scan of the tile counts in depth order and emission of (tile, item) pairs.
-// The scan's look-back orders blocks by workgroup index when the grid is
-// resident at once, else by an atomic ticket (as the radix passes do).
+// When the grid fits on the device at once, each block obtains its offset by
+// decoupled look-back (blocks ordered by workgroup index).  Larger grids would
+// wait on a chain as long as the grid (measured at 9.6M items: most of the
+// kernel's 626 us), so they scan in two levels first: the pair count of every
+// block, then one workgroup's scan of those counts; the emission then reads
+// its block's offset and waits on nothing.
+__global__ __launch_bounds__(kScanThreads) void scan_block_sums_kernel(const uint32_t* __restrict__ order,
+                                                                      const uint32_t* __restrict__ counts, uint32_t M,
+                                                                      uint32_t* __restrict__ sums) {
+    __shared__ uint32_t s_tmp[kScanThreads / kWave];
+    const int tid = threadIdx.x;
+    const uint32_t base = blockIdx.x * (uint32_t)kScanTile;
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        const uint32_t q = base + tid * kScanIpt + k;
+        if (q < M) v += counts[min(order[q], M - 1)];
+    }
+    const uint32_t excl = block_exclusive_scan<kScanThreads>(v, s_tmp);
+    if (tid == kScanThreads - 1) sums[blockIdx.x] = excl + v;
+}
+
+// Exclusive scan of the block counts in place (one workgroup), the pair total
+// and the overflow flag.
+__global__ __launch_bounds__(kScanThreads) void scan_block_base_kernel(uint32_t* __restrict__ sums, int nblocks,
+                                                                      uint32_t cap, Ctrl* __restrict__ ctrl) {
+    __shared__ uint32_t s_tmp[kScanThreads / kWave];
+    __shared__ uint32_t s_carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_carry = 0u;
+    __syncthreads();
+    for (int c0 = 0; c0 < nblocks; c0 += kScanThreads) {
+        const int i = c0 + tid;
+        const uint32_t v = i < nblocks ? sums[i] : 0u;
+        const uint32_t excl = block_exclusive_scan<kScanThreads>(v, s_tmp);
+        const uint32_t carry = s_carry;
+        if (i < nblocks) sums[i] = carry + excl;
+        __syncthreads();
+        if (tid == kScanThreads - 1) s_carry = carry + excl + v;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const uint32_t total = s_carry;
+        ctrl->num_pairs = total;
+        if (total > cap) atomicOr(&ctrl->status, (uint32_t)DQO_STATUS_OVERFLOW);
+    }
+}
+
 __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts, const short4* __restrict__ rects,
     uint32_t* __restrict__ offsets, uint32_t* __restrict__ pkeys, uint32_t* __restrict__ pvals, uint32_t M,
     uint32_t cap, int64_t n, int tiles_x, int tiles_per_view, int pair_passes, int copies, uint64_t* lb, Ctrl* ctrl,
-    bool ticket) {
+    const uint32_t* __restrict__ block_base) {
     __shared__ uint32_t s_incl[kScanTile];
     __shared__ uint32_t s_rec[kScanTile];
     __shared__ uint32_t s_tbase[kScanTile];
@@ -204,7 +250,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     __shared__ uint32_t s_tmp[kScanThreads / kWave];
     __shared__ uint32_t s_base, s_bid, s_agg;
     const int tid = threadIdx.x;
-    if (tid == 0) s_bid = ticket ? atomicAdd(&ctrl->counters[kCounterScan], 1u) : blockIdx.x;
+    if (tid == 0) s_bid = blockIdx.x;
     if (tid < kRadixBins) {
         for (int p = 0; p < kMaxPairPasses; ++p) s_hist[p][tid] = 0u;
     }
@@ -247,12 +293,16 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     __syncthreads();
     const uint32_t agg = s_agg;
     if (tid == 0) {
-        const uint32_t excl = lookback_exclusive(lb, 1, (int)bid, agg, epoch, &ctrl->status);
-        s_base = excl;
-        if (base + kScanTile >= M) {
-            const uint32_t total = excl + agg;
-            ctrl->num_pairs = total;
-            if (total > cap) atomicOr(&ctrl->status, (uint32_t)DQO_STATUS_OVERFLOW);
+        if (block_base) {
+            s_base = block_base[bid];
+        } else {
+            const uint32_t excl = lookback_exclusive(lb, 1, (int)bid, agg, epoch, &ctrl->status);
+            s_base = excl;
+            if (base + kScanTile >= M) {
+                const uint32_t total = excl + agg;
+                ctrl->num_pairs = total;
+                if (total > cap) atomicOr(&ctrl->status, (uint32_t)DQO_STATUS_OVERFLOW);
+            }
         }
     }
     __syncthreads();
@@ -341,11 +391,17 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
         src ^= 1;
     }
     const int pf = s.pair_first_buf;
+    const bool two_level = s.scan_blocks > resident_blocks<scan_emit_kernel, kScanThreads>();
+    if (two_level) {
+        hipLaunchKernelGGL(scan_block_sums_kernel, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st,
+                           s.depth_vals[0], s.counts, (uint32_t)M, s.scan_base);
+        hipLaunchKernelGGL(scan_block_base_kernel, dim3(1), dim3(kScanThreads), 0, st, s.scan_base, s.scan_blocks,
+                           (uint32_t)s.capacity, s.ctrl);
+    }
     hipLaunchKernelGGL(scan_emit_kernel, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st, s.depth_vals[0],
                        s.counts, s.rects, s.offsets, s.pair_keys[pf], s.pair_vals[pf], (uint32_t)M,
                        (uint32_t)s.capacity, f.n, f.views.tiles_x, f.views.tiles_per_view, s.pair_passes,
-                       s.hist_copies_pair, s.lb_scan, s.ctrl,
-                       s.scan_blocks > resident_blocks<scan_emit_kernel, kScanThreads>());  // order as the radix passes
+                       s.hist_copies_pair, s.lb_scan, s.ctrl, two_level ? (const uint32_t*)s.scan_base : nullptr);
     return hipGetLastError();
 }
 
