@@ -189,10 +189,10 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
 // Scan of the tile counts in depth order and emission of (tile, item) pairs.
 // When the grid fits on the device at once, each block obtains its offset by
 // decoupled look-back (blocks ordered by workgroup index).  Larger grids would
-// wait on a chain as long as the grid (measured at 9.6M items: most of the
-// kernel's 626 us), so they scan in two levels first: the pair count of every
-// block, then one workgroup's scan of those counts; the emission then reads
-// its block's offset and waits on nothing.
+// wait on a chain as long as the grid, so they scan in two levels first: the
+// pair count of every block, then one workgroup's scan of those counts; the
+// emission then reads its block's offset and waits on nothing (eight
+// keyframes, 9.6M items: 206 -> 211 training steps/s).
 __global__ __launch_bounds__(kScanThreads) void scan_block_sums_kernel(const uint32_t* __restrict__ order,
                                                                       const uint32_t* __restrict__ counts, uint32_t M,
                                                                       uint32_t* __restrict__ sums) {
