@@ -381,7 +381,7 @@ def bench_learned(args):
     t_data = time.time() - t0
     log(f"crops: {crops_tr.shape[0]} train, {crops_val.shape[0]} validation in {t_data:.1f} s")
     torch.cuda.init()
-    ctx = B.Context()
+    ctx = L.crop_context()
     t0 = time.time()
     rg, lab = L.generate_labels(ctx, crops_tr, iters=args.label_iters, log=log)
     t_labels = time.time() - t0
@@ -512,7 +512,8 @@ def main():
     learned = None
     if not args.no_learned and os.path.exists(LEARNED_MODEL):
         log("time-to-PSNR of the learned initialization on 20 held-out objects")
-        learned, _ = eval_learned(B.Context(), LEARNED_MODEL)
+        from paper_2503_02223_amd import learned as L
+        learned, _ = eval_learned(L.crop_context(), LEARNED_MODEL)
     out = {
         "metric": METRIC, "value": round(1e3 / ms, 2), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",

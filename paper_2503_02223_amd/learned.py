@@ -64,12 +64,19 @@ def he_init(seed):
             for ci, co in zip(NET_CHANNELS[:-1], NET_CHANNELS[1:])]
 
 
+def crop_context() -> B.Context:
+    """Rasterizer context of the 128x128 crops: 8x8 tiles (256 single-wave
+    workgroups per crop instead of 64 four-wave ones at 16x16; the plain
+    optimizer's 300 iterations on a held-out crop measured 0.101 -> 0.068 s)."""
+    return B.Context(tile_w=8, tile_h=8)
+
+
 class Net:
     """The network's parameters (FP32 master copy + BF16 packed copies), Adam
     state and per-batch-shape workspaces, all in device memory."""
 
     def __init__(self, ctx: Optional[B.Context] = None, theta: Optional[np.ndarray] = None, seed=0, device="cuda"):
-        self.ctx = ctx or B.Context()
+        self.ctx = ctx or crop_context()
         self.lay = net_layout()
         self.device = torch.device(device)
         th = pack_layers(he_init(seed), self.lay) if theta is None else np.asarray(theta, np.float32)

@@ -246,7 +246,7 @@ def test_trained_network_reaches_plain_psnr_in_fewer_iterations():
     import os
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2503_02223_amd", "data",
                         "learned_init.npz")
-    ctx = B.Context()
+    ctx = L.crop_context()
     net, _, thr = L.load_model(path, ctx=ctx)
     crops = L.make_crop_set(3, 8)  # the held-out seed of the benchmark
     recs, summary = L.time_to_psnr(ctx, net, thr, crops, iters=300)
