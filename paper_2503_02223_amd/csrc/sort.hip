@@ -227,7 +227,8 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         src ^= 1;
     }
     if (tiles_total > 0) {
-        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ((int64_t)cap + 255) / 256));
+        // one pair per thread, every key load in flight at once
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1 << 20, ((int64_t)cap + 255) / 256));
         hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges,
                            (uint32_t*)s.written);
         hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
