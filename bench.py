@@ -11,6 +11,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -430,7 +431,8 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--workers", type=int, default=16)
-    ap.add_argument("--save", default=os.path.join(ROOT, "gpurun_out", "learned_init.npz"))
+    ap.add_argument("--save", default=os.path.join(tempfile.gettempdir(), "dqo_learned_init.npz"),
+                    help="where the learned-init workload saves the trained model")
     ap.add_argument("--no-learned", action="store_true", help="skip the time-to-PSNR part of the default run")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
