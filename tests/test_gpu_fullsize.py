@@ -111,6 +111,12 @@ def test_sort_order_on_grids_too_large_to_be_resident():
     assert (np.diff(dk) >= 0).all()
     ties = np.diff(dk) == 0
     assert (np.diff(do)[ties] > 0).all()                     # stable: equal keys keep item order
+    # emission offsets: the exclusive scan of the tile counts in depth order (two-level scan here)
+    cnt = f.buf("counts", torch.int32, M).cpu().numpy().astype(np.int64)
+    off = f.buf("offsets", torch.int32, M).cpu().numpy().view(np.uint32).astype(np.int64)
+    c_ord = cnt[do]
+    np.testing.assert_array_equal(off[do], np.cumsum(c_ord) - c_ord)
+    assert c_ord.sum() == P
     keys = f.buf("pair_keys", torch.int32, P).cpu().numpy().astype(np.int64)
     vals = f.buf("pair_vals", torch.int32, P).cpu().numpy().astype(np.int64)
     assert (np.diff(keys) >= 0).all()
