@@ -33,8 +33,9 @@ struct Geo {
     int depth_blocks, scan_blocks, pair_blocks, pair_passes, pair_first_buf;
     int64_t lb_words;
     // scratch sub-offsets (relative to DQO_BUF_SCRATCH)
-    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_sbase, off_lbd, off_lbs,
-        off_lbp;
+    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_sbase, off_seg, off_cbase,
+        off_tlast, off_ckpt, off_lbd, off_lbs, off_lbp;
+    int64_t seg_cap, ckpt_cap;
 };
 
 int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams) {
@@ -111,6 +112,13 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.off_pose = so; so = align256(so + (int64_t)d->n_views * ((d->n + 255) / 256) * 6 * 8);
     g.off_written = so; so = align256(so + cap);
     g.off_sbase = so; so = align256(so + (int64_t)g.scan_blocks * 4);
+    // segment boundaries (64-pixel tiles only): sum over tiles of ceil(range / L) - 1 <= cap / L
+    g.ckpt_cap = tw * th == kWave ? cap / kSegLen + 1 : 0;
+    g.seg_cap = tiles_total + g.ckpt_cap;
+    g.off_seg = so; so = align256(so + g.seg_cap * 4);
+    g.off_cbase = so; so = align256(so + tiles_total * 4);
+    g.off_tlast = so; so = align256(so + tiles_total * 4);
+    g.off_ckpt = so; so = align256(so + g.ckpt_cap * 6 * kWave * ts);
     g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * g.depth_blocks * kRadixBins * 8);
     g.off_lbs = so; so = align256(so + (int64_t)g.scan_blocks * 8);
     g.off_lbp = so; so = align256(so + (int64_t)kMaxPairPasses * g.pair_blocks * kRadixBins * 8);
@@ -149,6 +157,12 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.pose_partials = (double*)(sc + g.off_pose);
     s.written = (uint8_t*)(sc + g.off_written);
     s.scan_base = (uint32_t*)(sc + g.off_sbase);
+    s.seg_list = (uint32_t*)(sc + g.off_seg);
+    s.ckpt_base = (uint32_t*)(sc + g.off_cbase);
+    s.tile_last = (int32_t*)(sc + g.off_tlast);
+    s.ckpt = sc + g.off_ckpt;
+    s.seg_cap = g.seg_cap;
+    s.ckpt_cap = g.ckpt_cap;
     s.ctrl = (Ctrl*)(b + g.L.offset[DQO_BUF_CONTROL]);
     s.lb_depth = (uint64_t*)(sc + g.off_lbd);
     s.lb_scan = (uint64_t*)(sc + g.off_lbs);

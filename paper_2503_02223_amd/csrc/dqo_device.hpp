@@ -30,6 +30,8 @@ constexpr int kPairTileMin = kSortThreads * kPairIptShort;  // sizes the pair lo
 inline int depth_ipt(int64_t items) { return items < (int64_t(1) << 18) ? 8 : items < (int64_t(1) << 19) ? 16 : 32; }
 // Scan + emission: one record per thread, 1024 per block, so that each of the
 // 16 wavefronts emits the pairs of its own 64 records.
+constexpr int kSegLen = 128;       // pairs per backward segment of a 64-pixel tile
+constexpr int kSegMax = 255;       // segments per tile (the last one takes the rest of the range)
 constexpr int kScanThreads = 1024;
 constexpr int kScanIpt = 1;  // 2 and 4 measured slower at 200k items (1646 -> 1627 / 1573 it/s)
 constexpr int kScanTile = kScanThreads * kScanIpt;
@@ -41,6 +43,7 @@ constexpr int kLossBlocks = 512;
 constexpr int kCounterDepth = 0;   // + pass
 constexpr int kCounterPair = 5;    // + pass
 constexpr int kCounterAdam = 12;   // workgroups done in the fused project-backward + Adam
+constexpr int kCounterSegTotal = 13;  // entries in the backward's segment list
 constexpr int kNumCounters = 16;
 constexpr int kHistCopies = 16;
 constexpr int kProjItems = 4;      // items per thread of the projection kernel
@@ -85,6 +88,13 @@ struct Consts {
     T z_near, dilation, q_max, alpha_min, alpha_max, t_min;
     T bg[3];
 };
+
+// Segments of a tile's pair range for the segmented backward (0 for an empty
+// tile); the last one takes the rest of the range when a tile has more than
+// kSegMax.
+__device__ __forceinline__ uint32_t tile_segments(uint32_t range) {
+    return min((range + kSegLen - 1) / (uint32_t)kSegLen, (uint32_t)kSegMax);
+}
 
 // Look-back words: [flag:2 | epoch:30 | value:32].
 constexpr uint64_t kFlagAggregate = 1ull;
@@ -219,6 +229,14 @@ struct StatePtrs {
     uint32_t* pair_vals[2];
     uint32_t* ranges;
     uint32_t* schedule;   // [V*tiles] launch order of the render workgroups
+    // Segmented backward of 64-pixel tiles: a tile's pair range is walked in
+    // segments of kSegLen pairs, one wavefront each, restarted from
+    // per-pixel states the forward stores at the segment boundaries.
+    uint32_t* seg_list;   // [seg_cap] (tile << 8 | segment) in launch order, then ~0u
+    uint32_t* ckpt_base;  // [V*tiles] first boundary record of each tile
+    int32_t* tile_last;   // [V*tiles] last blended position in each tile (forward)
+    void* ckpt;           // [ckpt_cap][6][64] T, colour (3), depth, target probability before each boundary
+    int64_t seg_cap, ckpt_cap;
     void* partials;
     void* sums;           // [V*n][kGradWords] per-item totals of the pair partials
     double* pose_partials;  // [V][ceil(n/256)][6] per-block camera-pose gradient sums
@@ -289,6 +307,7 @@ inline int resident_blocks() {
     return n;
 }
 hipError_t launch_clear_written(const StatePtrs& s, hipStream_t st);
+hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, hipStream_t st);
 hipError_t launch_associate(int n_obj, const double* mu, const double* R, const double* ax, int64_t n_det,
                             const double* boxes, const int32_t* det_frame, int n_frames, const double* P,
                             const int32_t* img_wh, double iou_min, double* iou, int32_t* match, double* occ,

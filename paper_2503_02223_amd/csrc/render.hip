@@ -104,7 +104,8 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule, T* __restrict__ color, T* __restrict__ depth, T* __restrict__ tfinal,
     int32_t* __restrict__ last, T* __restrict__ probs, int32_t* __restrict__ idmap,
     const int32_t* __restrict__ target, T* __restrict__ ptarget, int32_t* __restrict__ nblend, uint32_t cap,
-    uint32_t M) {
+    uint32_t M, const uint32_t* __restrict__ ckpt_base, T* __restrict__ ckpt, uint32_t ckpt_cap,
+    int32_t* __restrict__ tile_last) {
     constexpr int BLOCK = TW * TH;
     __shared__ __align__(16) T s_sp[BLOCK * kSplatWords];
     extern __shared__ unsigned char s_dyn[];
@@ -138,6 +139,23 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     if (rs + BLOCK + tid < re) rec2 = min(pvals[rs + BLOCK + tid], M - 1);
     for (uint32_t b0 = rs; b0 < re; b0 += BLOCK) {
         if (__syncthreads_count(!done) == 0) break;
+        if constexpr (BLOCK == kWave) {
+            // State before each segment boundary of the pair range, for the
+            // segmented backward (which restarts there).
+            const uint32_t rel = b0 - rs;
+            if (ckpt && rel > 0 && rel % kSegLen == 0 && rel / kSegLen < (uint32_t)kSegMax) {
+                const uint32_t e = ckpt_base[tile] + rel / kSegLen - 1u;
+                if (e < ckpt_cap) {
+                    T* c = ckpt + (size_t)e * 6 * kWave + tid;
+                    c[0 * kWave] = Tt;
+                    c[1 * kWave] = c0;
+                    c[2 * kWave] = c1;
+                    c[3 * kWave] = c2;
+                    c[4 * kWave] = dd;
+                    c[5 * kWave] = pt;
+                }
+            }
+        }
         if (b0 + tid < re) store_splat_lds<T>(s_sp + tid * kSplatWords, pf);
         __syncthreads();
         if (b0 + BLOCK + tid < re) load_splat<T>(pf, splats + (size_t)rec2 * kSplatWords);
@@ -192,6 +210,15 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
                 done = done || stop;
             }
             if (!wave_any(!done)) break;
+        }
+    }
+    if constexpr (BLOCK == kWave) {
+        if (ckpt) {
+            // The tile's last blended position: how far its backward has work.
+            int m = lastpos;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) m = max(m, __shfl_xor(m, d));
+            if (tid == 0) tile_last[tile] = m;
         }
     }
     if (!inside) return;
@@ -474,18 +501,25 @@ struct SlotIdx {
 };
 
 template <typename T, int TW, int TH>
-__global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
-    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
-    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
-    const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
-    const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
-    const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap, uint32_t M) {
-    static_assert(TW * TH == kWave, "one wavefront per tile");
-    __shared__ __align__(16) T s_sp[kWave * kSplatWords];
-    __shared__ uint32_t s_slot[kWave];
-
+__device__ __forceinline__ void backward_unit(
+    const Views<T>& V, const Consts<T>& cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ schedule, const T* __restrict__ tfinal, const int32_t* __restrict__ last,
+    const int32_t* __restrict__ target, const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT,
+    const T* __restrict__ dP, const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written,
+    uint32_t cap, uint32_t M, const uint32_t* __restrict__ seg_list, const uint32_t* __restrict__ ckpt_base,
+    const T* __restrict__ ckpt, uint32_t ckpt_cap, const T* __restrict__ color, const T* __restrict__ depth,
+    const T* __restrict__ ptarget, T* s_sp, uint32_t* s_slot, uint32_t unit) {
     const int lane = threadIdx.x;
-    const int tile = (int)min(schedule[blockIdx.x], (uint32_t)(gridDim.x - 1));
+    int tile;
+    uint32_t seg = 0u;
+    if (seg_list) {
+        const uint32_t e = seg_list[unit];
+        tile = (int)min(e >> 8, (uint32_t)(V.n_views * V.tiles_per_view - 1));
+        seg = e & 255u;
+    } else {
+        tile = (int)min(schedule[unit], (uint32_t)(gridDim.x - 1));
+    }
     const int view = tile / V.tiles_per_view;
     const int t = tile - view * V.tiles_per_view;
     const int ty = t / V.tiles_x, tx = t - ty * V.tiles_x;
@@ -496,13 +530,21 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     const int64_t o = view * HW + pix;
     const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
     const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
+    uint32_t s0 = rs, s1 = re;
+    if (seg_list) {
+        const uint32_t nseg = tile_segments(re - rs);
+        s0 = min(rs + seg * (uint32_t)kSegLen, re);
+        s1 = (seg + 1u >= nseg) ? re : min(s0 + (uint32_t)kSegLen, re);
+    }
 
     int lastp = -1;
     T Tcur = T(1), gc0 = T(0), gc1 = T(0), gc2 = T(0), gd = T(0), gt = T(0), gpt = T(0);
     int tgt = -2;
+    bool restart = false;
+    T S_restart = T(0);
     if (inside) {
         lastp = last[o];
-        if (lastp < (int)rs || lastp >= (int)re) lastp = -1;  // not from this frame's forward: no work
+        if (lastp < (int)s0 || lastp >= (int)re) lastp = -1;  // nothing in this segment (or not this frame's)
         Tcur = tfinal[o];
         gc0 = dC[(view * 3 + 0) * HW + pix];
         gc1 = dC[(view * 3 + 1) * HW + pix];
@@ -513,6 +555,24 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
             tgt = target[o];
             gpt = dPt[o];
             if (tgt == -1) gt += gpt;
+        }
+        if (lastp >= (int)s1) {
+            // The pixel blends past this segment: restart at its end from the
+            // state the forward stored there.  The sum behind the boundary is
+            // the total minus the part in front of it (colour without the
+            // background term, depth, target probability).
+            const uint32_t e = min(ckpt_base[tile] + seg, ckpt_cap - 1u);
+            const T* c = ckpt + (size_t)e * 6 * kWave + lane;
+            const T Tf = Tcur;
+            const T behind = gc0 * ((color[(view * 3 + 0) * HW + pix] - Tf * cs.bg[0]) - c[1 * kWave]) +
+                             gc1 * ((color[(view * 3 + 1) * HW + pix] - Tf * cs.bg[1]) - c[2 * kWave]) +
+                             gc2 * ((color[(view * 3 + 2) * HW + pix] - Tf * cs.bg[2]) - c[3 * kWave]) +
+                             gd * (depth[o] - c[4 * kWave]) +
+                             (tgt >= 0 ? gpt * (ptarget[o] - c[5 * kWave]) : T(0));
+            S_restart = behind + Tf * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
+            Tcur = c[0];
+            lastp = (int)s1 - 1;
+            restart = true;
         }
     }
     int maxlast = lastp;
@@ -525,8 +585,8 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     // Pairs behind every pixel's last blended Gaussian, and pairs that
     // contribute nowhere in the tile, are not written and stay unmarked
     // (their partials count as zero).
-    const uint32_t hi = (maxlast >= (int)rs) ? (uint32_t)(maxlast + 1) : rs;
-    T S = Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
+    const uint32_t hi = (maxlast >= (int)s0) ? (uint32_t)(maxlast + 1) : s0;
+    T S = restart ? S_restart : Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
     T v[64];
 #pragma unroll
     for (int k = 0; k < 64; ++k) v[k] = T(0);
@@ -544,7 +604,7 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     // Software prefetch: batch A = [a_s, a_e) is held in registers (record and
     // slot) while the current batch is walked; the pair indices of the batch
     // after it (B) are loaded one step earlier still.
-    auto batch_lo = [&](uint32_t e) { return (e - rs > (uint32_t)kWave) ? e - kWave : rs; };
+    auto batch_lo = [&](uint32_t e) { return (e - s0 > (uint32_t)kWave) ? e - kWave : s0; };
     uint32_t a_e = hi, a_s = batch_lo(hi);
     T pf[kSplatWords];
     uint32_t pf_slot = 0u;
@@ -683,6 +743,34 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     }
 }
 
+template <typename T, int TW, int TH>
+__global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
+    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
+    const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
+    const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
+    const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap, uint32_t M,
+    const uint32_t* __restrict__ seg_list, const uint32_t* __restrict__ ckpt_base, const T* __restrict__ ckpt,
+    uint32_t ckpt_cap, const T* __restrict__ color, const T* __restrict__ depth, const T* __restrict__ ptarget,
+    uint32_t* __restrict__ counters) {
+    static_assert(TW * TH == kWave, "one wavefront per tile");
+    __shared__ __align__(16) T s_sp[kWave * kSplatWords];
+    __shared__ uint32_t s_slot[kWave];
+
+    const int lane = threadIdx.x;
+    // One wavefront per tile, or (with a segment list) per listed segment of
+    // a tile's pair range, [s0, s1) of [rs, re); the list is built after the
+    // forward, so its length is read here and the rest of the grid, sized for
+    // the longest possible list, exits at once.  (A resident grid drawing
+    // entries from a work counter was measured slower: the loop around the
+    // walk raised its register demand past the budget and spilled.)
+    const uint32_t n_units = seg_list ? counters[kCounterSegTotal] : gridDim.x;
+    if (blockIdx.x >= n_units) return;
+    backward_unit<T, TW, TH>(V, cs, K, splats, rects, offsets, pvals, ranges, schedule, tfinal, last, target, dC, dD,
+                             dT, dP, dPt, partials, written, cap, M, seg_list, ckpt_base, ckpt, ckpt_cap, color, depth,
+                             ptarget, s_sp, s_slot, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename T, int TW, int TH>
 static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t st) {
@@ -694,12 +782,14 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
         hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, true>), dim3(blocks), dim3(TW * TH), dyn, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)img.probs, img.id_map, img.target,
-                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items);
+                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
+                           (T*)(s.ckpt_cap > 0 ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
     } else {
         hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, false>), dim3(blocks), dim3(TW * TH), 0, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)nullptr, (int32_t*)nullptr, img.target,
-                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items);
+                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
+                           (T*)(s.ckpt_cap > 0 ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
     }
     return hipGetLastError();
 }
@@ -710,11 +800,24 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
     if (blocks == 0) return hipSuccess;
     const StatePtrs& s = f.s;
     if constexpr (TW * TH == kWave) {
-        hipLaunchKernelGGL((render_backward_wave_kernel<T, TW, TH>), dim3(blocks), dim3(kWave), 0, st, f.views,
-                           f.consts, f.K, (const T*)s.splats, s.rects, s.offsets, s.pair_vals[0], s.ranges, s.schedule,
-                           (const T*)img.t_final, img.last, img.target, (const T*)g.d_color, (const T*)g.d_depth,
-                           (const T*)g.d_t_final, (const T*)g.d_probs, (const T*)g.d_p_target, (T*)s.partials, s.written,
-                           (uint32_t)s.capacity, (uint32_t)s.items);
+        // Segments of the pair ranges, each restarted from the forward's
+        // boundary states; not with gradients of the instance probabilities,
+        // whose sum behind a boundary would need every object's prefix.
+        const bool seg = s.ckpt_cap > 0 && !g.d_probs && img.color && img.depth && (img.p_target || !g.d_p_target);
+        unsigned grid = (unsigned)blocks;
+        if (seg) {
+            const hipError_t e = launch_segment_list(s, blocks, st);
+            if (e != hipSuccess) return e;
+            grid = (unsigned)s.seg_cap;
+        }
+        hipLaunchKernelGGL((render_backward_wave_kernel<T, TW, TH>), dim3(grid),
+                           dim3(kWave), 0, st, f.views, f.consts, f.K, (const T*)s.splats, s.rects, s.offsets,
+                           s.pair_vals[0], s.ranges, s.schedule, (const T*)img.t_final, img.last, img.target,
+                           (const T*)g.d_color, (const T*)g.d_depth, (const T*)g.d_t_final, (const T*)g.d_probs,
+                           (const T*)g.d_p_target, (T*)s.partials, s.written, (uint32_t)s.capacity,
+                           (uint32_t)s.items, seg ? s.seg_list : nullptr, s.ckpt_base, (const T*)s.ckpt,
+                           (uint32_t)s.ckpt_cap, (const T*)img.color, (const T*)img.depth, (const T*)img.p_target,
+                           s.ctrl->counters);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((render_backward_kernel<T, TW, TH>), dim3(blocks), dim3(TW * TH), 0, st, f.views, f.consts,

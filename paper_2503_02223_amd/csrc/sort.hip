@@ -154,8 +154,29 @@ __global__ __launch_bounds__(256) void tile_bounds_kernel(const uint32_t* __rest
 constexpr int kSchedThreads = 1024;
 constexpr int kSchedBins = 4096;
 
+// Exclusive scan, in index order, of count(i) for i in [0, n) by one block:
+// each thread takes a contiguous chunk.  Writes out[i] and returns the total.
+template <typename F>
+__device__ __forceinline__ uint32_t block_chunk_scan(int n, F count, uint32_t* __restrict__ out, uint32_t* s_tmp,
+                                                     uint32_t* s_total) {
+    const int tid = threadIdx.x;
+    const int per = (n + kSchedThreads - 1) / kSchedThreads;
+    const int lo = min(n, tid * per), hi = min(n, lo + per);
+    uint32_t sum = 0;
+    for (int i = lo; i < hi; ++i) sum += count(i);
+    uint32_t off = block_exclusive_scan<kSchedThreads>(sum, s_tmp);
+    for (int i = lo; i < hi; ++i) {
+        out[i] = off;
+        off += count(i);
+    }
+    if (tid == kSchedThreads - 1) *s_total = off;
+    __syncthreads();
+    return *s_total;
+}
+
 __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint32_t* __restrict__ ranges,
-                                                                     int tiles, uint32_t* __restrict__ schedule) {
+                                                                     int tiles, uint32_t* __restrict__ schedule,
+                                                                     uint32_t* __restrict__ ckpt_base) {
     __shared__ uint32_t s_cnt[kSchedBins];  // bin b holds count kSchedBins - 1 - b (descending order)
     __shared__ uint32_t s_tmp[kSchedThreads / kWave];
     constexpr int kPer = kSchedBins / kSchedThreads;
@@ -182,6 +203,58 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
     }
     __syncthreads();
     for (int t = tid; t < tiles; t += kSchedThreads) schedule[atomicAdd(&s_cnt[bin_of(t)], 1u)] = (uint32_t)t;
+    if (!ckpt_base) return;  // uniform
+    // Segmented backward of 64-pixel tiles: the first boundary record of
+    // each tile (index order), where the forward stores its boundary states.
+    __shared__ uint32_t s_total;
+    __syncthreads();
+    block_chunk_scan(
+        tiles,
+        [&](int t) {
+            const uint32_t k = tile_segments(ranges[2 * t + 1] - ranges[2 * t]);
+            return k ? k - 1u : 0u;
+        },
+        ckpt_base, s_tmp, &s_total);
+}
+
+// The backward's work list, built after the forward: every tile's segments
+// up to its last blended position, in launch order (heaviest first), and the
+// list's length.
+__global__ __launch_bounds__(kSchedThreads) void segment_list_kernel(const uint32_t* __restrict__ ranges,
+                                                                    const uint32_t* __restrict__ schedule,
+                                                                    const int32_t* __restrict__ tile_last, int tiles,
+                                                                    uint32_t* __restrict__ seg_list, int64_t seg_cap,
+                                                                    Ctrl* __restrict__ ctrl) {
+    __shared__ uint32_t s_tmp[kSchedThreads / kWave];
+    __shared__ uint32_t s_total;
+    const int tid = threadIdx.x;
+    auto segs = [&](uint32_t t) -> uint32_t {
+        const uint32_t rs = ranges[2 * t], re = ranges[2 * t + 1];
+        const int ml = tile_last[t];
+        if (ml < (int)rs || ml >= (int)re) return 0u;
+        return min(((uint32_t)ml - rs) / (uint32_t)kSegLen + 1u, tile_segments(re - rs));
+    };
+    const int per = (tiles + kSchedThreads - 1) / kSchedThreads;
+    const int lo = min(tiles, tid * per), hi = min(tiles, lo + per);
+    uint32_t nsum = 0;
+    for (int p = lo; p < hi; ++p) nsum += segs(schedule[p]);
+    uint32_t pos = block_exclusive_scan<kSchedThreads>(nsum, s_tmp);
+    for (int p = lo; p < hi; ++p) {
+        const uint32_t t = schedule[p];
+        const uint32_t k = segs(t);
+        for (uint32_t j = 0; j < k; ++j)
+            if ((int64_t)(pos + j) < seg_cap) seg_list[pos + j] = (t << 8) | j;
+        pos += k;
+    }
+    if (tid == kSchedThreads - 1) s_total = pos;
+    __syncthreads();
+    if (tid == 0) ctrl->counters[kCounterSegTotal] = (uint32_t)min((int64_t)s_total, seg_cap);
+}
+
+hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, hipStream_t st) {
+    hipLaunchKernelGGL(segment_list_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, s.schedule, s.tile_last,
+                       tiles_total, s.seg_list, s.seg_cap, s.ctrl);
+    return hipGetLastError();
 }
 
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
@@ -232,7 +305,7 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges,
                            (uint32_t*)s.written);
         hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
-                           s.schedule);
+                           s.schedule, s.ckpt_cap > 0 ? s.ckpt_base : nullptr);
         return hipGetLastError();
     }
     return launch_clear_written(s, st);
