@@ -115,7 +115,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     // segment boundaries (64-pixel tiles only): sum over tiles of ceil(range / L) - 1 <= cap / L
     g.ckpt_cap = tw * th == kWave ? cap / kSegLen + 1 : 0;
     g.seg_cap = tiles_total + g.ckpt_cap;
-    g.off_seg = so; so = align256(so + g.seg_cap * 4);
+    g.off_seg = so; so = align256(so + g.seg_cap * 8);
     g.off_cbase = so; so = align256(so + tiles_total * 4);
     g.off_tlast = so; so = align256(so + tiles_total * 4);
     g.off_ckpt = so; so = align256(so + g.ckpt_cap * 6 * kWave * ts);

@@ -92,6 +92,16 @@ struct Consts {
 // Segments of a tile's pair range for the segmented backward (0 for an empty
 // tile); the last one takes the rest of the range when a tile has more than
 // kSegMax.
+#ifndef DQO_SEG_UNITS
+#define DQO_SEG_UNITS 16384
+#endif
+constexpr int kSegUnits = DQO_SEG_UNITS;  // target length of the backward's segment list
+// Segmenting the backward pays where there are few tiles for the machine (the
+// longest ranges then finish last); with more tiles than this the grid is
+// balanced by tiles alone and the boundary states, the list and the restarts
+// only add work (measured: 1M Gaussians at 1200x680, 12750 tiles, backward
+// 11% slower segmented).
+constexpr int kSegTilesMax = 8192;
 __device__ __forceinline__ uint32_t tile_segments(uint32_t range) {
     return min((range + kSegLen - 1) / (uint32_t)kSegLen, (uint32_t)kSegMax);
 }
@@ -308,6 +318,12 @@ inline int resident_blocks() {
 }
 hipError_t launch_clear_written(const StatePtrs& s, hipStream_t st);
 hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, hipStream_t st);
+// Whether the 64-pixel-tile backward of a frame with these tiles runs
+// segmented (the forward then stores boundary states and the sort their
+// offsets).
+inline bool segmented_backward(const StatePtrs& s, int tiles_total) {
+    return s.ckpt_cap > 0 && tiles_total > 0 && tiles_total <= kSegTilesMax;
+}
 hipError_t launch_associate(int n_obj, const double* mu, const double* R, const double* ax, int64_t n_det,
                             const double* boxes, const int32_t* det_frame, int n_frames, const double* P,
                             const int32_t* img_wh, double iou_min, double* iou, int32_t* match, double* occ,

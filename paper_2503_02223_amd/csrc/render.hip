@@ -512,11 +512,12 @@ __device__ __forceinline__ void backward_unit(
     const T* __restrict__ ptarget, T* s_sp, uint32_t* s_slot, uint32_t unit) {
     const int lane = threadIdx.x;
     int tile;
-    uint32_t seg = 0u;
+    uint32_t seg = 0u, seg_n = 1u;  // first segment of the unit, segments in it
     if (seg_list) {
-        const uint32_t e = seg_list[unit];
-        tile = (int)min(e >> 8, (uint32_t)(V.n_views * V.tiles_per_view - 1));
-        seg = e & 255u;
+        const uint2 e = reinterpret_cast<const uint2*>(seg_list)[unit];
+        tile = (int)min(e.x, (uint32_t)(V.n_views * V.tiles_per_view - 1));
+        seg = e.y >> 8;
+        seg_n = max(e.y & 255u, 1u);
     } else {
         tile = (int)min(schedule[unit], (uint32_t)(gridDim.x - 1));
     }
@@ -534,7 +535,7 @@ __device__ __forceinline__ void backward_unit(
     if (seg_list) {
         const uint32_t nseg = tile_segments(re - rs);
         s0 = min(rs + seg * (uint32_t)kSegLen, re);
-        s1 = (seg + 1u >= nseg) ? re : min(s0 + (uint32_t)kSegLen, re);
+        s1 = (seg + seg_n >= nseg) ? re : min(rs + (seg + seg_n) * (uint32_t)kSegLen, re);
     }
 
     int lastp = -1;
@@ -561,7 +562,7 @@ __device__ __forceinline__ void backward_unit(
             // state the forward stored there.  The sum behind the boundary is
             // the total minus the part in front of it (colour without the
             // background term, depth, target probability).
-            const uint32_t e = min(ckpt_base[tile] + seg, ckpt_cap - 1u);
+            const uint32_t e = min(ckpt_base[tile] + seg + seg_n - 1u, ckpt_cap - 1u);
             const T* c = ckpt + (size_t)e * 6 * kWave + lane;
             const T Tf = Tcur;
             const T behind = gc0 * ((color[(view * 3 + 0) * HW + pix] - Tf * cs.bg[0]) - c[1 * kWave]) +
@@ -783,13 +784,13 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)img.probs, img.id_map, img.target,
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
-                           (T*)(s.ckpt_cap > 0 ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
+                           (T*)(segmented_backward(s, blocks) ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
     } else {
         hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, false>), dim3(blocks), dim3(TW * TH), 0, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)nullptr, (int32_t*)nullptr, img.target,
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
-                           (T*)(s.ckpt_cap > 0 ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
+                           (T*)(segmented_backward(s, blocks) ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
     }
     return hipGetLastError();
 }
@@ -803,12 +804,15 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
         // Segments of the pair ranges, each restarted from the forward's
         // boundary states; not with gradients of the instance probabilities,
         // whose sum behind a boundary would need every object's prefix.
-        const bool seg = s.ckpt_cap > 0 && !g.d_probs && img.color && img.depth && (img.p_target || !g.d_p_target);
+        const bool seg = segmented_backward(s, blocks) && !g.d_probs && img.color && img.depth &&
+                         (img.p_target || !g.d_p_target);
         unsigned grid = (unsigned)blocks;
         if (seg) {
             const hipError_t e = launch_segment_list(s, blocks, st);
             if (e != hipSuccess) return e;
-            grid = (unsigned)s.seg_cap;
+            // units = sum over tiles of ceil(k_t / g) <= segments / g + tiles,
+            // and g keeps segments / g within kSegUnits
+            grid = (unsigned)std::min<int64_t>(s.seg_cap, (int64_t)blocks + kSegUnits);
         }
         hipLaunchKernelGGL((render_backward_wave_kernel<T, TW, TH>), dim3(grid),
                            dim3(kWave), 0, st, f.views, f.consts, f.K, (const T*)s.splats, s.rects, s.offsets,

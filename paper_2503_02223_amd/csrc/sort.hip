@@ -217,9 +217,14 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
         ckpt_base, s_tmp, &s_total);
 }
 
-// The backward's work list, built after the forward: every tile's segments
-// up to its last blended position, in launch order (heaviest first), and the
-// list's length.
+// The backward's work list, built after the forward: the segments of every
+// tile up to its last blended position, grouped into units of g consecutive
+// segments, in launch order (heaviest first), and the list's length.  g is
+// the smallest count that keeps the list near kSegUnits entries: splitting
+// pays where a few long tiles would otherwise finish last, and costs a
+// restart per unit where there are tiles enough to fill the machine.
+// Entries are (tile, first segment << 8 | segments); at most kSegTilesMax
+// tiles.
 __global__ __launch_bounds__(kSchedThreads) void segment_list_kernel(const uint32_t* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ schedule,
                                                                     const int32_t* __restrict__ tile_last, int tiles,
@@ -228,30 +233,50 @@ __global__ __launch_bounds__(kSchedThreads) void segment_list_kernel(const uint3
     __shared__ uint32_t s_tmp[kSchedThreads / kWave];
     __shared__ uint32_t s_total;
     const int tid = threadIdx.x;
-    auto segs = [&](uint32_t t) -> uint32_t {
-        const uint32_t rs = ranges[2 * t], re = ranges[2 * t + 1];
-        const int ml = tile_last[t];
-        if (ml < (int)rs || ml >= (int)re) return 0u;
-        return min(((uint32_t)ml - rs) / (uint32_t)kSegLen + 1u, tile_segments(re - rs));
-    };
-    const int per = (tiles + kSchedThreads - 1) / kSchedThreads;
-    const int lo = min(tiles, tid * per), hi = min(tiles, lo + per);
-    uint32_t nsum = 0;
-    for (int p = lo; p < hi; ++p) nsum += segs(schedule[p]);
-    uint32_t pos = block_exclusive_scan<kSchedThreads>(nsum, s_tmp);
-    for (int p = lo; p < hi; ++p) {
-        const uint32_t t = schedule[p];
-        const uint32_t k = segs(t);
-        for (uint32_t j = 0; j < k; ++j)
-            if ((int64_t)(pos + j) < seg_cap) seg_list[pos + j] = (t << 8) | j;
-        pos += k;
+    // At most kSegTilesMax tiles: each thread's contiguous chunk of the launch
+    // order is held in registers, its loads all in flight at once.
+    constexpr int kPer = kSegTilesMax / kSchedThreads;
+    uint32_t tt[kPer], kk[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int p = tid * kPer + i;
+        tt[i] = p < tiles ? schedule[p] : ~0u;
     }
+    uint32_t nseg = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        kk[i] = 0u;
+        if (tt[i] != ~0u) {
+            const uint32_t rs = ranges[2 * tt[i]], re = ranges[2 * tt[i] + 1];
+            const int ml = tile_last[tt[i]];
+            if (ml >= (int)rs && ml < (int)re)
+                kk[i] = min(((uint32_t)ml - rs) / (uint32_t)kSegLen + 1u, tile_segments(re - rs));
+        }
+        nseg += kk[i];
+    }
+    const uint32_t incl = block_exclusive_scan<kSchedThreads>(nseg, s_tmp) + nseg;
+    if (tid == kSchedThreads - 1) s_total = incl;
+    __syncthreads();
+    const uint32_t g = max(1u, (s_total + (uint32_t)kSegUnits - 1u) / (uint32_t)kSegUnits);
+    uint32_t nunit = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) nunit += (kk[i] + g - 1u) / g;
+    uint32_t pos = block_exclusive_scan<kSchedThreads>(nunit, s_tmp);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+        for (uint32_t j = 0; j < kk[i]; j += g, ++pos)
+            if ((int64_t)pos < seg_cap) {
+                seg_list[2 * (size_t)pos] = tt[i];
+                seg_list[2 * (size_t)pos + 1] = (j << 8) | min(g, kk[i] - j);
+            }
+    __syncthreads();
     if (tid == kSchedThreads - 1) s_total = pos;
     __syncthreads();
     if (tid == 0) ctrl->counters[kCounterSegTotal] = (uint32_t)min((int64_t)s_total, seg_cap);
 }
 
 hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, hipStream_t st) {
+    if (tiles_total > kSegTilesMax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(segment_list_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, s.schedule, s.tile_last,
                        tiles_total, s.seg_list, s.seg_cap, s.ctrl);
     return hipGetLastError();
@@ -305,7 +330,7 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges,
                            (uint32_t*)s.written);
         hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
-                           s.schedule, s.ckpt_cap > 0 ? s.ckpt_base : nullptr);
+                           s.schedule, segmented_backward(s, tiles_total) ? s.ckpt_base : nullptr);
         return hipGetLastError();
     }
     return launch_clear_written(s, st);
