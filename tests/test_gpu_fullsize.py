@@ -88,6 +88,40 @@ def test_fullsize_sampled_backward(oracle, room):
     assert np.abs(g[:, ~touched]).max() == 0.0
 
 
+def test_fullsize_sampled_backward_segmented(oracle, room):
+    """The benchmarked backward configuration: forward without instance
+    channels, upstream gradients on colour, depth and T_final only, so the
+    backward runs per segment of the tile ranges (grouped into units as at this
+    size) with restarts from the forward's boundary states."""
+    sc, r, p, ids, _ = room
+    cam = sc["cams"][0]
+    img = r.forward(p, ids)
+    rng = np.random.default_rng(2)
+    pix = np.sort(rng.choice(640 * 480, size=256, replace=False)).astype(np.int64)
+    ref = oracle.render(sc["params"], sc["ids"], cam, K=sc["K"], pix=pix)
+    keep = unambiguous(ref, grads=True)
+    gC = rng.normal(size=(3, 256)) * keep
+    gD = rng.normal(size=256) * keep
+    gT = rng.normal(size=256) * keep
+    go, _ = oracle.render_backward(sc["params"], sc["ids"], cam, K=sc["K"], gC=gC, gD=gD,
+                                   gP=np.zeros((sc["K"], 256)), gT=gT, pix=pix)
+    FC, FD, FT = np.zeros((3, 640 * 480)), np.zeros(640 * 480), np.zeros(640 * 480)
+    FC[:, pix], FD[pix], FT[pix] = gC, gD, gT
+    grads = dict(d_color=to_dev(FC.reshape(1, 3, 480, 640)), d_depth=to_dev(FD.reshape(1, 480, 640)),
+                 d_t_final=to_dev(FT.reshape(1, 480, 640)))
+    g = r.backward(p, img, grads)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    rng_t = r.frame.buf("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
+    lastpos = img["last"][0].reshape(-1)[pix].cpu().numpy()
+    tile = (pix // 640 // 8) * 80 + (pix % 640) // 8
+    rel = lastpos - rng_t[tile, 0]
+    assert ((rel >= 256) & keep).sum() > 10
+    touched = np.abs(go).sum(0) > 0
+    assert touched.sum() > 500
+    close(g[:, touched], go[:, touched], GRAD_RTOL, what="sampled-pixel grads (segmented)")
+    assert np.abs(g[:, ~touched]).max() == 0.0
+
 def test_sort_order_on_grids_too_large_to_be_resident():
     """Eight keyframes over 1.2M Gaussians (9.6M items, tens of millions of
     pairs): the radix passes and the scan run more workgroups than the device

@@ -373,3 +373,41 @@ def test_dense_view_loss_mode_parity(oracle):
     img2, g2 = runs[1][0], runs[1][1]
     assert torch.equal(img["color"], img2["color"]) and torch.equal(img["last"], img2["last"])
     assert np.array_equal(g, g2)
+
+
+def test_segmented_backward_with_target_parity(oracle):
+    """Dense view with 8x8 tiles (tile ranges of several 128-pair segments):
+    the backward runs one wavefront per segment, each restarted from the
+    forward's stored state at the segment's end.  Upstream gradients on colour,
+    depth and the target-object probability (through the target channel, or
+    the background transmittance where the target is none) against the
+    oracle's adjoint; some pixels blend past the first boundary of their tile."""
+    sc = scenes.single_view_scene(seed=12, n=30000)
+    cam = sc["cams"][0]
+    H, W, K = cam["height"], cam["width"], sc["K"]
+    tg = oracle.render(scenes.perturb(sc["params"], 1), sc["ids"], cam, K=K)
+    t_id = oracle.id_map(tg["P"], tg["Tf"])
+    ref = _oracle_fwd(oracle, sc)
+    keep = unambiguous(ref, grads=True)
+    rng = np.random.default_rng(41)
+    gC = rng.normal(size=(3, H, W)) * keep
+    gD = rng.normal(size=(H, W)) * keep
+    gpt = rng.normal(size=(H, W)) * keep
+    gP = np.zeros((K, H, W))
+    for k in range(K):
+        gP[k] = np.where(t_id == k, gpt, 0.0)
+    gT = np.where(t_id == -1, gpt, 0.0)
+    go, _ = oracle.render_backward(sc["params"], sc["ids"], cam, K=K, gC=gC, gD=gD, gP=gP, gT=gT)
+    r, p, ids = _frame(sc, ctx=B.Context(tile_w=8, tile_h=8))
+    target = torch.tensor(t_id[None], dtype=torch.int32, device="cuda")
+    img = r.forward(p, ids, target=target)
+    grads = dict(d_color=to_dev(gC[None]), d_depth=to_dev(gD[None]), d_p_target=to_dev(gpt[None]))
+    g = r.backward(p, img, grads)
+    torch.cuda.synchronize()
+    rng_t = r.frame.buf("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
+    lastpos = img["last"][0].cpu().numpy()
+    ys, xs = np.mgrid[0:H, 0:W]
+    tile = (ys // 8) * ((W + 7) // 8) + xs // 8
+    rel = lastpos - rng_t[tile, 0]
+    assert ((rel >= 128) & keep).sum() > 100 and ((rel >= 256) & keep).any()
+    close(g.cpu().numpy(), go, GRAD_RTOL, what="param grads (segmented, target channel)")
