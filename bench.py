@@ -31,7 +31,7 @@ FLOP_PER_BLENDED = 46.0    # gradient of one blended (pixel, Gaussian) incl. its
 # HBM bytes per launch of the render backward from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (scaled by a 256 MiB copy: x2.000 and x1.000), valid only for the kernel source
 # they were taken with (see profiles/); reported as null otherwise.
-MEASURED_TRAFFIC = {"render_src_sha256_16": "2e06520c67374b27", "bytes_per_launch": 203259050}
+MEASURED_TRAFFIC = {"render_src_sha256_16": "44985d9e39e315d4", "bytes_per_launch": 227824258}
 
 
 def measured_traffic():

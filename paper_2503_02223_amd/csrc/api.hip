@@ -112,8 +112,9 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.off_pose = so; so = align256(so + (int64_t)d->n_views * ((d->n + 255) / 256) * 6 * 8);
     g.off_written = so; so = align256(so + cap);
     g.off_sbase = so; so = align256(so + (int64_t)g.scan_blocks * 4);
-    // segment boundaries (64-pixel tiles only): sum over tiles of ceil(range / L) - 1 <= cap / L
-    g.ckpt_cap = tw * th == kWave ? cap / kSegLen + 1 : 0;
+    // segment boundaries (64-pixel tiles, frames the backward segments):
+    // sum over tiles of ceil(range / L) - 1 <= cap / L
+    g.ckpt_cap = (tw * th == kWave && tiles_total <= kSegTilesMax) ? cap / kSegLen + 1 : 0;
     g.seg_cap = tiles_total + g.ckpt_cap;
     g.off_seg = so; so = align256(so + g.seg_cap * 8);
     g.off_cbase = so; so = align256(so + tiles_total * 4);

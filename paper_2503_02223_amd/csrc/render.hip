@@ -778,19 +778,28 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
     const int blocks = f.views.n_views * f.views.tiles_per_view;
     if (blocks == 0) return hipSuccess;
     const StatePtrs& s = f.s;
+    // Boundary states and the backward's segment list, for a backward that
+    // can run segmented (no instance channels: their sums behind a boundary
+    // would need every object's prefix).
+    const bool seg = segmented_backward(s, blocks) && !img.probs;
     if (img.probs && f.K > 0) {
         const size_t dyn = (size_t)f.K * TW * TH * sizeof(T);
         hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, true>), dim3(blocks), dim3(TW * TH), dyn, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)img.probs, img.id_map, img.target,
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
-                           (T*)(segmented_backward(s, blocks) ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
+                           (T*)(seg ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
     } else {
         hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, false>), dim3(blocks), dim3(TW * TH), 0, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)nullptr, (int32_t*)nullptr, img.target,
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
-                           (T*)(segmented_backward(s, blocks) ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
+                           (T*)(seg ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
+    }
+    if (seg) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_segment_list(s, blocks, st);
     }
     return hipGetLastError();
 }
@@ -802,14 +811,12 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
     const StatePtrs& s = f.s;
     if constexpr (TW * TH == kWave) {
         // Segments of the pair ranges, each restarted from the forward's
-        // boundary states; not with gradients of the instance probabilities,
-        // whose sum behind a boundary would need every object's prefix.
-        const bool seg = segmented_backward(s, blocks) && !g.d_probs && img.color && img.depth &&
+        // boundary states (stored by a forward without instance channels,
+        // which also built the segment list).
+        const bool seg = segmented_backward(s, blocks) && !img.probs && !g.d_probs && img.color && img.depth &&
                          (img.p_target || !g.d_p_target);
         unsigned grid = (unsigned)blocks;
         if (seg) {
-            const hipError_t e = launch_segment_list(s, blocks, st);
-            if (e != hipSuccess) return e;
             // units = sum over tiles of ceil(k_t / g) <= segments / g + tiles,
             // and g keeps segments / g within kSegUnits
             grid = (unsigned)std::min<int64_t>(s.seg_cap, (int64_t)blocks + kSegUnits);
