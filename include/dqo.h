@@ -259,7 +259,7 @@ int dqo_object_loss(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_ca
  * per-Gaussian sums are taken in dqo_project_backward in a fixed order.
  * With 8x8 tiles and at most 8192 tiles over all views, and when neither img
  * holds instance channels nor g their gradients, each tile's pair range is
- * walked in 128-pair segments by separate wavefronts, each restarting from
+ * walked in 64-pair segments by separate wavefronts, each restarting from
  * the state the forward stored at the segment's end: the call must then
  * follow the dqo_render_forward that produced img on this state, with no
  * other forward of that kind (a different target, say) in between. */

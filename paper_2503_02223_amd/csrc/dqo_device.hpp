@@ -30,7 +30,7 @@ constexpr int kPairTileMin = kSortThreads * kPairIptShort;  // sizes the pair lo
 inline int depth_ipt(int64_t items) { return items < (int64_t(1) << 18) ? 8 : items < (int64_t(1) << 19) ? 16 : 32; }
 // Scan + emission: one record per thread, 1024 per block, so that each of the
 // 16 wavefronts emits the pairs of its own 64 records.
-constexpr int kSegLen = 128;       // pairs per backward segment of a 64-pixel tile
+constexpr int kSegLen = 64;        // pairs per backward segment of a 64-pixel tile
 constexpr int kSegMax = 255;       // segments per tile (the last one takes the rest of the range)
 constexpr int kScanThreads = 1024;
 constexpr int kScanIpt = 1;  // 2 and 4 measured slower at 200k items (1646 -> 1627 / 1573 it/s)

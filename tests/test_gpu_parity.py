@@ -376,7 +376,7 @@ def test_dense_view_loss_mode_parity(oracle):
 
 
 def test_segmented_backward_with_target_parity(oracle):
-    """Dense view with 8x8 tiles (tile ranges of several 128-pair segments):
+    """Dense view with 8x8 tiles (tile ranges of several 64-pair segments):
     the backward runs one wavefront per segment, each restarted from the
     forward's stored state at the segment's end.  Upstream gradients on colour,
     depth and the target-object probability (through the target channel, or
