@@ -25,9 +25,17 @@ from paper_2503_02223_amd import scenes  # noqa: E402
 
 METRIC = "fwd+bwd iters/s @640x480, 200k Gaussians; time-to-PSNR learned vs plain init"
 MI355X_FP32_VECTOR_TFLOPS = 157.3   # published fp32 vector peak (256 CUs, 2.4 GHz)
-# Algorithmic FLOPs of the render backward (see the design notes):
-FLOP_PER_EXAMINED = 11.0   # contribution test of one (pixel, pair) at or before the pixel's last blend
-FLOP_PER_BLENDED = 46.0    # gradient of one blended (pixel, Gaussian) incl. its share of the reduction
+MI355X_HBM_GBS = 8000.0             # published HBM3E bandwidth
+# v_exp_f32 at a quarter of the non-packed FMA rate: 256 CUs x 4 SIMDs x 16 lanes / 4 x 2.4 GHz
+MI355X_EXP_PER_S = 256 * 4 * 16 / 4 * 2.4e9
+# Algorithmic work of the render backward per launch (the cost model of the
+# hot-path plan): 60 FLOP and one exponential per examined (pixel, pair), i.e.
+# every pair of the pixel's tile range at or before its last blended one; bytes
+# = 44 per pair of the list (pair value + 40-byte record) + 32 per pixel
+# (upstream gradients, T_final, last) + 40 per written (tile, Gaussian) pair of
+# gradient partials.
+FLOP_PER_EXAMINED = 60.0
+BYTES_PER_PAIR, BYTES_PER_PIXEL, BYTES_PER_WRITTEN = 44.0, 32.0, 40.0
 # HBM bytes per launch of the render backward from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (scaled by a 256 MiB copy: x2.000 and x1.000), valid only for the kernel source
 # they were taken with (render.hip and dqo_device.hpp); reported as null otherwise.
@@ -84,6 +92,78 @@ def backward_work(tr):
     return int(E), int(Bn)
 
 
+def written_pairs(tr):
+    """(tile, Gaussian) pairs whose gradient partials the render backward
+    writes in the current state: partials zeroed, one backward, records with a
+    nonzero entry counted (the loss's sign gradients make every written record
+    nonzero)."""
+    f = tr.r.frame
+    f.project_cull_bin(tr.params, tr.ids)
+    f.sort()
+    f.render_forward(tr.img)
+    f.object_loss(tr.img, tr.targets, tr.grads_img, tr.loss)
+    part = f.buf("partials", torch.float32)
+    part.zero_()
+    f.render_backward(tr.img, tr.grads_img)
+    torch.cuda.synchronize()
+    return int((part.view(-1, 10) != 0).any(1).sum().item())
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def small_scene_comparison(steps=200):
+    """The 2k-Gaussian 128x96 scene: GPU microseconds per training iteration
+    (the same step as the headline) against the FP64 oracle's seconds per
+    forward + loss + backward + Adam on the whole image."""
+    import oracle
+    sc = scenes.single_view_scene(seed=0, n=2000)
+    cam = sc["cams"][0]
+    K = sc["K"]
+    tg = oracle.render(scenes.perturb(sc["params"], 1), sc["ids"], cam, K=K)
+    t_id = oracle.id_map(tg["P"], tg["Tf"])
+    t0 = time.perf_counter()
+    out = oracle.render(sc["params"], sc["ids"], cam, K=K)
+    p_t = np.where(t_id >= 0, np.take_along_axis(out["P"], np.maximum(t_id, 0)[None], 0)[0], out["Tf"])
+    lo = oracle.object_loss(out["C"], out["D"], p_t, tg["C"], tg["D"], t_id)
+    gP = np.zeros((K,) + t_id.shape)
+    for k in range(K):
+        gP[k] = np.where(t_id == k, lo["gp"], 0.0)
+    gT = np.where(t_id == -1, lo["gp"], 0.0)
+    grads, _ = oracle.render_backward(sc["params"], sc["ids"], cam, K=K, gC=lo["gC"], gD=lo["gD"], gP=gP, gT=gT)
+    z = np.zeros_like(sc["params"])
+    oracle.adam(sc["params"], grads, z, z, 1, B.default_lrs())
+    t_oracle = time.perf_counter() - t0
+    dev = "cuda"
+    targets = dict(color=torch.tensor(tg["C"][None], dtype=torch.float32, device=dev),
+                   depth=torch.tensor(tg["D"][None], dtype=torch.float32, device=dev),
+                   id=torch.tensor(t_id[None], dtype=torch.int32, device=dev))
+    tr = B.Trainer(torch.tensor(sc["params"], dtype=torch.float32, device=dev),
+                   torch.tensor(sc["ids"], device=dev), sc["cams"], K, targets,
+                   ctx=B.Context(tile_w=8, tile_h=8), status_every=0)
+    for _ in range(10):
+        tr.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        tr.step()
+    torch.cuda.synchronize()
+    gpu_us = (time.perf_counter() - t1) * 1e6 / steps
+    tr.check()
+    return dict(workload="2,000 Gaussians, 128x96, K=3, 8x8 tiles; forward + object loss + backward + Adam",
+                gpu_us_per_iter=round(gpu_us, 2), oracle_s_per_iter=round(t_oracle, 4),
+                oracle_cores=oracle.num_threads())
+
+
 def cpu_baseline(sc, targets_seed=1, n_pix=1024, seed=0):
     """The FP64 oracle (every Gaussian at every sampled pixel) on a bounded
     sample of the same workload: forward + loss + backward over n_pix random
@@ -113,7 +193,8 @@ def cpu_baseline(sc, targets_seed=1, n_pix=1024, seed=0):
     oracle.adam(sc["params"], grads, z, z, 1, B.default_lrs())
     t_adam = time.perf_counter() - t1
     per_iter = t_render * (HW / n_pix) + t_adam
-    return dict(value=1.0 / per_iter, unit="iters/s", cores=oracle.num_threads(), kind="oracle",
+    return dict(value=1.0 / per_iter, unit="iters/s", cores=oracle.num_threads(), cpu_model=cpu_model(),
+                kind="oracle",
                 sample=f"FP64 forward+object loss+backward over {n_pix} of {HW} pixels with all "
                        f"{sc['params'].shape[1]} Gaussians ({t_render:.1f} s) scaled by the pixel count, "
                        f"plus one Adam step over all Gaussians ({t_adam:.2f} s)")
@@ -138,31 +219,49 @@ def bench_keyframes(args):
     targets = dict(color=t0["color"].clone(), depth=t0["depth"].clone(), id=t0["id_map"].clone())
     del r0, t0
     torch.cuda.empty_cache()
+    # Per-object jobs beside the whole-scene views: the objects most visible
+    # in some keyframe, each in that keyframe with its own Gaussians (objects
+    # are contiguous in the parameters) inside its observed box + 8 px.
+    idm = targets["id"].cpu().numpy()
+    H, W = idm.shape[1:]
+    cnt = np.stack([(idm == k).reshape(V, -1).sum(1) for k in range(sc["K"])])  # [K][V]
+    order = [k for k in np.argsort(-cnt.max(1)) if k > 0][:args.jobs]
+    jobs_desc = []
+    for k in order:
+        v = int(np.argmax(cnt[k]))
+        ys, xs = np.nonzero(idm[v] == k)
+        box = (max(int(xs.min()) - 8, 0), max(int(ys.min()) - 8, 0), min(int(xs.max()) + 9, W),
+               min(int(ys.max()) + 9, H))
+        g = np.flatnonzero(sc["ids"] == k)
+        jobs_desc.append(dict(object=int(k), view=v, window=box, first=int(g[0]), gaussians=int(g.size)))
+    cams = list(sc["cams"]) + [sc["cams"][j["view"]] for j in jobs_desc]
+    segments = [(0, n)] * V + [(j["first"], j["gaussians"]) for j in jobs_desc]
+    windows = [(0, 0, W, H)] * V + [j["window"] for j in jobs_desc]
+    jobs = [-1] * V + [j["object"] for j in jobs_desc]
+    jv = [j["view"] for j in jobs_desc]
+    targets = {key: torch.cat([t, t[jv]]).contiguous() for key, t in targets.items()}
 
     def make(ctx):
-        return B.Trainer(p0.clone(), ids, sc["cams"], sc["K"], targets, ctx=ctx)
+        return B.Trainer(p0.clone(), ids, cams, sc["K"], targets, ctx=ctx, segments=segments, windows=windows,
+                         jobs=jobs)
 
     log("autotuning the tile shape")
     best, table = autotune.autotune_tile(make)
     log(f"tile {best}: {table}")
     tr = make(B.Context(tile_w=best[0], tile_h=best[1]))
     g = tr.capture()
-    for _ in range(args.warmup):
-        g.replay()
+    tr.replay(g, args.warmup)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
-        g.replay()
+    tr.replay(g, args.steps)   # reads the device status every 100 replays and after the last
     torch.cuda.synchronize()
     dt = time.perf_counter() - t_start
     npairs = tr.check()
     ms = dt * 1e3 / args.steps
     # per-object dual quadrics from the rendered object masks of the 8 views
-    f = tr.r.frame
-    img = f.new_images(probs=True, id_map=True)
-    f.project_cull_bin(tr.params, ids)
-    f.sort()
-    f.render_forward(img)
+    # (the whole-scene views only: the mask boxes of every object)
+    r1 = B.Rasterizer(sc["cams"], n, sc["K"], ctx=B.Context(tile_w=16, tile_h=16))
+    img = r1.forward(tr.params, ids, probs=True, id_map=True)
     Ps = torch.tensor(np.stack([B.camera_matrix(c).reshape(12) for c in sc["cams"]]), dtype=torch.float64,
                       device="cuda")
     wh = torch.tensor([[c["width"], c["height"]] for c in sc["cams"]], dtype=torch.int32, device="cuda")
@@ -192,14 +291,16 @@ def bench_keyframes(args):
     iou_before = float(np.mean(1 - rl[:, 0] / np.maximum(n_box, 1))) if ok.any() else float("nan")
     iou_after = float(np.mean(1 - rl[:, 1] / np.maximum(n_box, 1))) if ok.any() else float("nan")
     out = {
-        "metric": "keyframe training iters/s (8 views x 640x480, 1.2M Gaussians, all views per step)",
+        "metric": "keyframe training iters/s (8 views x 640x480 + per-object jobs, 1.2M Gaussians, all per step)",
         "value": round(1e3 / ms, 2), "unit": "iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "8 ring keyframes 640x480 (r=2 m), 40 objects with log-uniform [1k, 80k] Gaussians "
-                               "plus background to 1.2M, K=41; one HIP-graph replay = project/bin + sort + render fwd "
-                               "+ object loss + render bwd + project bwd + Adam over all views",
-                   "n_gaussians": n, "views": V, "pairs": npairs, "tile": f"{best[0]}x{best[1]}",
+                               "plus background to 1.2M, K=41, and per-object jobs (an object's own Gaussians in "
+                               "its box of one keyframe, binary instance loss); one HIP-graph replay = project/bin + "
+                               "sort + render fwd + object loss + render bwd + project bwd + Adam over all views "
+                               "and jobs",
+                   "n_gaussians": n, "views": V, "jobs": jobs_desc, "pairs": npairs, "tile": f"{best[0]}x{best[1]}",
                    "autotune_ms_per_step": table},
         "quadric_fit": {"objects": int(sc["K"] - 1), "fitted": int(ok.sum()),
                         "mask_boxes_plus_fit_ms": round(e0.elapsed_time(e1), 4),
@@ -440,6 +541,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=200_000)
+    ap.add_argument("--jobs", type=int, default=8, help="per-object jobs beside the 8 keyframes (at most 8)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--event-every", type=int, default=10,
                     help="time the render backward with HIP events on every N-th timed step (default 10)")
@@ -511,17 +613,32 @@ def main():
     ms = dt * 1e3 / args.steps
     loss = tr.loss.cpu().numpy().tolist()
     E, Bn = backward_work(tr)
-    flops = FLOP_PER_EXAMINED * E + FLOP_PER_BLENDED * Bn
-    achieved = flops / (bwd_ms * 1e-3) / 1e12
-    roof = dict(bound="alu", kernel=(f"render_backward_wave_kernel<float,{tw},{th}>" if tw * th == 64
-                                     else f"render_backward_kernel<float,{tw},{th}>"), achieved=round(achieved, 3),
-                peak=MI355X_FP32_VECTOR_TFLOPS, unit="TFLOP/s", frac=round(achieved / MI355X_FP32_VECTOR_TFLOPS, 4),
-                traffic=measured_traffic(), avg_ms=round(bwd_ms, 4), examined_pairs=E, blended_pairs=Bn,
-                flop_per_examined=FLOP_PER_EXAMINED, flop_per_blended=FLOP_PER_BLENDED)
+    Wp = written_pairs(tr)
+    t = bwd_ms * 1e-3
+    alg_bytes = BYTES_PER_PAIR * npairs + BYTES_PER_PIXEL * 640 * 480 + BYTES_PER_WRITTEN * Wp
+    flops = FLOP_PER_EXAMINED * E
+    # roofline fraction = max(bytes / BW, flops / F, exps / E) / measured time
+    t_hbm = alg_bytes / (MI355X_HBM_GBS * 1e9)
+    t_flop = flops / (MI355X_FP32_VECTOR_TFLOPS * 1e12)
+    t_exp = E / MI355X_EXP_PER_S
+    kernel = (f"render_backward_wave_kernel<float,{tw},{th}>" if tw * th == 64
+              else f"render_backward_kernel<float,{tw},{th}>")
+    if t_hbm >= max(t_flop, t_exp):
+        roof = dict(bound="hbm", achieved=round(alg_bytes / t / 1e9, 1), peak=MI355X_HBM_GBS, unit="GB/s")
+    else:
+        roof = dict(bound="alu", achieved=round(flops / t / 1e12, 3), peak=MI355X_FP32_VECTOR_TFLOPS,
+                    unit="TFLOP/s")
+    roof.update(frac=round(max(t_hbm, t_flop, t_exp) / t, 4), traffic=measured_traffic(), kernel=kernel,
+                avg_ms=round(bwd_ms, 4), alg_bytes=int(alg_bytes), flops=int(flops),
+                bytes_frac=round(t_hbm / t, 4), flop_frac=round(t_flop / t, 4), exp_frac=round(t_exp / t, 4),
+                pairs=npairs, examined_pixel_pairs=E, blended_pixel_pairs=Bn, written_pairs=Wp,
+                flop_per_examined=FLOP_PER_EXAMINED)
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(sc, n_pix=args.cpu_pixels)
+        log("timing the 2k-Gaussian scene on the GPU and the oracle")
+        cpu["small_scene"] = small_scene_comparison()
     learned = None
     if not args.no_learned and os.path.exists(LEARNED_MODEL):
         log("time-to-PSNR of the learned initialization on 20 held-out objects")

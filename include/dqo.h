@@ -95,11 +95,27 @@ typedef struct dqo_camera {
 } dqo_camera;
 
 /* Size of one frame of work.  All views must share width and height.
- * segments (host memory, read at every call that takes the descriptor) is
- * either NULL, in which case every view sees all n Gaussians, or
- * [n_views][2] = (first, count): view v sees Gaussians [first, first + count)
- * only.  Segments let one launch render independent Gaussian sets (object
- * crops, per-object jobs) each in its own view; they may overlap. */
+ * The per-view arrays below are host memory, read at every call that takes
+ * the descriptor; each may be NULL.
+ * segments: NULL, in which case every view sees all n Gaussians, or
+ *   [n_views][2] = (first, count): view v sees Gaussians [first, first + count)
+ *   only.  Segments let one launch render independent Gaussian sets (object
+ *   crops, per-object jobs) each in its own view; they may overlap.
+ * windows: NULL (whole images) or [n_views][4] = (x0, y0, x1, y1): view v
+ *   renders only pixels x0 <= u < x1, y0 <= v < y1 (within the image; empty
+ *   when x1 <= x0 or y1 <= y0).  Pixels outside the window are written as if
+ *   no Gaussian covered them (colour = background, depth 0, T_final 1, last
+ *   -1, p_target as for an empty pixel), carry no loss, and the pairs of tiles
+ *   outside it are never made.
+ * jobs: NULL (every view whole-scene) or [n_views]: -1 for a whole-scene
+ *   view, k in [0, K) for a per-object job of object k (the objects are
+ *   optimised in parallel, Sec. III-D): the view's Gaussians (its segment)
+ *   are object k's, its instance channel ins_k of Eq. (12) is then
+ *   1 - T_final, and Eq. (13) compares it with the observed mask of k.  In
+ *   the forward, the loss and the backward, the target id t of a job's pixel
+ *   is read as k where t == k and -1 ("not this object": probability
+ *   T_final) elsewhere, and its colour and depth terms count only the pixels
+ *   observed as k. */
 typedef struct dqo_frame_desc {
     int64_t n;             /* Gaussians, >= 0 */
     int32_t n_views;       /* 1..DQO_MAX_VIEWS */
@@ -108,6 +124,8 @@ typedef struct dqo_frame_desc {
     int32_t dtype;         /* DQO_F32 or DQO_F64 */
     int32_t reserved;
     const int64_t* segments; /* NULL or [n_views][2] (first, count), within [0, n] */
+    const int32_t* windows;  /* NULL or [n_views][4] pixel windows (x0, y0, x1, y1) */
+    const int32_t* jobs;     /* NULL or [n_views] object of a per-object job, -1 = whole scene */
 } dqo_frame_desc;
 
 /* Sub-buffers of the caller-allocated state buffer (dqo_state_layout). */
@@ -222,11 +240,14 @@ int dqo_clear_status(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_c
 int dqo_project_cull_bin(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
                          const void* params, const int32_t* ids, void* state, void* stream);
 
-/* Stable radix sort of the pair list by global tile id (the list is already in
- * depth order, so the result is ordered by (tile, depth, item index)), then the
- * [start, end) range of every tile, the launch order of the render workgroups
- * (heaviest tiles first), and zeroed per-pair gradient partials for
- * dqo_render_backward. */
+/* The blending order of the alpha blending of Sec. III-D (front to back,
+ * by camera depth; the rasterization kernel of Sec. IV): stable radix sort
+ * of the pair list by global tile id (the list is already in depth order, so
+ * the result is ordered by (tile, depth, item index)), then the [start, end)
+ * range of every tile, the launch order of the render workgroups (heaviest
+ * tiles first), and cleared written-marks of the per-pair gradient partials
+ * for dqo_render_backward.  Needs dqo_project_cull_bin on the same state;
+ * the pair count is read on the device (no host synchronisation). */
 int dqo_sort(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams, void* state,
              void* stream);
 
@@ -240,35 +261,53 @@ int dqo_sort(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* c
 int dqo_render_forward(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
                        const void* state, const dqo_images* img, void* stream);
 
-/* Object loss of Eq. (10)-(14), read as: L_rgb = mean |C - C^| over 3VHW,
- * L_depth = mean |D - D^| over pixels with D^ > 0, L_obj = mean over VHW of
+/* Object loss of Eq. (10)-(14), read as: L_rgb = mean |C - C^| over the
+ * colour pixels (3 channels each), L_depth = mean |D - D^| over the colour
+ * pixels with D^ > 0, L_obj = mean over the window pixels of
  * -log max(p_t, ce_eps) with p_t = img->p_target; total = w_rgb L_rgb +
- * w_depth L_depth + lambda L_obj.  Writes loss[4] = {total, L_rgb, L_depth,
- * L_obj} (device double) and the upstream gradients d_color, d_depth and
- * d_p_target of `g` (sign(0) = 0; no CE gradient where p_t < ce_eps).  The
+ * w_depth L_depth + lambda L_obj.  Window pixels: every pixel of every view
+ * unless the descriptor gives windows.  Colour pixels: the window pixels of
+ * whole-scene views and, of a per-object job of object k, those observed as
+ * k (tgt->id, then required).  Each mean is taken over all views together.
+ * Writes loss[4] = {total, L_rgb, L_depth, L_obj} (device double) and the
+ * upstream gradients d_color, d_depth and d_p_target of `g` (zero outside
+ * the counted pixels; sign(0) = 0; no CE gradient where p_t < ce_eps).  The
  * reduction order is fixed, so the result is bitwise reproducible. */
 int dqo_object_loss(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
                     const dqo_images* img, const dqo_targets* tgt, const dqo_loss_weights* w,
                     double* loss /* device [4] */, const dqo_image_grads* g, void* state, void* stream);
 
-/* Adjoint of dqo_render_forward with the blended set held fixed.  Walks each
- * pixel back to front from its last blended Gaussian, recomputing the
- * transmittance T_i = T_{i+1} / (1 - alpha_i) instead of storing it, and
- * writes one gradient record per (tile, Gaussian) pair into the state
- * (partials of mean2d, conic, opacity, colour, depth).  No atomics: the
- * per-Gaussian sums are taken in dqo_project_backward in a fixed order.
+/* Adjoint of dqo_render_forward with the blended set held fixed: the
+ * back-propagation of the rendering losses through the alpha blending of
+ * colour, depth and the instance channels of Eq. (12) (Sec. III-D; the
+ * back-propagation kernel of Sec. IV).  Walks each pixel back to front from
+ * its last blended Gaussian, recomputing the transmittance
+ * T_i = T_{i+1} / (1 - alpha_i) instead of storing it, and writes one
+ * gradient record per (tile, Gaussian) pair into the state (partials of
+ * mean2d, conic, opacity, colour, depth).  No atomics: the per-Gaussian sums
+ * are taken in dqo_project_backward in a fixed order.
+ * img must hold the outputs of a dqo_render_forward on this state since its
+ * last dqo_project_cull_bin (the positions in img->last index that pair
+ * list); g the upstream gradients of those images (d_color required).
  * With 8x8 tiles and at most 8192 tiles over all views, and when neither img
  * holds instance channels nor g their gradients, each tile's pair range is
  * walked in 64-pair segments by separate wavefronts, each restarting from
- * the state the forward stored at the segment's end: the call must then
- * follow the dqo_render_forward that produced img on this state, with no
- * other forward of that kind (a different target, say) in between. */
+ * the state the forward stored at the segment's end.  Those states belong
+ * to the last such forward; the device checks that it is this binning and
+ * these images (img->last and img->target), and otherwise walks every tile
+ * whole, which gives the same gradients up to rounding order. */
 int dqo_render_backward(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
                         void* state, const dqo_images* img, const dqo_image_grads* g, void* stream);
 
-/* Sums each Gaussian's pair partials over tiles and views and applies the
- * chain rule through the projection to grads[14][n] (same layout as params;
- * overwritten; zero for Gaussians culled in every view). */
+/* Back-propagation through the projection of the Gaussian shape of
+ * Eq. (2)-(3) (the Gaussian's mean, rotation and axis scales, Sec. III-A)
+ * into every view, which completes the gradient of the rendering losses of
+ * Sec. III-D with respect to the Gaussian parameters: sums each Gaussian's
+ * pair partials over tiles and views in a fixed order and applies the chain
+ * rule through the projection to grads[14][n] (same layout as params;
+ * overwritten; zero for Gaussians culled in every view).  params must be the
+ * parameters the state was projected with; needs dqo_render_backward on the
+ * same state. */
 int dqo_project_backward(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
                          const void* params, const void* state, void* grads, void* stream);
 

@@ -10,6 +10,8 @@ Contents (each function states the passage of the paper it follows):
   tile_rects / pair_order              binning and (tile, depth) order, numpy
   object_loss                          Eq. (10)-(14) read as L1 colour, L1 depth,
                                        object cross-entropy
+  job_targets / object_loss_views      the same loss over windows of whole-scene
+                                       views and per-object jobs (Eq. (12)-(13))
   adam                                 the optimizer step (PyTorch semantics)
   dual_quadric_* / fit_dual_quadric    Eq. (1)-(4): quadric from boxes, its
                                        decomposition and its projection
@@ -298,6 +300,75 @@ def object_loss(C, D, p_t, tC, tD, t_id, w_rgb=1.0, w_depth=1.0, lam=1.0, eps=CE
     gD = w_depth * np.sign(dr) / nv if nv else np.zeros_like(D)
     gp = np.where(p_t >= eps, -lam / (npix * np.where(p_t >= eps, p_t, 1.0)), 0.0) if npix else p_t * 0
     return dict(loss=total, l_rgb=l_rgb, l_depth=l_d, l_obj=l_obj, n_valid=nv, gC=gC, gD=gD, gp=gp)
+
+
+def job_targets(t_id, job):
+    """Target of a per-object job (Sec. III-D; objects are optimised in
+    parallel, each on its own Gaussians G^k): the job of object k renders
+    only G^k, so its instance channel ins_k of Eq. (12) is 1 - T_final, and
+    Eq. (13) compares it with the observed mask of k.  As a target map: k
+    where the pixel is observed as k, -1 ("not this object", probability
+    T_final) elsewhere.  job < 0 (a whole-scene view) keeps t_id."""
+    t_id = np.asarray(t_id)
+    if job < 0:
+        return t_id
+    return np.where(t_id == job, job, -1).astype(t_id.dtype)
+
+
+def object_loss_views(C, D, P, Tf, tC, tD, t_id, jobs=None, windows=None, w_rgb=1.0, w_depth=1.0, lam=1.0,
+                      eps=CE_EPS):
+    """Object loss of Eq. (10)-(14) over views that are whole-scene renders
+    or per-object jobs, each restricted to a pixel window.
+
+    Per view v (images [V][...][H][W]; jobs[v] = -1 or the job's object k;
+    windows[v] = (x0, y0, x1, y1), pixels x0 <= u < x1, y0 <= v < y1):
+      * the cross-entropy term covers every window pixel, on the probability
+        of the target of job_targets (P_t, or T_final for -1);
+      * the colour and depth terms cover the window pixels of a whole-scene
+        view, and of a job only those observed as its object (Eq. (10)-(11)
+        sum over the object's own pixels); depth only where the observed
+        depth is > 0.
+    Each term is one mean over its pixels of all views together:
+    L = w_rgb * sum|C - C^| / (3 N_c) + w_depth * sum|D - D^| / N_d
+        + lam * sum -log max(p_t, eps) / N_o.
+    Returns the scalars, the counts and dL/dC, dL/dD, dL/dP, dL/dT_final
+    (zero outside the counted pixels; no CE gradient where p_t < eps)."""
+    C, D, P, Tf = (np.asarray(a, dtype=np.float64) for a in (C, D, P, Tf))
+    tC, tD = np.asarray(tC, dtype=np.float64), np.asarray(tD, dtype=np.float64)
+    t_id = np.asarray(t_id)
+    V, H, W = D.shape
+    K = P.shape[1]
+    jobs = [-1] * V if jobs is None else list(jobs)
+    windows = [(0, 0, W, H)] * V if windows is None else [tuple(w) for w in windows]
+    win = np.zeros((V, H, W), bool)
+    tgt = np.empty((V, H, W), np.int64)
+    for v in range(V):
+        x0, y0, x1, y1 = windows[v]
+        win[v, max(y0, 0):max(y1, 0), max(x0, 0):max(x1, 0)] = True
+        tgt[v] = job_targets(t_id[v], jobs[v])
+    colour = win.copy()
+    for v in range(V):
+        if jobs[v] >= 0:
+            colour[v] &= t_id[v] == jobs[v]
+    depth_ok = colour & (tD > 0)
+    n_c, n_d, n_o = int(colour.sum()), int(depth_ok.sum()), int(win.sum())
+    r = C - tC
+    l_rgb = np.abs(np.where(colour[:, None], r, 0.0)).sum() / (3 * n_c) if n_c else 0.0
+    dr = np.where(depth_ok, D - tD, 0.0)
+    l_d = np.abs(dr).sum() / n_d if n_d else 0.0
+    p_t = np.where(tgt >= 0, np.take_along_axis(P, np.clip(tgt, 0, K - 1)[:, None], 1)[:, 0], Tf)
+    ce = np.where(win, -np.log(np.maximum(p_t, eps)), 0.0)
+    l_obj = ce.sum() / n_o if n_o else 0.0
+    total = w_rgb * l_rgb + w_depth * l_d + lam * l_obj
+    gC = np.where(colour[:, None], w_rgb * np.sign(r) / (3 * n_c), 0.0) if n_c else np.zeros_like(C)
+    gD = w_depth * np.sign(dr) / n_d if n_d else np.zeros_like(D)
+    gq = np.where(win & (p_t >= eps), -lam / (max(n_o, 1) * np.where(p_t >= eps, p_t, 1.0)), 0.0)
+    gP = np.zeros_like(P)
+    for k in range(K):
+        gP[:, k] = np.where(tgt == k, gq, 0.0)
+    gT = np.where(tgt == -1, gq, 0.0)
+    return dict(loss=total, l_rgb=l_rgb, l_depth=l_d, l_obj=l_obj, n_colour=n_c, n_depth=n_d, n_obj=n_o,
+                gC=gC, gD=gD, gP=gP, gT=gT, gp=gq, target=tgt)
 
 
 # ---------------------------------------------------------------------- adam

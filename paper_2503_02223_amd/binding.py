@@ -61,7 +61,8 @@ class Camera(ctypes.Structure):
 class FrameDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_views", ctypes.c_int32), ("K", ctypes.c_int32),
                 ("pair_capacity", ctypes.c_int64), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("segments", ctypes.POINTER(ctypes.c_int64))]
+                ("segments", ctypes.POINTER(ctypes.c_int64)), ("windows", ctypes.POINTER(ctypes.c_int32)),
+                ("jobs", ctypes.POINTER(ctypes.c_int32))]
 
 
 class Layout(ctypes.Structure):
@@ -255,7 +256,7 @@ class Frame:
     """Caller-owned device state of one frame of work (n Gaussians, V views)."""
 
     def __init__(self, ctx: Context, cams: Sequence[dict], n: int, K: int, capacity: int,
-                 dtype=torch.float32, device="cuda", segments=None):
+                 dtype=torch.float32, device="cuda", segments=None, windows=None, jobs=None):
         self.ctx = ctx
         self.cam_dicts = list(cams)
         self.cams = make_cameras(cams)
@@ -268,6 +269,15 @@ class Frame:
             seg = np.ascontiguousarray(np.asarray(segments, dtype=np.int64).reshape(len(cams), 2))
             self.segments = (ctypes.c_int64 * seg.size)(*seg.ravel().tolist())
             self.desc.segments = ctypes.cast(self.segments, ctypes.POINTER(ctypes.c_int64))
+        self.windows = self.jobs = None
+        if windows is not None:    # [V][4] (x0, y0, x1, y1) pixel windows
+            win = np.ascontiguousarray(np.asarray(windows, dtype=np.int32).reshape(len(cams), 4))
+            self.windows = (ctypes.c_int32 * win.size)(*win.ravel().tolist())
+            self.desc.windows = ctypes.cast(self.windows, ctypes.POINTER(ctypes.c_int32))
+        if jobs is not None:       # [V] object of each per-object job, -1 = whole scene
+            jb = np.ascontiguousarray(np.asarray(jobs, dtype=np.int32).reshape(len(cams)))
+            self.jobs = (ctypes.c_int32 * jb.size)(*jb.tolist())
+            self.desc.jobs = ctypes.cast(self.jobs, ctypes.POINTER(ctypes.c_int32))
         self.layout = Layout()
         ctx.check(lib().dqo_state_layout(ctx.h, ctypes.byref(self.desc), self.cams, ctypes.byref(self.layout)))
         self.state = torch.empty(int(self.layout.total), dtype=torch.uint8, device=self.device)
@@ -540,16 +550,18 @@ class Rasterizer:
     """Frame + image buffers for a fixed camera set, with capacity management."""
 
     def __init__(self, cams: Sequence[dict], n: int, K: int, capacity: Optional[int] = None,
-                 dtype=torch.float32, ctx: Optional[Context] = None, device="cuda", segments=None):
+                 dtype=torch.float32, ctx: Optional[Context] = None, device="cuda", segments=None, windows=None,
+                 jobs=None):
         self.ctx = ctx if ctx is not None else Context()
         self.cams, self.n, self.K, self.dtype, self.device = list(cams), int(n), int(K), dtype, device
-        self.segments = segments
+        self.segments, self.windows, self.jobs = segments, windows, jobs
         cap = capacity if capacity is not None else max(1024, 4 * n * (len(cams) if segments is None else 1))
         self.frame = self._new_frame(min(cap, 1 << 30))
         self.generation = 0   # bumped by every bin(): identifies the pair list in the state
 
     def _new_frame(self, capacity):
-        return Frame(self.ctx, self.cams, self.n, self.K, capacity, self.dtype, self.device, segments=self.segments)
+        return Frame(self.ctx, self.cams, self.n, self.K, capacity, self.dtype, self.device, segments=self.segments,
+                     windows=self.windows, jobs=self.jobs)
 
     def bin(self, params, ids, grow=True, stream=None):
         """project_cull_bin + sort; when grow is set, checks the pair count (a
@@ -635,13 +647,14 @@ class Trainer:
     parameters); self.grads is then not written."""
 
     def __init__(self, params: torch.Tensor, ids: torch.Tensor, cams, K, targets: Dict[str, torch.Tensor],
-                 lrs=None, capacity=None, loss_weights=(1.0, 1.0, 1.0), ctx=None, segments=None, fused=True):
+                 lrs=None, capacity=None, loss_weights=(1.0, 1.0, 1.0), ctx=None, segments=None, fused=True,
+                 status_every=100, windows=None, jobs=None):
         self.params = params.contiguous()
         self.ids = ids
         self.n = params.shape[1]
         self.dtype = params.dtype
         self.r = Rasterizer(cams, self.n, K, capacity=capacity, dtype=self.dtype, ctx=ctx, segments=segments,
-                            device=params.device)
+                            device=params.device, windows=windows, jobs=jobs)
         self.r.bin(self.params, ids, grow=True)  # sizes the pair list once
         if self.r.frame.capacity < (1 << 30):   # headroom for pairs added while training
             cap = min(1 << 30, int(self.r.frame.read_status()[2] * 1.5) + 4096)
@@ -665,6 +678,11 @@ class Trainer:
         self.step_count = 0
         self.d_step = torch.zeros(1, dtype=torch.int64, device=dev)  # Adam step count on the device
         self.fused = fused   # project backward and Adam in one pass (bitwise the same as the two calls)
+        # Every status_every steps (0: never) the device status word is read
+        # (a host synchronisation): pair-list overflow or a device wait that
+        # gave up raise DqoError.  After a timeout the library orders the
+        # sort's blocks by ticket until the status is cleared.
+        self.status_every = int(status_every)
 
     def step(self, stream=None):
         f = self.r.frame
@@ -680,6 +698,17 @@ class Trainer:
             f.project_backward(self.params, self.grads, stream)
             adam_step_counted(self.r.ctx, self.params, self.grads, self.m, self.v, self.lrs, self.d_step,
                               stream=stream)
+        if self.status_every and self.step_count % self.status_every == 0:
+            self.check(stream)
+
+    def replay(self, graph, steps: int):
+        """Replays a captured step `steps` times, reading the device status
+        every status_every replays and after the last."""
+        for i in range(1, steps + 1):
+            graph.replay()
+            self.step_count += 1
+            if self.status_every and (i % self.status_every == 0 or i == steps):
+                self.check()
 
     def capture(self):
         """Records one training step (every kernel of it, on one stream) in a
@@ -691,13 +720,19 @@ class Trainer:
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self.step()
+        every, self.status_every = self.status_every, 0   # no synchronisation inside the capture
+        try:
+            with torch.cuda.graph(g):
+                self.step()
+        finally:
+            self.status_every = every
         self.step_count -= 1  # the capture itself does not run
         return g
 
-    def check(self):
-        rc, st, npairs = self.r.frame.read_status()
+    def check(self, stream=None):
+        """Reads the device status (synchronises): raises DqoError on pair-list
+        overflow or a device wait that gave up; returns the pair count."""
+        rc, st, npairs = self.r.frame.read_status(stream)
         if st & (STATUS_OVERFLOW | STATUS_TIMEOUT):
             raise DqoError(ECAPACITY if st & STATUS_OVERFLOW else EINTERNAL,
                            f"status {st}, pairs {npairs}, capacity {self.r.frame.capacity}")

@@ -58,6 +58,11 @@ int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera
                             (long long)first, (long long)count, (long long)d->n);
         }
     }
+    if (d->jobs) {
+        for (int v = 0; v < d->n_views; ++v)
+            if (d->jobs[v] < -1 || d->jobs[v] >= d->K)
+                return fail(ctx, DQO_EINVAL, "job of view %d = %d outside [-1, K = %d)", v, d->jobs[v], d->K);
+    }
     const int W = cams[0].width, H = cams[0].height;
     if (W < 1 || H < 1 || W > 32767 || H > 32767) return fail(ctx, DQO_EINVAL, "image size %dx%d invalid", W, H);
     for (int v = 0; v < d->n_views; ++v) {
@@ -87,7 +92,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.items = (int64_t)d->n * d->n_views;
     const int64_t M = g.items, cap = d->pair_capacity;
     const int64_t ts = d->dtype == DQO_F64 ? 8 : 4;
-    g.depth_blocks = (int)((M + kSortThreads * depth_ipt(M) - 1) / (kSortThreads * depth_ipt(M)));
+    g.depth_blocks = (int)((M + kDepthNt * depth_ipt(M) - 1) / (kDepthNt * depth_ipt(M)));
     g.scan_blocks = (int)((M + kScanTile - 1) / kScanTile);
     g.pair_blocks = (int)((cap + kPairTileMin - 1) / kPairTileMin);
     int64_t sz[DQO_BUF_COUNT];
@@ -200,6 +205,25 @@ Frame<T> make_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camer
         dc.limy = (T)(1.3 * 0.5 * cams[v].height / cams[v].fy);
         dc.seg_lo = d->segments ? (int32_t)d->segments[2 * v] : 0;
         dc.seg_hi = d->segments ? (int32_t)(d->segments[2 * v] + d->segments[2 * v + 1]) : (int32_t)d->n;
+        const int W = cams[0].width, H = cams[0].height;
+        int32_t x0 = 0, y0 = 0, x1 = W, y1 = H;
+        if (d->windows) {
+            x0 = std::max(0, d->windows[4 * v]);
+            y0 = std::max(0, d->windows[4 * v + 1]);
+            x1 = std::min(W, d->windows[4 * v + 2]);
+            y1 = std::min(H, d->windows[4 * v + 3]);
+            if (x1 <= x0 || y1 <= y0) x0 = y0 = x1 = y1 = 0;
+        }
+        dc.win_x0 = x0;
+        dc.win_y0 = y0;
+        dc.win_x1 = x1;
+        dc.win_y1 = y1;
+        const int tw = ctx->cfg.tile_w, th = ctx->cfg.tile_h;
+        dc.tile_x0 = x0 / tw;
+        dc.tile_y0 = y0 / th;
+        dc.tile_x1 = x1 > x0 ? (x1 - 1) / tw : -1;
+        dc.tile_y1 = y1 > y0 ? (y1 - 1) / th : -1;
+        dc.job = d->jobs ? d->jobs[v] : -1;
     }
     f.views.n_views = d->n_views;
     f.views.W = cams[0].width;
@@ -261,6 +285,54 @@ int run(const dqo_ctx* ctx, const char* what, F&& fn) {
     if (e != hipSuccess) return hip_fail(ctx, e, what);
     ctx->err[0] = 0;
     return DQO_OK;
+}
+
+int check_loss_args(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const dqo_images* img,
+                    const dqo_targets* tgt, const dqo_loss_weights* w, double* loss, const dqo_image_grads* gr) {
+    int rc = validate_frame(ctx, d, cams);
+    if (rc) return rc;
+    if (!img || !img->color || !img->depth || !img->p_target)
+        return fail(ctx, DQO_EINVAL, "object_loss needs color, depth and p_target images");
+    if (!tgt || !tgt->color || !tgt->depth) return fail(ctx, DQO_EINVAL, "object_loss needs target color and depth");
+    if (!w || !loss) return fail(ctx, DQO_EINVAL, "weights and loss must not be NULL");
+    if (!(w->ce_eps > 0)) return fail(ctx, DQO_EINVAL, "ce_eps must be > 0");
+    if (gr && (!gr->d_color || !gr->d_depth || !gr->d_p_target))
+        return fail(ctx, DQO_EINVAL, "object_loss gradients need d_color, d_depth and d_p_target");
+    if (d->jobs && !tgt->id) {
+        for (int v = 0; v < d->n_views; ++v)
+            if (d->jobs[v] >= 0) return fail(ctx, DQO_EINVAL, "per-object jobs need the target ids");
+    }
+    return DQO_OK;
+}
+
+int enqueue_loss(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const dqo_images* img,
+                 const dqo_targets* tgt, const dqo_loss_weights* w, double* loss, const dqo_image_grads* gr,
+                 double* partials, uint32_t* n_valid, void* stream) {
+    dqo_image_grads none;
+    memset(&none, 0, sizeof(none));
+    const int64_t HW = (int64_t)cams[0].width * cams[0].height;
+    const dqo_image_grads& g = gr ? *gr : none;
+    // each view's window and job, as the render kernels see them
+    Geo geo = geometry(ctx, d, cams);
+    Frame<float> f = make_frame<float>(ctx, d, cams, geo, nullptr);
+    LossViewsHost lv;
+    memset(&lv, 0, sizeof(lv));
+    for (int v = 0; v < d->n_views; ++v) {
+        const DevCam<float>& c = f.views.cam[v];
+        lv.win[v][0] = c.win_x0;
+        lv.win[v][1] = c.win_y0;
+        lv.win[v][2] = c.win_x1;
+        lv.win[v][3] = c.win_y1;
+        lv.job[v] = c.job;
+    }
+    lv.W = cams[0].width;
+    return run(ctx, "object_loss", [&] {
+        if (d->dtype == DQO_F32)
+            return launch_object_loss<float>(HW, d->n_views, *img, *tgt, *w, loss, g, lv, partials, n_valid,
+                                             (hipStream_t)stream);
+        return launch_object_loss<double>(HW, d->n_views, *img, *tgt, *w, loss, g, lv, partials, n_valid,
+                                          (hipStream_t)stream);
+    });
 }
 
 }  // namespace
@@ -423,28 +495,13 @@ int dqo_render_forward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_ca
 int dqo_object_loss(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, const dqo_images* img,
                     const dqo_targets* tgt, const dqo_loss_weights* w, double* loss, const dqo_image_grads* gr,
                     void* state, void* stream) {
-    int rc = validate_frame(ctx, d, cams);
+    int rc = check_loss_args(ctx, d, cams, img, tgt, w, loss, gr);
     if (rc) return rc;
-    if (!img || !img->color || !img->depth || !img->p_target)
-        return fail(ctx, DQO_EINVAL, "object_loss needs color, depth and p_target images");
-    if (!tgt || !tgt->color || !tgt->depth) return fail(ctx, DQO_EINVAL, "object_loss needs target color and depth");
-    if (!w || !loss || !state) return fail(ctx, DQO_EINVAL, "weights, loss and state must not be NULL");
-    if (!(w->ce_eps > 0)) return fail(ctx, DQO_EINVAL, "ce_eps must be > 0");
-    if (gr && (!gr->d_color || !gr->d_depth || !gr->d_p_target))
-        return fail(ctx, DQO_EINVAL, "object_loss gradients need d_color, d_depth and d_p_target");
-    dqo_image_grads none;
-    memset(&none, 0, sizeof(none));
+    if (!state) return fail(ctx, DQO_EINVAL, "state must not be NULL");
     Geo g = geometry(ctx, d, cams);
-    if (d->dtype == DQO_F32) {
-        Frame<float> f = make_frame<float>(ctx, d, cams, g, state);
-        return run(ctx, "object_loss", [&] {
-            return launch_object_loss<float>(f, *img, *tgt, *w, loss, gr ? *gr : none, (hipStream_t)stream);
-        });
-    }
-    Frame<double> f = make_frame<double>(ctx, d, cams, g, state);
-    return run(ctx, "object_loss", [&] {
-        return launch_object_loss<double>(f, *img, *tgt, *w, loss, gr ? *gr : none, (hipStream_t)stream);
-    });
+    StatePtrs s = state_ptrs(g, state);
+    return enqueue_loss(ctx, d, cams, img, tgt, w, loss, gr, &s.ctrl->loss_partials[0][0], &s.ctrl->n_valid,
+                        stream);
 }
 
 int dqo_render_backward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, void* state,

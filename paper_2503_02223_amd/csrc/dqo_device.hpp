@@ -25,9 +25,26 @@ constexpr int kSortThreads = 256;
 // depth passes are fastest with 2048-item blocks at 200k items (4096: 1700 ->
 // 1672 it/s, 8192 slower still) and with 8192-item blocks from about a
 // million (175 -> 180 it/s at 9.6M); 4096 in between.
-constexpr int kPairIptShort = 16, kPairIptLong = 32;
-constexpr int kPairTileMin = kSortThreads * kPairIptShort;  // sizes the pair look-back arrays
-inline int depth_ipt(int64_t items) { return items < (int64_t(1) << 18) ? 8 : items < (int64_t(1) << 19) ? 16 : 32; }
+// Workgroup sizes of the depth and pair passes (256 or 1024 threads).
+#ifndef DQO_DEPTH_NT
+#define DQO_DEPTH_NT 256
+#endif
+#ifndef DQO_PAIR_NT
+#define DQO_PAIR_NT 256
+#endif
+#ifndef DQO_PAIR_IPT_SHORT
+#define DQO_PAIR_IPT_SHORT (DQO_PAIR_NT == 256 ? 16 : 8)
+#endif
+#ifndef DQO_DEPTH_IPT_SMALL
+#define DQO_DEPTH_IPT_SMALL (DQO_DEPTH_NT == 256 ? 8 : 4)
+#endif
+constexpr int kDepthNt = DQO_DEPTH_NT, kPairNt = DQO_PAIR_NT;
+constexpr int kPairIptShort = DQO_PAIR_IPT_SHORT, kPairIptLong = 2 * DQO_PAIR_IPT_SHORT;
+constexpr int kPairTileMin = kPairNt * kPairIptShort;  // sizes the pair look-back arrays
+inline int depth_ipt(int64_t items) {
+    constexpr int s = DQO_DEPTH_IPT_SMALL;
+    return items < (int64_t(1) << 18) ? s : items < (int64_t(1) << 19) ? 2 * s : 4 * s;
+}
 // Scan + emission: one record per thread, 1024 per block, so that each of the
 // 16 wavefronts emits the pairs of its own 64 records.
 constexpr int kSegLen = 64;        // pairs per backward segment of a 64-pixel tile
@@ -38,9 +55,11 @@ constexpr int kScanTile = kScanThreads * kScanIpt;
 constexpr int kMaxDepthPasses = 4;
 constexpr int kMaxPairPasses = 4;
 constexpr int kLossBlocks = 512;
+constexpr int kLossParts = 8;      // partial sums per loss workgroup (6 used)
 
 // Counter slots in the control block (dynamic block index per look-back chain).
 constexpr int kCounterDepth = 0;   // + pass
+constexpr int kCounterScan = 4;    // scan + emission blocks (ticket order after a timeout)
 constexpr int kCounterPair = 5;    // + pass
 constexpr int kCounterAdam = 12;   // workgroups done in the fused project-backward + Adam
 constexpr int kCounterSegTotal = 13;  // entries in the backward's segment list
@@ -55,12 +74,17 @@ struct Ctrl {
     uint32_t num_pairs;   // total pairs requested (may exceed the capacity)
     uint32_t n_valid;     // valid-depth pixel count of the last loss
     uint32_t counters[kNumCounters];
+    // Which forward the segmented backward's boundary states, tile ends and
+    // segment list belong to: the binning epoch and the addresses of that
+    // forward's `last` and `target` images.  A backward whose frame or images
+    // differ walks the whole tiles instead (the stored states are not its own).
+    uint64_t seg_stamp[3];
     // Digit histograms of every radix pass, in kHistCopies copies: a workgroup
     // adds its counts to copy (block index mod kHistCopies), which spreads the
     // atomics over more addresses; a radix pass sums the copies of its digit.
     uint32_t hist_depth[kHistCopies][kMaxDepthPasses][kRadixBins];
     uint32_t hist_pair[kHistCopies][kMaxPairPasses][kRadixBins];
-    double loss_partials[kLossBlocks][4];
+    double loss_partials[kLossBlocks][kLossParts];
 };
 
 template <typename T>
@@ -70,7 +94,21 @@ struct DevCam {
     T fx, fy, cx, cy;
     T limx, limy;  // |x/z|, |y/z| limits of the projection Jacobian (1.3 x half field of view)
     int32_t seg_lo, seg_hi;  // Gaussians [seg_lo, seg_hi) are seen by this view
+    int32_t win_x0, win_y0, win_x1, win_y1;    // pixels rendered: x0 <= u < x1, y0 <= v < y1
+    int32_t tile_x0, tile_y0, tile_x1, tile_y1;  // tiles overlapping the window (inclusive; empty if x1 < x0)
+    int32_t job;  // -1 whole-scene view, else the object of a per-object job
 };
+
+// Whether pixel (u, v) of a view is rendered (inside the image and the window).
+template <typename T>
+__device__ __forceinline__ bool in_window(const DevCam<T>& c, int u, int v) {
+    return u >= c.win_x0 && u < c.win_x1 && v >= c.win_y0 && v < c.win_y1;
+}
+
+// The target id a view's pixel is rendered against: the observed id t in a
+// whole-scene view; in a per-object job of object k, k where t == k and -1
+// ("not this object", probability T_final) elsewhere.
+__device__ __forceinline__ int job_target(int job, int t) { return job < 0 ? t : (t == job ? job : -1); }
 
 // Everything a kernel needs to know about the views (passed by value).
 template <typename T>
@@ -92,10 +130,6 @@ struct Consts {
 // Segments of a tile's pair range for the segmented backward (0 for an empty
 // tile); the last one takes the rest of the range when a tile has more than
 // kSegMax.
-#ifndef DQO_SEG_UNITS
-#define DQO_SEG_UNITS 16384
-#endif
-constexpr int kSegUnits = DQO_SEG_UNITS;  // target length of the backward's segment list
 // Segmenting the backward pays where there are few tiles for the machine (the
 // longest ranges then finish last); with more tiles than this the grid is
 // balanced by tiles alone and the boundary states, the list and the restarts
@@ -242,7 +276,7 @@ struct StatePtrs {
     // Segmented backward of 64-pixel tiles: a tile's pair range is walked in
     // segments of kSegLen pairs, one wavefront each, restarted from
     // per-pixel states the forward stores at the segment boundaries.
-    uint32_t* seg_list;   // [seg_cap] (tile << 8 | segment) in launch order, then ~0u
+    uint32_t* seg_list;   // [seg_cap] (tile, segment << 8 | 1) in launch order (built after the forward)
     uint32_t* ckpt_base;  // [V*tiles] first boundary record of each tile
     int32_t* tile_last;   // [V*tiles] last blended position in each tile (forward)
     void* ckpt;           // [ckpt_cap][6][64] T, colour (3), depth, target probability before each boundary
@@ -286,10 +320,20 @@ hipError_t launch_render_backward(const Frame<T>& f, const dqo_images& img, cons
                                   hipStream_t st);
 template <typename T>
 hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads, hipStream_t st);
+// Object loss over V images of HW pixels; per-workgroup partial sums in
+// partials[loss_partial_blocks(V * HW)][kLossParts] (at most kLossBlocks - 1
+// rows), the valid-depth pixel count in *n_valid.  views: each view's pixel
+// window and job (-1 whole scene).
+struct LossViewsHost {
+    int32_t win[DQO_MAX_VIEWS][4];
+    int32_t job[DQO_MAX_VIEWS];
+    int32_t W;
+};
+int loss_partial_blocks(int64_t npix);
 template <typename T>
-hipError_t launch_object_loss(const Frame<T>& f, const dqo_images& img, const dqo_targets& tgt,
+hipError_t launch_object_loss(int64_t HW, int V, const dqo_images& img, const dqo_targets& tgt,
                               const dqo_loss_weights& w, double* loss, const dqo_image_grads& g,
-                              hipStream_t st);
+                              const LossViewsHost& views, double* partials, uint32_t* n_valid, hipStream_t st);
 template <typename T>
 hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, const dqo_adam& hp, int64_t step, int64_t* d_step,
                        hipStream_t st, int rows = kParams);
@@ -317,7 +361,8 @@ inline int resident_blocks() {
     return n;
 }
 hipError_t launch_clear_written(const StatePtrs& s, hipStream_t st);
-hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, hipStream_t st);
+hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, const void* last, const void* target,
+                               hipStream_t st);
 // Whether the 64-pixel-tile backward of a frame with these tiles runs
 // segmented (the forward then stores boundary states and the sort their
 // offsets).

@@ -156,10 +156,11 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
                 const T ex = T(3) * sqrt(pr.s00), ey = T(3) * sqrt(pr.s11);
                 T x0 = floor((pr.mx - ex) / T(V.tile_w)), x1 = floor((pr.mx + ex) / T(V.tile_w));
                 T y0 = floor((pr.my - ey) / T(V.tile_h)), y1 = floor((pr.my + ey) / T(V.tile_h));
-                x0 = max(x0, T(0));
-                y0 = max(y0, T(0));
-                x1 = min(x1, T(V.tiles_x - 1));
-                y1 = min(y1, T(V.tiles_y - 1));
+                // tiles of the view's window only (the whole image unless windowed)
+                x0 = max(x0, T(V.cam[v].tile_x0));
+                y0 = max(y0, T(V.cam[v].tile_y0));
+                x1 = min(x1, T(V.cam[v].tile_x1));
+                y1 = min(y1, T(V.cam[v].tile_y1));
                 if (x0 <= x1 && y0 <= y1) {
                     rc = make_short4((short)x0, (short)y0, (short)x1, (short)y1);
                     cnt = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
@@ -250,7 +251,14 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     __shared__ uint32_t s_tmp[kScanThreads / kWave];
     __shared__ uint32_t s_base, s_bid, s_agg;
     const int tid = threadIdx.x;
-    if (tid == 0) s_bid = blockIdx.x;
+    if (tid == 0) {
+        // Single-level scans chain every block to its predecessor by
+        // workgroup index, which needs the whole grid on the device at once;
+        // once a bounded wait has given up (status bit), the order comes from
+        // a ticket instead.  The two-level scan waits on nothing.
+        const bool ticket = !block_base && (ctrl->status & (uint32_t)DQO_STATUS_TIMEOUT) != 0u;
+        s_bid = ticket ? atomicAdd(&ctrl->counters[kCounterScan], 1u) : blockIdx.x;
+    }
     if (tid < kRadixBins) {
         for (int p = 0; p < kMaxPairPasses; ++p) s_hist[p][tid] = 0u;
     }
@@ -386,7 +394,7 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
                                          s.depth_vals[src ^ 1], nullptr, (uint32_t)M, p * kRadixBits,
                                          &s.ctrl->hist_depth[0][p][0], kMaxDepthPasses * kRadixBins, s.hist_copies_depth,
                                          s.lb_depth + (size_t)p * s.depth_blocks * kRadixBins,
-                                         &s.ctrl->counters[kCounterDepth + p], s.ctrl, st, depth_ipt(M));
+                                         &s.ctrl->counters[kCounterDepth + p], s.ctrl, st, kDepthNt, depth_ipt(M));
         if (e != hipSuccess) return e;
         src ^= 1;
     }

@@ -90,6 +90,51 @@ __device__ __forceinline__ void store_splat_lds<float>(float* dst, const float (
     for (int q = 0; q < 3; ++q) d4[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
 }
 
+// Whether a splat can contribute at any rendered pixel centre of a tile,
+// whose centres lie in the box [bx0, bx1] x [by0, by1]: the smallest
+// Mahalanobis form Q over the box (Q is convex: 0 where the mean lies in the
+// box, else the least of the four edge minima, each edge's at its clamped
+// stationary point) against q_max, and the largest alpha, o exp(-Q_min / 2),
+// against alpha_min.  About a quarter of the (tile, Gaussian) pairs that the
+// 3-sigma box puts in a tile fail it.  Both bounds keep a margin, so the
+// per-pixel tests, evaluated in other arithmetic, can never accept a splat
+// this rejects: skipping the rejected ones leaves every result bitwise the
+// same (a rejected splat would carry zero weight at every pixel).
+template <typename T>
+__device__ __forceinline__ bool tile_may_contribute(const T (&sp)[kSplatWords], int px0, int px1, int py0, int py1,
+                                                    const Consts<T>& cs) {
+    if (px0 > px1 || py0 > py1) return false;
+    const T bx0 = T(px0) + T(0.5), bx1 = T(px1) + T(0.5), by0 = T(py0) + T(0.5), by1 = T(py1) + T(0.5);
+    const T mx = sp[0], my = sp[1], A = sp[2], B = sp[3], C = sp[4];
+    auto qf = [&](T dx, T dy) { return fmadd(A * dx, dx, fmadd(T(2) * B * dx, dy, C * dy * dy)); };
+    const T iA = T(1) / A, iC = T(1) / C;
+    T q = T(0);
+    if (!(mx >= bx0 && mx <= bx1 && my >= by0 && my <= by1)) {
+        const T ex0 = bx0 - mx, ex1 = bx1 - mx, ey0 = by0 - my, ey1 = by1 - my;
+        q = min(min(qf(ex0, min(max(-B * ex0 * iC, ey0), ey1)), qf(ex1, min(max(-B * ex1 * iC, ey0), ey1))),
+                min(qf(min(max(-B * ey0 * iA, ex0), ex1), ey0), qf(min(max(-B * ey1 * iA, ex0), ex1), ey1)));
+    }
+    return q <= cs.q_max * T(1.001) + T(1e-3) && sp[5] * fast_exp<T>(T(-0.5) * q) >= cs.alpha_min * T(0.999);
+}
+
+// The pixels of a tile that are rendered (inside the image and the view's
+// window): columns [px0, px1], rows [py0, py1] (empty when px0 > px1 or
+// py0 > py1).  Wave-uniform integers.
+template <typename T>
+__device__ __forceinline__ void tile_pixel_box(const Views<T>& V, int view, int tx, int ty, int TW, int TH, int& px0,
+                                               int& px1, int& py0, int& py1) {
+    const DevCam<T>& c = V.cam[view];
+    px0 = max(tx * TW, c.win_x0);
+    px1 = min(tx * TW + TW, c.win_x1) - 1;
+    py0 = max(ty * TH, c.win_y0);
+    py1 = min(ty * TH + TH, c.win_y1) - 1;
+}
+
+// Number of set bits of a wave-wide ballot below this lane.
+__device__ __forceinline__ int rank_below(uint64_t bal) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+}
+
 // Records whose contribution tests are evaluated together (FP32; FP64 keeps 4
 // to bound register use).
 #ifndef DQO_FWD_GROUP
@@ -107,7 +152,9 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     uint32_t M, const uint32_t* __restrict__ ckpt_base, T* __restrict__ ckpt, uint32_t ckpt_cap,
     int32_t* __restrict__ tile_last) {
     constexpr int BLOCK = TW * TH;
+    constexpr int NW = BLOCK / kWave;
     __shared__ __align__(16) T s_sp[BLOCK * kSplatWords];
+    __shared__ int s_wc[NW];
     extern __shared__ unsigned char s_dyn[];
     T* s_P = reinterpret_cast<T*>(s_dyn);  // [K][BLOCK] when PROBS
 
@@ -117,19 +164,24 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     const int t = tile - view * V.tiles_per_view;
     const int ty = t / V.tiles_x, tx = t - ty * V.tiles_x;
     const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
-    const bool inside = px < V.W && py < V.H;
+    // pixels of the image outside the view's window are written as empty
+    const bool in_img = px < V.W && py < V.H;
+    const bool inside = in_img && in_window(V.cam[view], px, py);
     const int64_t HW = (int64_t)V.W * V.H;
     const int64_t pix = (int64_t)py * V.W + px;
     const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
     const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
     int tgt = -2;
-    if (target && inside) tgt = target[view * HW + pix];
+    if (target && in_img) tgt = job_target(V.cam[view].job, target[view * HW + pix]);
     if (PROBS)
         for (int k = 0; k < K; ++k) s_P[k * BLOCK + tid] = T(0);
 
     T Tt = T(1), c0 = T(0), c1 = T(0), c2 = T(0), dd = T(0), pt = T(0);
     int lastpos = -1, nb_count = 0;
     bool done = !inside;
+    int bx0, bx1, by0, by1;
+    tile_pixel_box<T>(V, view, tx, ty, TW, TH, bx0, bx1, by0, by1);
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
     // Software prefetch: this lane's record of the next batch is loaded into
     // registers while the current batch is walked; the pair index one batch
     // further ahead is loaded one step earlier still.
@@ -156,11 +208,28 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
                 }
             }
         }
-        if (b0 + tid < re) store_splat_lds<T>(s_sp + tid * kSplatWords, pf);
+        // The batch's records that may contribute somewhere in the tile, in
+        // order, compacted into LDS with their positions in the pad word.
+        const bool cand = (b0 + tid < re) && tile_may_contribute<T>(pf, bx0, bx1, by0, by1, cs);
+        const uint64_t bal = __ballot(cand);
+        int nb = __popcll(bal), off = 0;
+        if constexpr (NW > 1) {
+            if (lane == 0) s_wc[wave] = nb;
+            __syncthreads();
+            nb = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                off += (w < wave) ? s_wc[w] : 0;
+                nb += s_wc[w];
+            }
+        }
+        if (cand) {
+            pf[kSplatWords - 1] = id_to_word<T>((int)(b0 + tid));
+            store_splat_lds<T>(s_sp + (off + rank_below(bal)) * kSplatWords, pf);
+        }
         __syncthreads();
         if (b0 + BLOCK + tid < re) load_splat<T>(pf, splats + (size_t)rec2 * kSplatWords);
         if (b0 + 2 * BLOCK + tid < re) rec2 = min(pvals[b0 + 2 * BLOCK + tid], M - 1);
-        const int nb = (int)min((uint32_t)BLOCK, re - b0);
         if (!wave_any(!done)) continue;
         // Groups of fwd_group<T>() records: their contribution tests (quadratic
         // form, exponential, thresholds) are independent and evaluated side
@@ -202,7 +271,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
                 const int id = word_to_id<T>(rec[k][7]);
                 pt += (id == tgt) ? w : T(0);
                 if (w != T(0)) {
-                    lastpos = (int)(b0 + j0 + k);
+                    lastpos = word_to_id<T>(rec[k][kSplatWords - 1]);
                     ++nb_count;
                     if (PROBS && id >= 0 && id < K) s_P[id * BLOCK + tid] += w;
                 }
@@ -221,7 +290,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
             if (tid == 0) tile_last[tile] = m;
         }
     }
-    if (!inside) return;
+    if (!in_img) return;
     const int64_t o = view * HW + pix;
     color[(view * 3 + 0) * HW + pix] = c0 + Tt * cs.bg[0];
     color[(view * 3 + 1) * HW + pix] = c1 + Tt * cs.bg[1];
@@ -334,6 +403,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     __shared__ uint32_t s_slot[BLOCK];
     __shared__ T s_red[2][NW][kWave];
     __shared__ int s_maxlast;
+    __shared__ int s_wc[NW];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -343,7 +413,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     const int t = tile - view * V.tiles_per_view;
     const int ty = t / V.tiles_x, tx = t - ty * V.tiles_x;
     const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
-    const bool inside = px < V.W && py < V.H;
+    const bool inside = px < V.W && py < V.H && in_window(V.cam[view], px, py);
     const int64_t HW = (int64_t)V.W * V.H;
     const int64_t pix = (int64_t)py * V.W + px;
     const int64_t o = view * HW + pix;
@@ -363,7 +433,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
         gd = dD ? dD[o] : T(0);
         gt = dT ? dT[o] : T(0);
         if (dPt && target) {
-            tgt = target[o];
+            tgt = job_target(V.cam[view].job, target[o]);
             gpt = dPt[o];
             if (tgt == -1) gt += gpt;
         }
@@ -377,15 +447,38 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     // stay unmarked (their partials count as zero).
     const uint32_t hi = (maxlast >= (int)rs) ? (uint32_t)(maxlast + 1) : rs;
     T S = Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
+    int bx0, bx1, by0, by1;
+    tile_pixel_box<T>(V, view, tx, ty, TW, TH, bx0, bx1, by0, by1);
     int buf = 0;
     for (uint32_t bend = hi; bend > rs;) {
         const uint32_t bstart = (bend - rs > (uint32_t)BLOCK) ? bend - BLOCK : rs;
-        const int nb = (int)(bend - bstart);
+        const int nbr = (int)(bend - bstart);
         __syncthreads();
-        if (tid < nb) {
+        // the batch's records that may contribute in the tile, compacted in
+        // order with their positions in the pad word
+        T r[kSplatWords];
+        uint32_t slot = 0u;
+        bool cand = false;
+        if (tid < nbr) {
             const uint32_t rec = min(pvals[bstart + tid], M - 1);
-            copy_splat<T>(s_sp + tid * kSplatWords, splats + (size_t)rec * kSplatWords);
-            s_slot[tid] = pair_slot(rects, offsets, rec, tx, ty);
+            load_splat<T>(r, splats + (size_t)rec * kSplatWords);
+            cand = tile_may_contribute<T>(r, bx0, bx1, by0, by1, cs);
+            slot = pair_slot(rects, offsets, rec, tx, ty);
+        }
+        const uint64_t bal = __ballot(cand);
+        if (lane == 0) s_wc[wave] = __popcll(bal);
+        __syncthreads();
+        int nb = 0, off = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            off += (w < wave) ? s_wc[w] : 0;
+            nb += s_wc[w];
+        }
+        if (cand) {
+            const int q = off + rank_below(bal);
+            r[kSplatWords - 1] = id_to_word<T>((int)(bstart + tid));
+            store_splat_lds<T>(s_sp + q * kSplatWords, r);
+            s_slot[q] = slot;
         }
         __syncthreads();
         for (int c0 = nb - 1; c0 >= 0; c0 -= kChunk) {
@@ -400,7 +493,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
                 const T* sp = s_sp + jl * kSplatWords;
                 T dx, dy;
                 const T Q = quad_form(sp, sx, sy, dx, dy);
-                const bool in = (Q <= cs.q_max) && ((int)(bstart + jl) <= lastp);
+                const bool in = (Q <= cs.q_max) && (word_to_id<T>(sp[kSplatWords - 1]) <= lastp);
                 if (!wave_any(in)) continue;
                 const T G = falloff<T>(Q);
                 const T araw = sp[5] * G;
@@ -519,13 +612,13 @@ __device__ __forceinline__ void backward_unit(
         seg = e.y >> 8;
         seg_n = max(e.y & 255u, 1u);
     } else {
-        tile = (int)min(schedule[unit], (uint32_t)(gridDim.x - 1));
+        tile = (int)min(schedule[unit], (uint32_t)(V.n_views * V.tiles_per_view - 1));
     }
     const int view = tile / V.tiles_per_view;
     const int t = tile - view * V.tiles_per_view;
     const int ty = t / V.tiles_x, tx = t - ty * V.tiles_x;
     const int px = tx * TW + (lane % TW), py = ty * TH + (lane / TW);
-    const bool inside = px < V.W && py < V.H;
+    const bool inside = px < V.W && py < V.H && in_window(V.cam[view], px, py);
     const int64_t HW = (int64_t)V.W * V.H;
     const int64_t pix = (int64_t)py * V.W + px;
     const int64_t o = view * HW + pix;
@@ -553,7 +646,7 @@ __device__ __forceinline__ void backward_unit(
         gd = dD ? dD[o] : T(0);
         gt = dT ? dT[o] : T(0);
         if (dPt && target) {
-            tgt = target[o];
+            tgt = job_target(V.cam[view].job, target[o]);
             gpt = dPt[o];
             if (tgt == -1) gt += gpt;
         }
@@ -593,6 +686,8 @@ __device__ __forceinline__ void backward_unit(
     for (int k = 0; k < 64; ++k) v[k] = T(0);
     uint32_t chunk[kChunk] = {};              // pair slot of the Gaussian in each reduction slot
     const int lane_slot = lane / kGradWords;  // the reduction slot whose sum this lane stores
+    int bx0, bx1, by0, by1;
+    tile_pixel_box<T>(V, view, tx, ty, TW, TH, bx0, bx1, by0, by1);
 
     // walk state (wave-uniform): the LDS batch holds positions [bstart, bend)
     uint32_t bend = hi, bstart = hi;
@@ -647,14 +742,20 @@ __device__ __forceinline__ void backward_unit(
                 if (a_e <= a_s) return false;
                 bend = a_e;
                 bstart = a_s;
-                const int nb = (int)(bend - bstart);
+                const int nbr = (int)(bend - bstart);
                 __syncthreads();
-                if (lane < nb) {
-                    store_splat_lds<T>(s_sp + lane * kSplatWords, pf);
-                    s_slot[lane] = pf_slot;
+                // the records that may contribute in the tile, compacted in
+                // order with their positions in the pad word
+                const bool cand = lane < nbr && tile_may_contribute<T>(pf, bx0, bx1, by0, by1, cs);
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(cand);
+                if (cand) {
+                    const int q = rank_below(bal);
+                    pf[kSplatWords - 1] = id_to_word<T>((int)(bstart + lane));
+                    store_splat_lds<T>(s_sp + q * kSplatWords, pf);
+                    s_slot[q] = pf_slot;
                 }
                 __syncthreads();
-                jl = nb - 1;
+                jl = __popcll(bal) - 1;
                 a_e = b_e;
                 a_s = b_s;
                 if (lane < (int)(a_e - a_s)) {
@@ -668,7 +769,7 @@ __device__ __forceinline__ void backward_unit(
             lds_rec(jl);
             sp = cur;
             const T Q = quad_form(sp, sx, sy, dx, dy);
-            const bool in_q = Q <= cs.q_max, in_l = (int)(bstart + jl) <= lastp;
+            const bool in_q = Q <= cs.q_max, in_l = word_to_id<T>(sp[kSplatWords - 1]) <= lastp;
             const uint64_t m_in = __builtin_amdgcn_ballot_w64(in_q) & __builtin_amdgcn_ballot_w64(in_l);
             if (m_in == 0ull) {
                 --jl;
@@ -753,7 +854,7 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap, uint32_t M,
     const uint32_t* __restrict__ seg_list, const uint32_t* __restrict__ ckpt_base, const T* __restrict__ ckpt,
     uint32_t ckpt_cap, const T* __restrict__ color, const T* __restrict__ depth, const T* __restrict__ ptarget,
-    uint32_t* __restrict__ counters) {
+    const Ctrl* __restrict__ ctrl) {
     static_assert(TW * TH == kWave, "one wavefront per tile");
     __shared__ __align__(16) T s_sp[kWave * kSplatWords];
     __shared__ uint32_t s_slot[kWave];
@@ -765,11 +866,20 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     // the longest possible list, exits at once.  (A resident grid drawing
     // entries from a work counter was measured slower: the loop around the
     // walk raised its register demand past the budget and spilled.)
-    const uint32_t n_units = seg_list ? counters[kCounterSegTotal] : gridDim.x;
-    if (blockIdx.x >= n_units) return;
+    // The segments restart from states stored by one particular forward; if
+    // the frame was binned again since, or the images are another forward's,
+    // those states are not this backward's and every tile is walked whole
+    // instead (the grid holds at least one workgroup per tile).
+    const uint32_t n_tiles = (uint32_t)(V.n_views * V.tiles_per_view);
+    if (seg_list && (ctrl->seg_stamp[0] != (uint64_t)ctrl->epoch || ctrl->seg_stamp[1] != (uint64_t)(uintptr_t)last ||
+                     ctrl->seg_stamp[2] != (uint64_t)(uintptr_t)target))
+        seg_list = nullptr;
+    const uint32_t n_units = seg_list ? ctrl->counters[kCounterSegTotal] : n_tiles;
+    const uint32_t unit = blockIdx.x;
+    if (unit >= n_units) return;
     backward_unit<T, TW, TH>(V, cs, K, splats, rects, offsets, pvals, ranges, schedule, tfinal, last, target, dC, dD,
                              dT, dP, dPt, partials, written, cap, M, seg_list, ckpt_base, ckpt, ckpt_cap, color, depth,
-                             ptarget, s_sp, s_slot, blockIdx.x);
+                             ptarget, s_sp, s_slot, unit);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -778,9 +888,9 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
     const int blocks = f.views.n_views * f.views.tiles_per_view;
     if (blocks == 0) return hipSuccess;
     const StatePtrs& s = f.s;
-    // Boundary states and the backward's segment list, for a backward that
-    // can run segmented (no instance channels: their sums behind a boundary
-    // would need every object's prefix).
+    // Boundary states, tile ends and the backward's segment list, for a
+    // backward that can run segmented (no instance channels: their sums behind
+    // a boundary would need every object's prefix).
     const bool seg = segmented_backward(s, blocks) && !img.probs;
     if (img.probs && f.K > 0) {
         const size_t dyn = (size_t)f.K * TW * TH * sizeof(T);
@@ -799,7 +909,7 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
     if (seg) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_segment_list(s, blocks, st);
+        return launch_segment_list(s, blocks, img.last, img.target, st);
     }
     return hipGetLastError();
 }
@@ -815,12 +925,8 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
         // which also built the segment list).
         const bool seg = segmented_backward(s, blocks) && !img.probs && !g.d_probs && img.color && img.depth &&
                          (img.p_target || !g.d_p_target);
-        unsigned grid = (unsigned)blocks;
-        if (seg) {
-            // units = sum over tiles of ceil(k_t / g) <= segments / g + tiles,
-            // and g keeps segments / g within kSegUnits
-            grid = (unsigned)std::min<int64_t>(s.seg_cap, (int64_t)blocks + kSegUnits);
-        }
+        // units = segments up to each tile's end <= tiles + pairs / kSegLen = seg_cap
+        const unsigned grid = seg ? (unsigned)std::max<int64_t>(s.seg_cap, blocks) : (unsigned)blocks;
         hipLaunchKernelGGL((render_backward_wave_kernel<T, TW, TH>), dim3(grid),
                            dim3(kWave), 0, st, f.views, f.consts, f.K, (const T*)s.splats, s.rects, s.offsets,
                            s.pair_vals[0], s.ranges, s.schedule, (const T*)img.t_final, img.last, img.target,
@@ -828,7 +934,7 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
                            (const T*)g.d_p_target, (T*)s.partials, s.written, (uint32_t)s.capacity,
                            (uint32_t)s.items, seg ? s.seg_list : nullptr, s.ckpt_base, (const T*)s.ckpt,
                            (uint32_t)s.ckpt_cap, (const T*)img.color, (const T*)img.depth, (const T*)img.p_target,
-                           s.ctrl->counters);
+                           s.ctrl);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((render_backward_kernel<T, TW, TH>), dim3(blocks), dim3(TW * TH), 0, st, f.views, f.consts,

@@ -17,34 +17,42 @@
 
 namespace dqo {
 
-template <int IPT>
-__global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
+template <int NT, int IPT>
+__global__ __launch_bounds__(NT) void radix_pass_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
     const uint32_t* __restrict__ ghist, int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter,
-    Ctrl* ctrl) {
-    constexpr int kTile = kSortThreads * IPT;
+    int resident, Ctrl* ctrl) {
+    static_assert(NT >= kRadixBins && NT % kWave == 0, "one thread per digit at least");
+    constexpr int kTile = NT * IPT;
+    constexpr int kWaves = NT / kWave;
     __shared__ uint32_t s_keys[kTile];
     __shared__ uint32_t s_vals[kTile];
-    __shared__ uint32_t s_wcnt[kSortThreads / kWave][kRadixBins];
+    __shared__ uint32_t s_wcnt[kWaves][kRadixBins];
     __shared__ uint32_t s_dstart[kRadixBins];
     __shared__ uint32_t s_gbase[kRadixBins];
-    __shared__ uint32_t s_tmp[kSortThreads / kWave];
-    __shared__ uint32_t s_bid;
+    __shared__ uint32_t s_tmp[kWaves];
+    __shared__ uint32_t s_bid, s_epoch;
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
-    if (tid == 0) s_bid = counter ? atomicAdd(counter, 1u) : blockIdx.x;
-#pragma unroll
-    for (int w = 0; w < kSortThreads / kWave; ++w) s_wcnt[w][tid] = 0;
+    if (tid == 0) {
+        // Workgroup-index order needs the whole grid on the device at once;
+        // once a bounded wait has given up (status bit, kept until the caller
+        // clears it) the order comes from the ticket instead, every frame.
+        const bool ticket = !resident || (ctrl->status & (uint32_t)DQO_STATUS_TIMEOUT) != 0u;
+        s_bid = ticket ? atomicAdd(counter, 1u) : blockIdx.x;
+        s_epoch = ctrl->epoch;
+    }
+    for (int i = tid; i < kWaves * kRadixBins; i += NT) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t bid = s_bid;
     uint32_t n = n_host;
     if (n_dev) n = min(*n_dev, n_host);
     const uint32_t base = bid * (uint32_t)kTile;
     if (base >= n) return;  // uniform over the block; no later block waits on this one
-    const uint32_t epoch = ctrl->epoch;
+    const uint32_t epoch = s_epoch;
 
     uint32_t key[IPT], val[IPT], rank[IPT];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -77,24 +85,29 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     }
     __syncthreads();
 
-    // Thread t owns digit t: per-wave exclusive offsets and the block total.
+    // Thread t < 256 owns digit t: per-wave exclusive offsets and the block total.
     const int t = tid;
-    uint32_t total = 0;
+    const bool owner = t < kRadixBins;
+    uint32_t total = 0, gcount = 0;
+    if (owner) {
 #pragma unroll
-    for (int w = 0; w < kSortThreads / kWave; ++w) {
-        const uint32_t c = s_wcnt[w][t];
-        s_wcnt[w][t] = total;
-        total += c;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = s_wcnt[w][t];
+            s_wcnt[w][t] = total;
+            total += c;
+        }
+        // the digit's count over all keys: the sum of the histogram copies
+        for (int c = 0; c < hist_copies; ++c) gcount += ghist[c * hist_stride + t];
     }
-    const uint32_t dstart = block_exclusive_scan_256(total, s_tmp);
-    uint32_t gcount = 0;  // the digit's count over all keys: the sum of the histogram copies
-    for (int c = 0; c < hist_copies; ++c) gcount += ghist[c * hist_stride + t];
-    const uint32_t gdig = block_exclusive_scan_256(gcount, s_tmp);
-    s_dstart[t] = dstart;
-    // A digit that no key has anywhere needs no chain: every block skips it.
-    const uint32_t excl =
-        gcount ? lookback_exclusive(lb + t, kRadixBins, (int)bid, total, epoch, &ctrl->status) : 0u;
-    s_gbase[t] = gdig + excl;
+    const uint32_t dstart = block_exclusive_scan<NT>(total, s_tmp);
+    const uint32_t gdig = block_exclusive_scan<NT>(gcount, s_tmp);
+    if (owner) {
+        s_dstart[t] = dstart;
+        // A digit that no key has anywhere needs no chain: every block skips it.
+        const uint32_t excl =
+            gcount ? lookback_exclusive(lb + t, kRadixBins, (int)bid, total, epoch, &ctrl->status) : 0u;
+        s_gbase[t] = gdig + excl;
+    }
     __syncthreads();
 
 #pragma unroll
@@ -111,7 +124,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     }
     __syncthreads();
     const uint32_t cnt = min((uint32_t)kTile, n - base);
-    for (uint32_t q = tid; q < cnt; q += kSortThreads) {
+    for (uint32_t q = tid; q < cnt; q += NT) {
         const uint32_t k = s_keys[q];
         const uint32_t d = (k >> shift) & (kRadixBins - 1);
         const uint32_t o = s_gbase[d] + (q - s_dstart[d]);
@@ -217,110 +230,129 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
         ckpt_base, s_tmp, &s_total);
 }
 
-// The backward's work list, built after the forward: the segments of every
-// tile up to its last blended position, grouped into units of g consecutive
-// segments, in launch order (heaviest first), and the list's length.  g is
-// the smallest count that keeps the list near kSegUnits entries: splitting
-// pays where a few long tiles would otherwise finish last, and costs a
-// restart per unit where there are tiles enough to fill the machine.
-// Entries are (tile, first segment << 8 | segments); at most kSegTilesMax
-// tiles.
+// The backward's work list, built after the forward: every 64-pair segment
+// of every tile up to the tile's last blended position, one wavefront each,
+// in launch order (heaviest tile first): entries (tile, segment << 8 | 1),
+// and the list's length.  One thread per tile of the launch order, 1024 per
+// block; each block also sums the segments of all tiles before its own (at
+// most 7 per thread), so the blocks need nothing from one another.  At most
+// kSegTilesMax tiles.  Block 0 stamps the list with the binning epoch and
+// the forward's images, which the backward checks.
 __global__ __launch_bounds__(kSchedThreads) void segment_list_kernel(const uint32_t* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ schedule,
                                                                     const int32_t* __restrict__ tile_last, int tiles,
                                                                     uint32_t* __restrict__ seg_list, int64_t seg_cap,
-                                                                    Ctrl* __restrict__ ctrl) {
+                                                                    Ctrl* __restrict__ ctrl, uint64_t last_addr,
+                                                                    uint64_t target_addr) {
     __shared__ uint32_t s_tmp[kSchedThreads / kWave];
-    __shared__ uint32_t s_total;
     const int tid = threadIdx.x;
-    // At most kSegTilesMax tiles: each thread's contiguous chunk of the launch
-    // order is held in registers, its loads all in flight at once.
-    constexpr int kPer = kSegTilesMax / kSchedThreads;
-    uint32_t tt[kPer], kk[kPer];
+    const int b = blockIdx.x;
+    auto segs = [&](int p) -> uint32_t {
+        const uint32_t t = schedule[p];
+        const uint32_t rs = ranges[2 * t], re = ranges[2 * t + 1];
+        const int ml = tile_last[t];
+        return (ml >= (int)rs && ml < (int)re) ? min(((uint32_t)ml - rs) / (uint32_t)kSegLen + 1u, tile_segments(re - rs))
+                                               : 0u;
+    };
+    constexpr int kMaxBefore = kSegTilesMax / kSchedThreads - 1;
+    uint32_t before = 0;  // segments of the tiles before this block's, this thread's share
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const int p = tid * kPer + i;
-        tt[i] = p < tiles ? schedule[p] : ~0u;
+    for (int i = 0; i < kMaxBefore; ++i) {
+        const int p = i * kSchedThreads + tid;
+        if (i < b) before += segs(p);
     }
-    uint32_t nseg = 0;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        kk[i] = 0u;
-        if (tt[i] != ~0u) {
-            const uint32_t rs = ranges[2 * tt[i]], re = ranges[2 * tt[i] + 1];
-            const int ml = tile_last[tt[i]];
-            if (ml >= (int)rs && ml < (int)re)
-                kk[i] = min(((uint32_t)ml - rs) / (uint32_t)kSegLen + 1u, tile_segments(re - rs));
+    const int p = b * kSchedThreads + tid;
+    const uint32_t t = p < tiles ? schedule[p] : 0u;
+    const uint32_t k = p < tiles ? segs(p) : 0u;
+    const uint32_t base = block_exclusive_scan<kSchedThreads>(before, s_tmp) + before;  // inclusive: thread 1023 has all
+    __shared__ uint32_t s_base;
+    if (tid == kSchedThreads - 1) s_base = base;
+    __syncthreads();
+    uint32_t pos = s_base + block_exclusive_scan<kSchedThreads>(k, s_tmp);
+    for (uint32_t j = 0; j < k; ++j, ++pos)
+        if ((int64_t)pos < seg_cap) {
+            seg_list[2 * (size_t)pos] = t;
+            seg_list[2 * (size_t)pos + 1] = (j << 8) | 1u;
         }
-        nseg += kk[i];
+    if (b == (int)gridDim.x - 1 && tid == kSchedThreads - 1)
+        ctrl->counters[kCounterSegTotal] = (uint32_t)min((int64_t)pos, seg_cap);
+    if (b == 0 && tid == 0) {
+        // the forward these states belong to (checked by the backward)
+        ctrl->seg_stamp[0] = ctrl->epoch;
+        ctrl->seg_stamp[1] = last_addr;
+        ctrl->seg_stamp[2] = target_addr;
     }
-    const uint32_t incl = block_exclusive_scan<kSchedThreads>(nseg, s_tmp) + nseg;
-    if (tid == kSchedThreads - 1) s_total = incl;
-    __syncthreads();
-    const uint32_t g = max(1u, (s_total + (uint32_t)kSegUnits - 1u) / (uint32_t)kSegUnits);
-    uint32_t nunit = 0;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) nunit += (kk[i] + g - 1u) / g;
-    uint32_t pos = block_exclusive_scan<kSchedThreads>(nunit, s_tmp);
-#pragma unroll
-    for (int i = 0; i < kPer; ++i)
-        for (uint32_t j = 0; j < kk[i]; j += g, ++pos)
-            if ((int64_t)pos < seg_cap) {
-                seg_list[2 * (size_t)pos] = tt[i];
-                seg_list[2 * (size_t)pos + 1] = (j << 8) | min(g, kk[i] - j);
-            }
-    __syncthreads();
-    if (tid == kSchedThreads - 1) s_total = pos;
-    __syncthreads();
-    if (tid == 0) ctrl->counters[kCounterSegTotal] = (uint32_t)min((int64_t)s_total, seg_cap);
 }
 
-hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, hipStream_t st) {
+hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, const void* last, const void* target,
+                               hipStream_t st) {
     if (tiles_total > kSegTilesMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(segment_list_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, s.schedule, s.tile_last,
-                       tiles_total, s.seg_list, s.seg_cap, s.ctrl);
+    const int blocks = (tiles_total + kSchedThreads - 1) / kSchedThreads;
+    hipLaunchKernelGGL(segment_list_kernel, dim3(blocks), dim3(kSchedThreads), 0, st, s.ranges, s.schedule,
+                       s.tile_last, tiles_total, s.seg_list, s.seg_cap, s.ctrl, (uint64_t)(uintptr_t)last,
+                       (uint64_t)(uintptr_t)target);
     return hipGetLastError();
+}
+
+template <int NT, int IPT>
+static hipError_t radix_launch(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                               const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
+                               int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter, Ctrl* ctrl,
+                               hipStream_t st) {
+    const int blocks = (int)((n_host + NT * IPT - 1) / (NT * IPT));
+    // the whole grid is resident: workgroup index order (unless a wait has timed out)
+    const int res = blocks <= resident_blocks<radix_pass_kernel<NT, IPT>, NT>() ? 1 : 0;
+    hipLaunchKernelGGL((radix_pass_kernel<NT, IPT>), dim3(blocks), dim3(NT), 0, st, kin, vin, kout, vout, n_dev,
+                       n_host, shift, ghist, hist_stride, hist_copies, lb, counter, res, ctrl);
+    return hipGetLastError();
+}
+
+bool radix_resident(int nt, int ipt, int64_t items) {
+    const int64_t blocks = (items + (int64_t)nt * ipt - 1) / ((int64_t)nt * ipt);
+    int res = 0;
+#define DQO_RADIX_RES(NT_, IPT_) \
+    if (nt == NT_ && ipt == IPT_) res = resident_blocks<radix_pass_kernel<NT_, IPT_>, NT_>();
+    DQO_RADIX_RES(256, 8)
+    DQO_RADIX_RES(256, 16)
+    DQO_RADIX_RES(256, 32)
+    DQO_RADIX_RES(1024, 4)
+    DQO_RADIX_RES(1024, 8)
+    DQO_RADIX_RES(1024, 16)
+#undef DQO_RADIX_RES
+    return blocks <= res;
 }
 
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
                              int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter, Ctrl* ctrl,
-                             hipStream_t st, int ipt) {
+                             hipStream_t st, int nt, int ipt) {
     if (n_host == 0) return hipSuccess;
-    const int blocks = (int)((n_host + kSortThreads * ipt - 1) / (kSortThreads * ipt));
-    if (ipt != 8 && ipt != 16 && ipt != 32) return hipErrorInvalidValue;
-    const int resident = ipt == 8    ? resident_blocks<radix_pass_kernel<8>, kSortThreads>()
-                         : ipt == 16 ? resident_blocks<radix_pass_kernel<16>, kSortThreads>()
-                                     : resident_blocks<radix_pass_kernel<32>, kSortThreads>();
-    if (blocks <= resident)
-        counter = nullptr;  // the whole grid is resident: workgroup index order
-    if (ipt == 8)
-        hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
-    else if (ipt == 16)
-        hipLaunchKernelGGL(radix_pass_kernel<16>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
-    else if (ipt == 32)
-        hipLaunchKernelGGL(radix_pass_kernel<32>, dim3(blocks), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
-                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, ctrl);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+#define DQO_RADIX_CASE(NT_, IPT_)                                                                            \
+    if (nt == NT_ && ipt == IPT_)                                                                            \
+        return radix_launch<NT_, IPT_>(kin, vin, kout, vout, n_dev, n_host, shift, ghist, hist_stride, hist_copies, \
+                                       lb, counter, ctrl, st);
+    DQO_RADIX_CASE(256, 8)
+    DQO_RADIX_CASE(256, 16)
+    DQO_RADIX_CASE(256, 32)
+    DQO_RADIX_CASE(1024, 4)
+    DQO_RADIX_CASE(1024, 8)
+    DQO_RADIX_CASE(1024, 16)
+#undef DQO_RADIX_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st) {
     const uint32_t cap = (uint32_t)s.capacity;
     const uint32_t* n_dev = &s.ctrl->num_pairs;
-    // 4096-item blocks while that grid is resident at once, else 8192
-    const int64_t short_blocks = ((int64_t)cap + kPairTileMin - 1) / kPairTileMin;
-    const int ipt = short_blocks <= resident_blocks<radix_pass_kernel<kPairIptShort>, kSortThreads>() ? kPairIptShort
-                                                                                                       : kPairIptLong;
+    // short blocks while that grid is resident at once, else long ones
+    const bool short_ok = radix_resident(kPairNt, kPairIptShort, cap);
+    const int ipt = short_ok ? kPairIptShort : kPairIptLong;
     int src = s.pair_first_buf;
     for (int p = 0; p < s.pair_passes; ++p) {
         hipError_t e = launch_radix_pass(s.pair_keys[src], s.pair_vals[src], s.pair_keys[src ^ 1],
                                          s.pair_vals[src ^ 1], n_dev, cap, p * kRadixBits,
                                          &s.ctrl->hist_pair[0][p][0], kMaxPairPasses * kRadixBins, s.hist_copies_pair, s.lb_pair + (size_t)p * s.pair_blocks * kRadixBins,
-                                         &s.ctrl->counters[kCounterPair + p], s.ctrl, st, ipt);
+                                         &s.ctrl->counters[kCounterPair + p], s.ctrl, st, kPairNt, ipt);
         if (e != hipSuccess) return e;
         src ^= 1;
     }

@@ -34,6 +34,9 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
                              int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter, Ctrl* ctrl,
-                             hipStream_t st, int ipt);
+                             hipStream_t st, int nt, int ipt);
+// Whether a radix pass of nt threads x ipt items per block over `items` keys
+// fits on the device at once (resident-grid block order).
+bool radix_resident(int nt, int ipt, int64_t items);
 
 }  // namespace dqo

@@ -130,6 +130,35 @@ def test_segments_validated_on_host():
         assert (rc == 0) == ok, seg
 
 
+def test_jobs_and_windows_validated_on_host():
+    ctx = B.Context()
+    sc = scenes.single_view_scene(n=100)
+    cams = B.make_cameras(sc["cams"] * 2)
+    L = B.Layout()
+    for jobs, ok in (([-1, 2], True), ([0, 1], True), ([3, -1], False), ([-2, 0], False)):
+        arr = (ctypes.c_int32 * 2)(*jobs)
+        d = B.FrameDesc(n=100, n_views=2, K=3, pair_capacity=5000, dtype=B.F32,
+                        jobs=ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)))
+        rc = B.lib().dqo_state_layout(ctx.h, ctypes.byref(d), cams, ctypes.byref(L))
+        assert (rc == 0) == ok, jobs
+    # windows are clipped to the image (any values are accepted)
+    win = (ctypes.c_int32 * 8)(-5, -5, 500, 500, 10, 10, 5, 5)
+    d = B.FrameDesc(n=100, n_views=2, K=3, pair_capacity=5000, dtype=B.F32,
+                    windows=ctypes.cast(win, ctypes.POINTER(ctypes.c_int32)))
+    assert B.lib().dqo_state_layout(ctx.h, ctypes.byref(d), cams, ctypes.byref(L)) == 0
+    # the loss of per-object jobs needs the observed ids
+    arr = (ctypes.c_int32 * 2)(-1, 1)
+    d = B.FrameDesc(n=100, n_views=2, K=3, pair_capacity=5000, dtype=B.F32,
+                    jobs=ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)))
+    fake = ctypes.c_void_p(1)   # never dereferenced: validation fails first
+    img = B.Images(fake, fake, fake, fake, None, None, fake, fake, None)
+    tgt = B.Targets(fake, fake, None)
+    w = B.LossWeights(1.0, 1.0, 1.0, 1e-6)
+    assert B.lib().dqo_object_loss(ctx.h, ctypes.byref(d), cams, ctypes.byref(img), ctypes.byref(tgt),
+                                   ctypes.byref(w), fake, None, fake, None) == B.EINVAL
+    assert b"target ids" in B.lib().dqo_last_error(ctx.h)
+
+
 def test_new_entry_points_validate_on_host():
     """Incremental update, quadric refinement, pose gradient, fused backward +
     Adam and association: bad arguments are rejected with EINVAL and a

@@ -79,7 +79,7 @@ def _oracle_fwd(oracle, sc, cfg=None, pix=None):
     return oracle.render(sc["params"], sc["ids"], sc["cams"][0], cfg=cfg, K=sc["K"], pix=pix)
 
 
-@pytest.mark.parametrize("seed,tile", [(0, (16, 16)), (3, (16, 16)), (4, (8, 8))])
+@pytest.mark.parametrize("seed,tile", [(0, (16, 16)), (3, (16, 16)), (4, (8, 8)), (5, (16, 8)), (6, (8, 32))])
 def test_render_forward_parity(oracle, seed, tile):
     sc = scenes.single_view_scene(seed=seed, n=2000)
     r, p, ids = _frame(sc, ctx=B.Context(tile_w=tile[0], tile_h=tile[1]))
@@ -129,7 +129,8 @@ def _sparse_upstream(seed, ref, H, W, K, keep):
     return g
 
 
-@pytest.mark.parametrize("seed,tile", [(0, (16, 16)), (2, (16, 16)), (0, (8, 8)), (1, (32, 8))])
+@pytest.mark.parametrize("seed,tile", [(0, (16, 16)), (2, (16, 16)), (0, (8, 8)), (1, (32, 8)), (3, (16, 8)),
+                                       (4, (8, 32))])
 def test_render_backward_parity(oracle, seed, tile):
     sc = scenes.single_view_scene(seed=seed, n=2000)
     cam = sc["cams"][0]
