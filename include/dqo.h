@@ -277,6 +277,26 @@ int dqo_object_loss(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_ca
                     const dqo_images* img, const dqo_targets* tgt, const dqo_loss_weights* w,
                     double* loss /* device [4] */, const dqo_image_grads* g, void* state, void* stream);
 
+/* dqo_object_loss for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same loss, gradients and reduction order (bitwise the
+ * same results), but no state buffer: the per-workgroup partial sums and
+ * the valid-depth count live in a scratch array of the library, one 32 KiB
+ * copy per device (held until the process ends), whose address is looked
+ * up once per device on the first call there.  The call allocates nothing.
+ * Every call on one device shares that scratch, and nothing in it needs to
+ * start at zero (each call overwrites what it reads): calls that overlap on
+ * one device (other streams, other host threads) race and must be ordered
+ * by the caller.  The scratch holds 511 rows of partial sums, the most the
+ * loss pass uses for any frame (one row per reduction workgroup); a size
+ * check rejects with DQO_EINVAL a call that would need more, which no valid
+ * frame does.  desc->n, pair_capacity and segments are not used (n may be
+ * 0); windows and jobs are honoured as by dqo_object_loss.  At most 64
+ * devices. */
+int dqo_object_loss_noalloc(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
+                            const dqo_images* img, const dqo_targets* tgt, const dqo_loss_weights* w,
+                            double* loss /* device [4] */, const dqo_image_grads* g, void* stream);
+
 /* Adjoint of dqo_render_forward with the blended set held fixed: the
  * back-propagation of the rendering losses through the alpha blending of
  * colour, depth and the instance channels of Eq. (12) (Sec. III-D; the

@@ -31,7 +31,8 @@ EXPORTED = ["dqo_config_default", "dqo_ctx_create", "dqo_ctx_destroy", "dqo_last
             "dqo_project_cull_bin", "dqo_sort", "dqo_render_forward", "dqo_object_loss", "dqo_render_backward",
             "dqo_project_backward", "dqo_project_backward_adam", "dqo_pose_backward", "dqo_adam_step", "dqo_adam_step_counted", "dqo_fit_dual_quadric",
             "dqo_id_boxes", "dqo_incremental_masks", "dqo_densify", "dqo_quadric_iou_grad",
-            "dqo_refine_quadrics", "dqo_associate", "dqo_quadric_distance", "dqo_associate_decide"]
+            "dqo_refine_quadrics", "dqo_associate", "dqo_quadric_distance", "dqo_associate_decide",
+            "dqo_object_loss_noalloc"]
 # include/dqo_learned.h
 EXPORTED_LEARNED = ["dqo_net_layout_get", "dqo_net_workspace_size", "dqo_net_pack", "dqo_net_forward", "dqo_net_loss",
                     "dqo_net_backward", "dqo_adam_flat", "dqo_init_gaussians", "dqo_init_labels", "dqo_net_fallback",
@@ -153,6 +154,7 @@ def lib():
     L.dqo_sort.argtypes = fr + [vp, vp]
     L.dqo_render_forward.argtypes = fr + [vp, P(Images), vp]
     L.dqo_object_loss.argtypes = fr + [P(Images), P(Targets), P(LossWeights), vp, P(ImageGrads), vp, vp]
+    L.dqo_object_loss_noalloc.argtypes = fr + [P(Images), P(Targets), P(LossWeights), vp, P(ImageGrads), vp]
     L.dqo_render_backward.argtypes = fr + [vp, P(Images), P(ImageGrads), vp]
     L.dqo_project_backward.argtypes = fr + [vp, vp, vp, vp]
     L.dqo_project_backward_adam.argtypes = fr + [vp, vp, vp, vp, P(AdamParams), vp, vp, vp]
@@ -405,6 +407,25 @@ class Frame:
         self.ctx.check(lib().dqo_densify(*self._fr(), ctypes.byref(t), _ptr(masks), ctypes.byref(c), int(n_old),
                                          int(params.shape[1]), _ptr(params), _ptr(ids), _ptr(counts),
                                          _stream(stream)))
+
+
+def object_loss_noalloc(ctx: Context, cams: Sequence[dict], K: int, img: Dict[str, torch.Tensor],
+                        tgt: Dict[str, torch.Tensor], grads: Optional[Dict[str, torch.Tensor]], loss: torch.Tensor,
+                        w_rgb=1.0, w_depth=1.0, lam=1.0, ce_eps=1e-6, stream=None):
+    """The object loss of Frame.object_loss without a state buffer: its
+    partial sums live in the library's per-device scratch, so the call
+    allocates nothing (calls that overlap on one GPU race)."""
+    dt = F64 if img["color"].dtype == torch.float64 else F32
+    desc = FrameDesc(n=0, n_views=len(cams), K=int(K), pair_capacity=0, dtype=dt)
+    s = Frame._images(img)
+    t = Targets(_ptr(tgt["color"]), _ptr(tgt["depth"]), _ptr(tgt.get("id")))
+    w = LossWeights(w_rgb, w_depth, lam, ce_eps)
+    g = None
+    if grads is not None:
+        g = ctypes.byref(ImageGrads(*(_ptr(grads.get(k)) for k in ("d_color", "d_depth", "d_t_final", "d_probs",
+                                                                  "d_p_target"))))
+    ctx.check(lib().dqo_object_loss_noalloc(ctx.h, ctypes.byref(desc), make_cameras(cams), ctypes.byref(s),
+                                            ctypes.byref(t), ctypes.byref(w), _ptr(loss), g, _stream(stream)))
 
 
 def adam_step(ctx: Context, params, grads, m, v, lrs, step, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "ctx.hpp"
 #include "dqo_device.hpp"
@@ -502,6 +503,54 @@ int dqo_object_loss(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camer
     StatePtrs s = state_ptrs(g, state);
     return enqueue_loss(ctx, d, cams, img, tgt, w, loss, gr, &s.ctrl->loss_partials[0][0], &s.ctrl->n_valid,
                         stream);
+}
+
+// The allocation-free object loss: its per-workgroup partial sums and the
+// valid-depth count live in `scratch`, one copy per device, whose address
+// is taken once per device (a __device__ symbol's host-side name is not a
+// device address: kernels get the address from hipGetSymbolAddress).
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+int scratch_address(const dqo_ctx* ctx, void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(ctx, e, "object_loss_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return fail(ctx, DQO_EINVAL, "object_loss_noalloc: device %d beyond the %d supported", dev,
+                    kNoAllocMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(ctx, e, "object_loss_noalloc: hipGetSymbolAddress(scratch)");
+        if (!p) return fail(ctx, DQO_EHIP, "object_loss_noalloc: no device address for scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DQO_OK;
+}
+}  // namespace
+
+int dqo_object_loss_noalloc(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams,
+                            const dqo_images* img, const dqo_targets* tgt, const dqo_loss_weights* w, double* loss,
+                            const dqo_image_grads* gr, void* stream) {
+    int rc = check_loss_args(ctx, d, cams, img, tgt, w, loss, gr);
+    if (rc) return rc;
+    const int64_t npix = (int64_t)cams[0].width * cams[0].height * d->n_views;
+    const int blocks = loss_partial_blocks(npix);
+    if ((int64_t)blocks * kLossParts + 1 > kNoAllocScratchDoubles)
+        return fail(ctx, DQO_EINVAL, "object_loss_noalloc: %d partial rows exceed the scratch of %d", blocks,
+                    (kNoAllocScratchDoubles - 1) / kLossParts);
+    void* sp = nullptr;
+    rc = scratch_address(ctx, &sp);
+    if (rc) return rc;
+    double* partials = (double*)sp;
+    uint32_t* n_valid = (uint32_t*)(partials + (kNoAllocScratchDoubles - 1));
+    return enqueue_loss(ctx, d, cams, img, tgt, w, loss, gr, partials, n_valid, stream);
 }
 
 int dqo_render_backward(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams, void* state,

@@ -56,6 +56,10 @@ constexpr int kMaxDepthPasses = 4;
 constexpr int kMaxPairPasses = 4;
 constexpr int kLossBlocks = 512;
 constexpr int kLossParts = 8;      // partial sums per loss workgroup (6 used)
+// Scratch of the allocation-free object loss: kLossBlocks - 1 rows of
+// kLossParts partial sums and the valid-depth count (32 KiB per device).
+constexpr int kNoAllocScratchDoubles = kLossParts * (kLossBlocks - 1) + 1;
+constexpr int kNoAllocMaxDevices = 64;
 
 // Counter slots in the control block (dynamic block index per look-back chain).
 constexpr int kCounterDepth = 0;   // + pass
