@@ -39,7 +39,7 @@ BYTES_PER_PAIR, BYTES_PER_PIXEL, BYTES_PER_WRITTEN = 44.0, 32.0, 40.0
 # HBM bytes per launch of the render backward from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (scaled by a 256 MiB copy: x2.000 and x1.000), valid only for the kernel source
 # they were taken with (render.hip and dqo_device.hpp); reported as null otherwise.
-MEASURED_TRAFFIC = {"render_src_sha256_16": "6e3c62f54eb06c26", "bytes_per_launch": 297334909}
+MEASURED_TRAFFIC = {"render_src_sha256_16": "7b876ed2bb881286", "bytes_per_launch": 306803528}
 
 
 def measured_traffic():
@@ -152,14 +152,16 @@ def small_scene_comparison(steps=200):
                    ctx=B.Context(tile_w=8, tile_h=8), status_every=0)
     for _ in range(10):
         tr.step()
+    g = tr.capture()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(steps):
-        tr.step()
+        g.replay()
     torch.cuda.synchronize()
     gpu_us = (time.perf_counter() - t1) * 1e6 / steps
     tr.check()
-    return dict(workload="2,000 Gaussians, 128x96, K=3, 8x8 tiles; forward + object loss + backward + Adam",
+    return dict(workload="2,000 Gaussians, 128x96, K=3, 8x8 tiles; forward + object loss + backward + Adam "
+                         "(the GPU step replayed as one HIP graph)",
                 gpu_us_per_iter=round(gpu_us, 2), oracle_s_per_iter=round(t_oracle, 4),
                 oracle_cores=oracle.num_threads())
 
@@ -545,6 +547,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--event-every", type=int, default=10,
                     help="time the render backward with HIP events on every N-th timed step (default 10)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="issue every timed step eagerly instead of replaying the captured step")
     ap.add_argument("--cpu-pixels", type=int, default=49152)
     ap.add_argument("--tile", default="8x8", help="pixel tile WxH (8x8, 16x8, 16x16, 32x8, 8x32)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -580,34 +584,41 @@ def main():
         tr.step()
     torch.cuda.synchronize()
     tr.check()
-    # timed region: K whole steps; HIP events around the render backward on the
-    # stream it is launched on (torch's current stream), on every
-    # --event-every-th step (each pair of event records adds a ~6 us gap on
-    # either side of the kernel, which is measurement, not workload)
+    # The step is captured once in a HIP graph (every kernel of it, on one
+    # stream): replaying it costs one launch instead of the ~20 kernel
+    # launches and 6 library calls that the host otherwise issues per step
+    # (about 0.4 ms of host time, as long as the step itself).  The capture
+    # runs no step.  Timed region: K whole steps; every --event-every-th one
+    # runs eagerly with HIP events around the render backward on the stream it
+    # is launched on (torch's current stream), the others replay the graph.
+    graph = tr.capture() if not args.no_graph else None
     stream = torch.cuda.current_stream()
-    sampled = list(range(0, args.steps, max(1, args.event_every)))
+    every = max(1, args.event_every)
+    sampled = list(range(0, args.steps, every))
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
-    orig = tr.r.frame.render_backward
-    calls = [0]
+    f = tr.r.frame
+    orig = f.render_backward
+    state = {"k": None}
 
     def timed_bwd(img, grads, s=None):
-        k = calls[0]
-        calls[0] += 1
-        if k not in ev:
-            return orig(img, grads, s)
-        a, b = ev[k]
+        a, b = ev[state["k"]]
         a.record(stream)
         orig(img, grads, s)
         b.record(stream)
 
-    tr.r.frame.render_backward = timed_bwd
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        tr.step()
+    for k in range(args.steps):
+        if k in ev or graph is None:
+            state["k"] = k
+            f.render_backward = timed_bwd if k in ev else orig
+            tr.step()
+            f.render_backward = orig
+        else:
+            graph.replay()
+            tr.step_count += 1
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    tr.r.frame.render_backward = orig
     npairs = tr.check()
     bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in ev.values()]))
     ms = dt * 1e3 / args.steps
@@ -650,9 +661,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "room of 200k Gaussians (20 object blobs + 30% background, K=21) at 640x480, "
                                "f=600; step = project/bin + sort + render fwd + object loss (L1 rgb + L1 depth + "
-                               "object CE) + render bwd + project bwd + Adam",
+                               "object CE) + render bwd + project bwd + Adam, replayed as one HIP graph",
                    "n_gaussians": args.n, "width": 640, "height": 480, "K": sc["K"], "pairs": npairs,
-                   "tile": args.tile, "loss": [round(x, 6) for x in loss]},
+                   "tile": args.tile, "graph": graph is not None, "loss": [round(x, 6) for x in loss]},
         "roofline": roof, "cpu_baseline": cpu, "learned_init": learned,
     }
     print(json.dumps(out), flush=True)
