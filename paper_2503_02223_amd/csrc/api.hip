@@ -122,7 +122,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     // sum over tiles of ceil(range / L) - 1 <= cap / L
     g.ckpt_cap = (tw * th == kWave && tiles_total <= kSegTilesMax) ? cap / kSegLen + 1 : 0;
     g.seg_cap = tiles_total + g.ckpt_cap;
-    g.off_seg = so; so = align256(so + g.seg_cap * 8);
+    g.off_seg = so; so = align256(so + g.seg_cap * 16);
     g.off_cbase = so; so = align256(so + tiles_total * 4);
     g.off_tlast = so; so = align256(so + tiles_total * 4);
     g.off_ckpt = so; so = align256(so + g.ckpt_cap * 6 * kWave * ts);
@@ -164,7 +164,7 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.pose_partials = (double*)(sc + g.off_pose);
     s.written = (uint8_t*)(sc + g.off_written);
     s.scan_base = (uint32_t*)(sc + g.off_sbase);
-    s.seg_list = (uint32_t*)(sc + g.off_seg);
+    s.seg_list = (uint4*)(sc + g.off_seg);
     s.ckpt_base = (uint32_t*)(sc + g.off_cbase);
     s.tile_last = (int32_t*)(sc + g.off_tlast);
     s.ckpt = sc + g.off_ckpt;

@@ -49,6 +49,7 @@ inline int depth_ipt(int64_t items) {
 // 16 wavefronts emits the pairs of its own 64 records.
 constexpr int kSegLen = 64;        // pairs per backward segment of a 64-pixel tile
 constexpr int kSegMax = 255;       // segments per tile (the last one takes the rest of the range)
+constexpr uint32_t kNoBoundary = 0xFFFFFFFFu;  // segment-list entry of a tile's last segment: no restart
 constexpr int kScanThreads = 1024;
 constexpr int kScanIpt = 1;  // 2 and 4 measured slower at 200k items (1646 -> 1627 / 1573 it/s)
 constexpr int kScanTile = kScanThreads * kScanIpt;
@@ -280,7 +281,7 @@ struct StatePtrs {
     // Segmented backward of 64-pixel tiles: a tile's pair range is walked in
     // segments of kSegLen pairs, one wavefront each, restarted from
     // per-pixel states the forward stores at the segment boundaries.
-    uint32_t* seg_list;   // [seg_cap] (tile, segment << 8 | 1) in launch order (built after the forward)
+    uint4* seg_list;      // [seg_cap] (tile, first position, walk end, boundary record) in launch order (after the forward)
     uint32_t* ckpt_base;  // [V*tiles] first boundary record of each tile
     int32_t* tile_last;   // [V*tiles] last blended position in each tile (forward)
     void* ckpt;           // [ckpt_cap][6][64] T, colour (3), depth, target probability before each boundary

@@ -107,7 +107,9 @@ __device__ __forceinline__ bool tile_may_contribute(const T (&sp)[kSplatWords], 
     const T bx0 = T(px0) + T(0.5), bx1 = T(px1) + T(0.5), by0 = T(py0) + T(0.5), by1 = T(py1) + T(0.5);
     const T mx = sp[0], my = sp[1], A = sp[2], B = sp[3], C = sp[4];
     auto qf = [&](T dx, T dy) { return fmadd(A * dx, dx, fmadd(T(2) * B * dx, dy, C * dy * dy)); };
-    const T iA = T(1) / A, iC = T(1) / C;
+    // approximate reciprocals: they only move the clamped stationary points,
+    // where Q is flat to first order, far inside the bounds' margins
+    const T iA = fast_rcp<T>(A), iC = fast_rcp<T>(C);
     T q = T(0);
     if (!(mx >= bx0 && mx <= bx1 && my >= by0 && my <= by1)) {
         const T ex0 = bx0 - mx, ex1 = bx1 - mx, ey0 = by0 - my, ey1 = by1 - my;
@@ -563,7 +565,9 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
 
 // Backward for 64-pixel tiles: the workgroup is one wavefront, so the
 // transposed wave sums are already the tile sums and no barrier is needed
-// between chunks.  Only Gaussians that contribute somewhere in the tile take a
+// between chunks.  The conic words are summed without their constant factors
+// (-1/2 on the two diagonal words, -1 on the mixed one), which the lane that
+// stores a word's sum applies once.  Only Gaussians that contribute somewhere in the tile take a
 // reduction slot: the walk finds the next contributing Gaussian, fills slot c
 // (c = 0..5, a separate statically indexed code section each, so the slot
 // values stay in fixed registers), and after six slots the wave transposes and
@@ -572,8 +576,9 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
 // ten values of its slot, so nothing is cleared between chunks: the values
 // past the NS filled slots are set to zero here, as constants.
 template <int NS, typename T>
-__device__ __forceinline__ void flush_slots(T (&v)[64], int lane, int lane_slot, const uint32_t (&chunk)[kChunk],
-                                            T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap) {
+__device__ __forceinline__ void flush_slots(T (&v)[64], int lane, int lane_slot, T lane_factor,
+                                            const uint32_t (&chunk)[kChunk], T* __restrict__ partials,
+                                            uint8_t* __restrict__ written, uint32_t cap) {
 #pragma unroll
     for (int k = NS * kGradWords; k < 64; ++k) v[k] = T(0);
     wave_transpose_sum<T>(v, lane);
@@ -582,7 +587,7 @@ __device__ __forceinline__ void flush_slots(T (&v)[64], int lane, int lane_slot,
 #pragma unroll
         for (int c = 1; c < NS; ++c) slot = (lane_slot == c) ? chunk[c] : slot;
         if (slot < cap) {
-            partials[(size_t)slot * kGradWords + (lane - lane_slot * kGradWords)] = v[0];
+            partials[(size_t)slot * kGradWords + (lane - lane_slot * kGradWords)] = v[0] * lane_factor;
             if (lane == lane_slot * kGradWords) written[slot] = 1;
         }
     }
@@ -593,26 +598,34 @@ struct SlotIdx {
     static constexpr int value = C;
 };
 
-template <typename T, int TW, int TH>
+template <typename T, int TW, int TH, bool PROBS>
 __device__ __forceinline__ void backward_unit(
     const Views<T>& V, const Consts<T>& cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ schedule, const T* __restrict__ tfinal, const int32_t* __restrict__ last,
     const int32_t* __restrict__ target, const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT,
     const T* __restrict__ dP, const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written,
-    uint32_t cap, uint32_t M, const uint32_t* __restrict__ seg_list, const uint32_t* __restrict__ ckpt_base,
-    const T* __restrict__ ckpt, uint32_t ckpt_cap, const T* __restrict__ color, const T* __restrict__ depth,
-    const T* __restrict__ ptarget, T* s_sp, uint32_t* s_slot, uint32_t unit) {
+    uint32_t cap, uint32_t M, const uint4* __restrict__ seg_list, const T* __restrict__ ckpt, uint32_t ckpt_cap,
+    const T* __restrict__ color, const T* __restrict__ depth, const T* __restrict__ ptarget, T* s_sp,
+    uint32_t* s_slot, uint32_t unit) {
     const int lane = threadIdx.x;
+    const uint32_t n_tiles = (uint32_t)(V.n_views * V.tiles_per_view);
+    // A listed segment comes with its walk [s0, hi) and the boundary record
+    // at its end (pixels blending past s1 restart from it); a whole tile
+    // walks its range up to its pixels' last blended position.
     int tile;
-    uint32_t seg = 0u, seg_n = 1u;  // first segment of the unit, segments in it
+    uint32_t s0, s1, hi_seg = 0u, bnd = kNoBoundary;
     if (seg_list) {
-        const uint2 e = reinterpret_cast<const uint2*>(seg_list)[unit];
-        tile = (int)min(e.x, (uint32_t)(V.n_views * V.tiles_per_view - 1));
-        seg = e.y >> 8;
-        seg_n = max(e.y & 255u, 1u);
+        const uint4 en = seg_list[unit];
+        tile = (int)min(en.x, n_tiles - 1u);
+        s0 = min(en.y, cap);
+        hi_seg = min(max(en.z, s0), cap);
+        bnd = en.w;
+        s1 = (bnd == kNoBoundary) ? 0xFFFFFFFFu : s0 + (uint32_t)kSegLen;
     } else {
-        tile = (int)min(schedule[unit], (uint32_t)(V.n_views * V.tiles_per_view - 1));
+        tile = (int)min(schedule[unit], n_tiles - 1u);
+        s0 = min(ranges[2 * tile], cap);
+        s1 = min(ranges[2 * tile + 1], cap);
     }
     const int view = tile / V.tiles_per_view;
     const int t = tile - view * V.tiles_per_view;
@@ -623,13 +636,6 @@ __device__ __forceinline__ void backward_unit(
     const int64_t pix = (int64_t)py * V.W + px;
     const int64_t o = view * HW + pix;
     const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
-    const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
-    uint32_t s0 = rs, s1 = re;
-    if (seg_list) {
-        const uint32_t nseg = tile_segments(re - rs);
-        s0 = min(rs + seg * (uint32_t)kSegLen, re);
-        s1 = (seg + seg_n >= nseg) ? re : min(rs + (seg + seg_n) * (uint32_t)kSegLen, re);
-    }
 
     int lastp = -1;
     T Tcur = T(1), gc0 = T(0), gc1 = T(0), gc2 = T(0), gd = T(0), gt = T(0), gpt = T(0);
@@ -638,7 +644,8 @@ __device__ __forceinline__ void backward_unit(
     T S_restart = T(0);
     if (inside) {
         lastp = last[o];
-        if (lastp < (int)s0 || lastp >= (int)re) lastp = -1;  // nothing in this segment (or not this frame's)
+        // nothing in this segment (whole tiles: nothing of this frame's)
+        if (lastp < (int)s0 || (!seg_list && lastp >= (int)s1)) lastp = -1;
         Tcur = tfinal[o];
         gc0 = dC[(view * 3 + 0) * HW + pix];
         gc1 = dC[(view * 3 + 1) * HW + pix];
@@ -650,52 +657,67 @@ __device__ __forceinline__ void backward_unit(
             gpt = dPt[o];
             if (tgt == -1) gt += gpt;
         }
-        if (lastp >= (int)s1) {
-            // The pixel blends past this segment: restart at its end from the
-            // state the forward stored there.  The sum behind the boundary is
-            // the total minus the part in front of it (colour without the
-            // background term, depth, target probability).
-            const uint32_t e = min(ckpt_base[tile] + seg + seg_n - 1u, ckpt_cap - 1u);
-            const T* c = ckpt + (size_t)e * 6 * kWave + lane;
-            const T Tf = Tcur;
-            const T behind = gc0 * ((color[(view * 3 + 0) * HW + pix] - Tf * cs.bg[0]) - c[1 * kWave]) +
-                             gc1 * ((color[(view * 3 + 1) * HW + pix] - Tf * cs.bg[1]) - c[2 * kWave]) +
-                             gc2 * ((color[(view * 3 + 2) * HW + pix] - Tf * cs.bg[2]) - c[3 * kWave]) +
-                             gd * (depth[o] - c[4 * kWave]) +
-                             (tgt >= 0 ? gpt * (ptarget[o] - c[5 * kWave]) : T(0));
-            S_restart = behind + Tf * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
-            Tcur = c[0];
-            lastp = (int)s1 - 1;
-            restart = true;
+        if (bnd != kNoBoundary) {
+            // Some pixels blend past this segment: they restart at its end
+            // from the state the forward stored there.  The sum behind the
+            // boundary is the total minus the part in front of it (colour
+            // without the background term, depth, target probability).  The
+            // loads are issued for every pixel, beside the ones above.
+            const T* c = ckpt + (size_t)min(bnd, ckpt_cap - 1u) * 6 * kWave + lane;
+            T ck[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) ck[q] = c[q * kWave];
+            const T col0 = color[(view * 3 + 0) * HW + pix], col1 = color[(view * 3 + 1) * HW + pix],
+                    col2 = color[(view * 3 + 2) * HW + pix], dep = depth[o], ptg = ptarget ? ptarget[o] : T(0);
+            if (lastp >= (int)s1) {
+                const T Tf = Tcur;
+                const T behind = gc0 * ((col0 - Tf * cs.bg[0]) - ck[1]) + gc1 * ((col1 - Tf * cs.bg[1]) - ck[2]) +
+                                 gc2 * ((col2 - Tf * cs.bg[2]) - ck[3]) + gd * (dep - ck[4]) +
+                                 (tgt >= 0 ? gpt * (ptg - ck[5]) : T(0));
+                S_restart = behind + Tf * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
+                Tcur = ck[0];
+                lastp = (int)s1 - 1;
+                restart = true;
+            }
         }
     }
-    int maxlast = lastp;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d));
-    // Equal in every lane; said so, the walk state derived from it lives in
-    // scalar registers and the loop control is scalar branches (measured
-    // 10% faster than the same walk with its state in vector registers).
-    maxlast = __builtin_amdgcn_readfirstlane(maxlast);
     // Pairs behind every pixel's last blended Gaussian, and pairs that
     // contribute nowhere in the tile, are not written and stay unmarked
     // (their partials count as zero).
-    const uint32_t hi = (maxlast >= (int)s0) ? (uint32_t)(maxlast + 1) : s0;
+    uint32_t hi = hi_seg;
+    if (!seg_list) {
+        int maxlast = lastp;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d));
+        // Equal in every lane; said so, the walk state derived from it lives
+        // in scalar registers and the loop control is scalar branches
+        // (measured 10% faster than the same walk with its state in vector
+        // registers).
+        maxlast = __builtin_amdgcn_readfirstlane(maxlast);
+        hi = (maxlast >= (int)s0) ? (uint32_t)(maxlast + 1) : s0;
+    }
     T S = restart ? S_restart : Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
     T v[64];
 #pragma unroll
     for (int k = 0; k < 64; ++k) v[k] = T(0);
     uint32_t chunk[kChunk] = {};              // pair slot of the Gaussian in each reduction slot
     const int lane_slot = lane / kGradWords;  // the reduction slot whose sum this lane stores
+    const int lane_word = lane - lane_slot * kGradWords;
+    const T lane_factor = (lane_word == 2 || lane_word == 4) ? T(-0.5) : (lane_word == 3) ? T(-1) : T(1);
+    // the target-probability gradient joins a Gaussian's colour sum where its
+    // object is the pixel's target (tgt -1: T_final's gradient carries it)
+    const T gpt_obj = tgt >= 0 ? gpt : T(0);
     int bx0, bx1, by0, by1;
     tile_pixel_box<T>(V, view, tx, ty, TW, TH, bx0, bx1, by0, by1);
 
     // walk state (wave-uniform): the LDS batch holds positions [bstart, bend)
     uint32_t bend = hi, bstart = hi;
     int jl = -1;
-    // contribution state of the Gaussian found by `next`
+    // contribution state of the Gaussian found by `next`, zero in the lanes
+    // it does not blend: alpha, alpha where it is not clamped (the factor of
+    // alpha's derivatives), the falloff where not clamped
     const T* sp = s_sp;
-    T dx = T(0), dy = T(0), G = T(0), a0 = T(0);
-    bool clamped = false, contrib = false;
+    T dx = T(0), dy = T(0), a = T(0), a_free = T(0), G_free = T(0);
 
     // Software prefetch: batch A = [a_s, a_e) is held in registers (record and
     // slot) while the current batch is walked; the pair indices of the batch
@@ -769,46 +791,49 @@ __device__ __forceinline__ void backward_unit(
             lds_rec(jl);
             sp = cur;
             const T Q = quad_form(sp, sx, sy, dx, dy);
-            const bool in_q = Q <= cs.q_max, in_l = word_to_id<T>(sp[kSplatWords - 1]) <= lastp;
-            const uint64_t m_in = __builtin_amdgcn_ballot_w64(in_q) & __builtin_amdgcn_ballot_w64(in_l);
-            if (m_in == 0ull) {
-                --jl;
-                continue;
-            }
-            G = falloff<T>(Q);
+            const T G = falloff<T>(Q);
             const T araw = sp[5] * G;
-            clamped = !(araw < cs.alpha_max);
-            a0 = clamped ? cs.alpha_max : araw;  // min(araw, alpha_max), one select
-            const bool in_a = a0 >= cs.alpha_min;
-            if ((m_in & __builtin_amdgcn_ballot_w64(in_a)) == 0ull) {
+            const bool clamped = !(araw < cs.alpha_max);
+            const T a0 = clamped ? cs.alpha_max : araw;  // min(araw, alpha_max), one select
+            const bool contrib =
+                (Q <= cs.q_max) & (word_to_id<T>(sp[kSplatWords - 1]) <= lastp) & (a0 >= cs.alpha_min);
+            a = contrib ? a0 : T(0);
+            if (__builtin_amdgcn_ballot_w64(a != T(0)) == 0ull) {
                 --jl;
                 continue;
             }
-            contrib = in_q && in_l && in_a;
+            a_free = clamped ? T(0) : a;
+            G_free = (a_free != T(0)) ? G : T(0);
             return true;
         }
     };
     // Gradient of the found Gaussian into slot C; advances the walk.
+    // In the lanes the Gaussian does not blend, a = 0 leaves T and S as they
+    // are and zeroes every word (w = 0, a_free = G_free = 0).
     auto take = [&](auto cidx) {
         constexpr int C = decltype(cidx)::value;
-        const T a = contrib ? a0 : T(0);
         const T roma = fast_rcp<T>(T(1) - a);
         const T Ti = Tcur * roma;
         const T w = a * Ti;
         const int id = word_to_id<T>(sp[7]);
         T vv = fmadd(gc0, sp[8], fmadd(gc1, sp[9], fmadd(gc2, sp[10], gd * sp[6])));
-        vv += (tgt >= 0 && id == tgt) ? gpt : T(0);
-        if (dP && contrib && id >= 0 && id < K) vv += dP[((int64_t)view * K + id) * HW + pix];
-        const T dalpha = contrib ? (Ti * vv - S * roma) : T(0);
+        vv += (id == tgt) ? gpt_obj : T(0);
+        if constexpr (PROBS) {
+            if (a != T(0) && id >= 0 && id < K) vv += dP[((int64_t)view * K + id) * HW + pix];
+        }
+        const T dalpha = fmadd(Ti, vv, -(S * roma));
         S = fmadd(w, vv, S);
         Tcur = Ti;
-        const T dQ = clamped ? T(0) : dalpha * (T(-0.5) * a);
-        v[C * kGradWords + 0] = dQ * (T(-2) * (sp[2] * dx + sp[3] * dy));
-        v[C * kGradWords + 1] = dQ * (T(-2) * (sp[3] * dx + sp[4] * dy));
-        v[C * kGradWords + 2] = dQ * dx * dx;
-        v[C * kGradWords + 3] = dQ * T(2) * dx * dy;
-        v[C * kGradWords + 4] = dQ * dy * dy;
-        v[C * kGradWords + 5] = clamped ? T(0) : dalpha * G;
+        // dQ' = -2 dL/dQ: the mean words are dQ' (conic row . d), the conic
+        // words dQ' dx^2, dQ' dx dy, dQ' dy^2 before their factors
+        const T dq = dalpha * a_free;
+        const T t1 = dq * dx, t2 = dq * dy;
+        v[C * kGradWords + 0] = fmadd(sp[2], t1, sp[3] * t2);
+        v[C * kGradWords + 1] = fmadd(sp[3], t1, sp[4] * t2);
+        v[C * kGradWords + 2] = t1 * dx;
+        v[C * kGradWords + 3] = t1 * dy;
+        v[C * kGradWords + 4] = t2 * dy;
+        v[C * kGradWords + 5] = dalpha * G_free;
         v[C * kGradWords + 6] = gc0 * w;
         v[C * kGradWords + 7] = gc1 * w;
         v[C * kGradWords + 8] = gc2 * w;
@@ -823,38 +848,38 @@ __device__ __forceinline__ void backward_unit(
     for (;;) {
         if (!next()) break;
         take(SlotIdx<0>{});
-        if (!next()) { flush_slots<1>(v, lane, lane_slot, chunk, partials, written, cap); break; }
+        if (!next()) { flush_slots<1>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
         take(SlotIdx<1>{});
         if constexpr (NS > 2) {
-            if (!next()) { flush_slots<2>(v, lane, lane_slot, chunk, partials, written, cap); break; }
+            if (!next()) { flush_slots<2>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
             take(SlotIdx<2>{});
         }
         if constexpr (NS > 3) {
-            if (!next()) { flush_slots<3>(v, lane, lane_slot, chunk, partials, written, cap); break; }
+            if (!next()) { flush_slots<3>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
             take(SlotIdx<3>{});
         }
         if constexpr (NS > 4) {
-            if (!next()) { flush_slots<4>(v, lane, lane_slot, chunk, partials, written, cap); break; }
+            if (!next()) { flush_slots<4>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
             take(SlotIdx<4>{});
         }
         if constexpr (NS > 5) {
-            if (!next()) { flush_slots<5>(v, lane, lane_slot, chunk, partials, written, cap); break; }
+            if (!next()) { flush_slots<5>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
             take(SlotIdx<5>{});
         }
-        flush_slots<NS>(v, lane, lane_slot, chunk, partials, written, cap);
+        flush_slots<NS>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap);
     }
 }
 
-template <typename T, int TW, int TH>
+// PROBS: with gradients of the instance channels (an instantiation of its own)
+template <typename T, int TW, int TH, bool PROBS>
 __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
     const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
     const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
     const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap, uint32_t M,
-    const uint32_t* __restrict__ seg_list, const uint32_t* __restrict__ ckpt_base, const T* __restrict__ ckpt,
-    uint32_t ckpt_cap, const T* __restrict__ color, const T* __restrict__ depth, const T* __restrict__ ptarget,
-    const Ctrl* __restrict__ ctrl) {
+    const uint4* __restrict__ seg_list, const T* __restrict__ ckpt, uint32_t ckpt_cap, const T* __restrict__ color,
+    const T* __restrict__ depth, const T* __restrict__ ptarget, const Ctrl* __restrict__ ctrl) {
     static_assert(TW * TH == kWave, "one wavefront per tile");
     __shared__ __align__(16) T s_sp[kWave * kSplatWords];
     __shared__ uint32_t s_slot[kWave];
@@ -877,9 +902,9 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     const uint32_t n_units = seg_list ? ctrl->counters[kCounterSegTotal] : n_tiles;
     const uint32_t unit = blockIdx.x;
     if (unit >= n_units) return;
-    backward_unit<T, TW, TH>(V, cs, K, splats, rects, offsets, pvals, ranges, schedule, tfinal, last, target, dC, dD,
-                             dT, dP, dPt, partials, written, cap, M, seg_list, ckpt_base, ckpt, ckpt_cap, color, depth,
-                             ptarget, s_sp, s_slot, unit);
+    backward_unit<T, TW, TH, PROBS>(V, cs, K, splats, rects, offsets, pvals, ranges, schedule, tfinal, last, target,
+                                    dC, dD, dT, dP, dPt, partials, written, cap, M, seg_list, ckpt, ckpt_cap, color,
+                                    depth, ptarget, s_sp, s_slot, unit);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -927,14 +952,14 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
                          (img.p_target || !g.d_p_target);
         // units = segments up to each tile's end <= tiles + pairs / kSegLen = seg_cap
         const unsigned grid = seg ? (unsigned)std::max<int64_t>(s.seg_cap, blocks) : (unsigned)blocks;
-        hipLaunchKernelGGL((render_backward_wave_kernel<T, TW, TH>), dim3(grid),
-                           dim3(kWave), 0, st, f.views, f.consts, f.K, (const T*)s.splats, s.rects, s.offsets,
+        auto kern = g.d_probs ? render_backward_wave_kernel<T, TW, TH, true>
+                              : render_backward_wave_kernel<T, TW, TH, false>;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave), 0, st, f.views, f.consts, f.K, (const T*)s.splats, s.rects, s.offsets,
                            s.pair_vals[0], s.ranges, s.schedule, (const T*)img.t_final, img.last, img.target,
                            (const T*)g.d_color, (const T*)g.d_depth, (const T*)g.d_t_final, (const T*)g.d_probs,
                            (const T*)g.d_p_target, (T*)s.partials, s.written, (uint32_t)s.capacity,
-                           (uint32_t)s.items, seg ? s.seg_list : nullptr, s.ckpt_base, (const T*)s.ckpt,
-                           (uint32_t)s.ckpt_cap, (const T*)img.color, (const T*)img.depth, (const T*)img.p_target,
-                           s.ctrl);
+                           (uint32_t)s.items, seg ? s.seg_list : nullptr, (const T*)s.ckpt, (uint32_t)s.ckpt_cap,
+                           (const T*)img.color, (const T*)img.depth, (const T*)img.p_target, s.ctrl);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((render_backward_kernel<T, TW, TH>), dim3(blocks), dim3(TW * TH), 0, st, f.views, f.consts,

@@ -232,16 +232,22 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
 
 // The backward's work list, built after the forward: every 64-pair segment
 // of every tile up to the tile's last blended position, one wavefront each,
-// in launch order (heaviest tile first): entries (tile, segment << 8 | 1),
-// and the list's length.  One thread per tile of the launch order, 1024 per
+// in launch order (heaviest tile first), and the list's length.  An entry
+// holds what the wavefront's first loads need: the tile, the segment's first
+// position, the end of its walk (one past the tile's last blended position
+// when that lies in the segment, else the segment's end) and the record of
+// the boundary state at the segment's end (kNoBoundary where no pixel blends
+// past the segment: the one holding the tile's last blended position, and
+// the last of its range).  One thread per tile of the launch order, 1024 per
 // block; each block also sums the segments of all tiles before its own (at
 // most 7 per thread), so the blocks need nothing from one another.  At most
 // kSegTilesMax tiles.  Block 0 stamps the list with the binning epoch and
 // the forward's images, which the backward checks.
 __global__ __launch_bounds__(kSchedThreads) void segment_list_kernel(const uint32_t* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ schedule,
-                                                                    const int32_t* __restrict__ tile_last, int tiles,
-                                                                    uint32_t* __restrict__ seg_list, int64_t seg_cap,
+                                                                    const int32_t* __restrict__ tile_last,
+                                                                    const uint32_t* __restrict__ ckpt_base, int tiles,
+                                                                    uint4* __restrict__ seg_list, int64_t seg_cap,
                                                                     Ctrl* __restrict__ ctrl, uint64_t last_addr,
                                                                     uint64_t target_addr) {
     __shared__ uint32_t s_tmp[kSchedThreads / kWave];
@@ -264,6 +270,9 @@ __global__ __launch_bounds__(kSchedThreads) void segment_list_kernel(const uint3
     const int p = b * kSchedThreads + tid;
     const uint32_t t = p < tiles ? schedule[p] : 0u;
     const uint32_t k = p < tiles ? segs(p) : 0u;
+    const uint32_t rs = p < tiles ? ranges[2 * t] : 0u, re = p < tiles ? ranges[2 * t + 1] : 0u;
+    const uint32_t nseg = tile_segments(re - rs), last_end = (uint32_t)(p < tiles ? tile_last[t] : 0) + 1u;
+    const uint32_t cb = p < tiles ? ckpt_base[t] : 0u;
     const uint32_t base = block_exclusive_scan<kSchedThreads>(before, s_tmp) + before;  // inclusive: thread 1023 has all
     __shared__ uint32_t s_base;
     if (tid == kSchedThreads - 1) s_base = base;
@@ -271,8 +280,11 @@ __global__ __launch_bounds__(kSchedThreads) void segment_list_kernel(const uint3
     uint32_t pos = s_base + block_exclusive_scan<kSchedThreads>(k, s_tmp);
     for (uint32_t j = 0; j < k; ++j, ++pos)
         if ((int64_t)pos < seg_cap) {
-            seg_list[2 * (size_t)pos] = t;
-            seg_list[2 * (size_t)pos + 1] = (j << 8) | 1u;
+            const uint32_t s0 = rs + j * (uint32_t)kSegLen;
+            const bool tail = j + 1u >= nseg;  // the tile's last segment takes the rest of the range
+            const uint32_t s1 = tail ? re : s0 + (uint32_t)kSegLen;
+            const bool past = !tail && last_end > s1;
+            seg_list[pos] = make_uint4(t, s0, min(last_end, s1), past ? cb + j : kNoBoundary);
         }
     if (b == (int)gridDim.x - 1 && tid == kSchedThreads - 1)
         ctrl->counters[kCounterSegTotal] = (uint32_t)min((int64_t)pos, seg_cap);
@@ -289,7 +301,7 @@ hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, const void* 
     if (tiles_total > kSegTilesMax) return hipErrorInvalidValue;
     const int blocks = (tiles_total + kSchedThreads - 1) / kSchedThreads;
     hipLaunchKernelGGL(segment_list_kernel, dim3(blocks), dim3(kSchedThreads), 0, st, s.ranges, s.schedule,
-                       s.tile_last, tiles_total, s.seg_list, s.seg_cap, s.ctrl, (uint64_t)(uintptr_t)last,
+                       s.tile_last, s.ckpt_base, tiles_total, s.seg_list, s.seg_cap, s.ctrl, (uint64_t)(uintptr_t)last,
                        (uint64_t)(uintptr_t)target);
     return hipGetLastError();
 }
