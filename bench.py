@@ -39,7 +39,7 @@ BYTES_PER_PAIR, BYTES_PER_PIXEL, BYTES_PER_WRITTEN = 44.0, 32.0, 40.0
 # HBM bytes per launch of the render backward from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (scaled by a 256 MiB copy: x2.000 and x1.000), valid only for the kernel source
 # they were taken with (render.hip and dqo_device.hpp); reported as null otherwise.
-MEASURED_TRAFFIC = {"render_src_sha256_16": "7b876ed2bb881286", "bytes_per_launch": 306803528}
+MEASURED_TRAFFIC = {"render_src_sha256_16": "5fdb3e300aa41558", "bytes_per_launch": 203103712}
 
 
 def measured_traffic():
@@ -545,7 +545,7 @@ def main():
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--jobs", type=int, default=8, help="per-object jobs beside the 8 keyframes (at most 8)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--event-every", type=int, default=10,
+    ap.add_argument("--event-every", type=int, default=25,
                     help="time the render backward with HIP events on every N-th timed step (default 10)")
     ap.add_argument("--no-graph", action="store_true",
                     help="issue every timed step eagerly instead of replaying the captured step")
@@ -632,7 +632,9 @@ def main():
     t_hbm = alg_bytes / (MI355X_HBM_GBS * 1e9)
     t_flop = flops / (MI355X_FP32_VECTOR_TFLOPS * 1e12)
     t_exp = E / MI355X_EXP_PER_S
-    kernel = (f"render_backward_wave_kernel<float,{tw},{th}>" if tw * th == 64
+    # 64-pixel tiles: the segmented instantiation (no instance channels) up to 8192 tiles
+    seg = -(-640 // tw) * -(-480 // th) <= 8192
+    kernel = (f"render_backward_wave_kernel<float,{tw},{th},false,{'true' if seg else 'false'}>" if tw * th == 64
               else f"render_backward_kernel<float,{tw},{th}>")
     if t_hbm >= max(t_flop, t_exp):
         roof = dict(bound="hbm", achieved=round(alg_bytes / t / 1e9, 1), peak=MI355X_HBM_GBS, unit="GB/s")

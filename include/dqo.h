@@ -130,7 +130,9 @@ typedef struct dqo_frame_desc {
 
 /* Sub-buffers of the caller-allocated state buffer (dqo_state_layout). */
 enum dqo_buf {
-    DQO_BUF_SPLATS = 0,  /* [V*n] records of 12 values: mx,my,A,B,C,opacity,z,id,r,g,b,0 */
+    DQO_BUF_SPLATS = 0,  /* [V*n] records of 16 values: mx,my,A,B,C,opacity,z,id,r,g,b,0, first pair slot,
+                            tile rectangle x0 | y0 << 16, rectangle width, 0 (integers as FP32 bit patterns,
+                            FP64 values) */
     DQO_BUF_RECTS,       /* [V*n] int16x4 tile rectangle x0,y0,x1,y1 (inclusive), empty = x1<x0 */
     DQO_BUF_COUNTS,      /* [V*n] uint32 tiles covered */
     DQO_BUF_OFFSETS,     /* [V*n] uint32 first slot of the item's pairs in emission order */

@@ -20,6 +20,7 @@ LIBPATH = os.path.join(HERE, "libdqo.so")
 MAX_VIEWS = 16
 MAX_K = 64
 NUM_PARAMS = 14
+SPLAT_WORDS = 16  # values per splat record in the state buffer (dqo_buf DQO_BUF_SPLATS)
 OK, EINVAL, ECAPACITY, ENONFINITE, EDEGENERATE, EHIP, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 F32, F64 = 0, 1
 STATUS_OVERFLOW, STATUS_NONFINITE, STATUS_TIMEOUT = 1, 2, 4

@@ -126,9 +126,10 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.off_cbase = so; so = align256(so + tiles_total * 4);
     g.off_tlast = so; so = align256(so + tiles_total * 4);
     g.off_ckpt = so; so = align256(so + g.ckpt_cap * 6 * kWave * ts);
-    g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * g.depth_blocks * kRadixBins * 8);
-    g.off_lbs = so; so = align256(so + (int64_t)g.scan_blocks * 8);
-    g.off_lbp = so; so = align256(so + (int64_t)kMaxPairPasses * g.pair_blocks * kRadixBins * 8);
+    // look-back words: every block's, then every group's (grouped look-back)
+    g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * lb_blocks(g.depth_blocks) * kRadixBins * 8);
+    g.off_lbs = so; so = align256(so + (int64_t)lb_blocks(g.scan_blocks) * 8);
+    g.off_lbp = so; so = align256(so + (int64_t)kMaxPairPasses * lb_blocks(g.pair_blocks) * kRadixBins * 8);
     g.lb_words = (so - g.off_lbd) / 8;
     sz[DQO_BUF_SCRATCH] = so;
     int64_t off = 0;

@@ -11,7 +11,13 @@ namespace dqo {
 
 constexpr int kWave = 64;
 constexpr int kParams = DQO_NUM_PARAMS;
-constexpr int kSplatWords = 12;   // mx,my,A,B,C,o,z,id,r,g,b,pad
+// Splat record (one 64-byte line in FP32): mx,my,A,B,C,o,z,id,r,g,b,pad, then
+// the item's first pair slot, its tile rectangle's x0 | y0 << 16 and width,
+// pad.  The render kernels walk the first kRecWords (the pad word carries the
+// pair's position there).
+constexpr int kSplatWords = 16;
+constexpr int kRecWords = 12;
+constexpr int kSpSlot = 12, kSpRect = 13, kSpRectW = 14;
 constexpr int kGradWords = 10;    // dmx,dmy,dA,dB,dC,do,dr,dg,db,dz
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
@@ -217,6 +223,59 @@ __device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* words, int stri
     }
     lb_store(words + (size_t)slot * stride, lb_pack(kFlagInclusive, epoch, excl + agg));
     return excl;
+}
+
+// Sum of the values published at words[j * stride], j in [lo, hi), waiting
+// for each to carry this epoch; the loads of up to 16 entries are in flight
+// at once and only the entries not yet published are read again.
+__device__ __forceinline__ uint32_t lb_sum_published(const uint64_t* words, int stride, int lo, int hi,
+                                                     uint32_t epoch, uint32_t* status) {
+    uint32_t sum = 0, spins = 0;
+    for (int j0 = lo; j0 < hi; j0 += 16) {
+        uint32_t pending = (hi - j0 >= 16) ? 0xFFFFu : ((1u << (hi - j0)) - 1u);
+        while (pending) {
+            uint64_t w[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) w[k] = ((pending >> k) & 1u) ? lb_load(words + (size_t)(j0 + k) * stride) : 0ull;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (((pending >> k) & 1u) && lb_flag(w[k], epoch) != 0u) {
+                    sum += (uint32_t)w[k];
+                    pending &= ~(1u << k);
+                }
+            }
+            if (pending) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(status, (uint32_t)DQO_STATUS_TIMEOUT);
+                    return sum;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    }
+    return sum;
+}
+
+// Exclusive prefix of `slot` over 0..slot-1 when every block of the grid
+// starts at once.  The chained walk above then reads every predecessor's
+// aggregate, a window per round trip (slot / 16 round trips in all, as the
+// inclusive values spread).  Here blocks form groups of kLbGroup: each block
+// publishes its aggregate, the last block of a group sums the group and
+// publishes the group's total at gwords, and a block adds the totals of the
+// groups before its own to the aggregates of the blocks before it in its
+// group: three round trips, and far fewer loads.  Blocks wait only on blocks
+// of lower index.
+constexpr int kLbGroup = 16;
+__host__ __device__ constexpr int lb_groups(int blocks) { return (blocks + kLbGroup - 1) / kLbGroup; }
+__host__ __device__ constexpr int lb_blocks(int blocks) { return blocks + lb_groups(blocks); }  // words per digit
+__device__ __forceinline__ uint32_t lookback_grouped(uint64_t* words, uint64_t* gwords, int stride, int slot,
+                                                     uint32_t agg, uint32_t epoch, uint32_t* status) {
+    lb_store(words + (size_t)slot * stride, lb_pack(kFlagAggregate, epoch, agg));
+    const int g = slot / kLbGroup, first = g * kLbGroup;
+    const uint32_t in_group = lb_sum_published(words, stride, first, slot, epoch, status);
+    if (slot == first + kLbGroup - 1)
+        lb_store(gwords + (size_t)g * stride, lb_pack(kFlagAggregate, epoch, in_group + agg));
+    return in_group + lb_sum_published(gwords, stride, 0, g, epoch, status);
 }
 
 template <typename T>

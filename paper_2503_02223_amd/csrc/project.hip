@@ -47,6 +47,7 @@ __device__ __forceinline__ void store_splat<float>(float* dst, const float (&w)[
     d[0] = make_float4(w[0], w[1], w[2], w[3]);
     d[1] = make_float4(w[4], w[5], w[6], w[7]);
     d[2] = make_float4(w[8], w[9], w[10], w[11]);
+    d[3] = make_float4(w[12], w[13], w[14], w[15]);
 }
 
 template <typename T>
@@ -168,6 +169,10 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
                 w[0] = pr.mx; w[1] = pr.my; w[2] = pr.A; w[3] = pr.B; w[4] = pr.C; w[5] = pr.o; w[6] = pr.z;
                 w[7] = id_to_word<T>(ids[g]);
                 w[8] = p[11]; w[9] = p[12]; w[10] = p[13];
+                // the tile rectangle for the render backward's pair slots
+                // (the first slot, kSpSlot, is written by the scan)
+                w[kSpRect] = id_to_word<T>((int)((uint32_t)(uint16_t)rc.x | ((uint32_t)(uint16_t)rc.y << 16)));
+                w[kSpRectW] = id_to_word<T>(rc.z - rc.x + 1);
             }
             store_splat<T>(splats + i * kSplatWords, w);
             rects[i] = rc;
@@ -236,9 +241,10 @@ __global__ __launch_bounds__(kScanThreads) void scan_block_base_kernel(uint32_t*
     }
 }
 
+template <typename T>
 __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts, const short4* __restrict__ rects,
-    uint32_t* __restrict__ offsets, uint32_t* __restrict__ pkeys, uint32_t* __restrict__ pvals, uint32_t M,
+    uint32_t* __restrict__ offsets, T* __restrict__ splats, uint32_t* __restrict__ pkeys, uint32_t* __restrict__ pvals, uint32_t M,
     uint32_t cap, int64_t n, int tiles_x, int tiles_per_view, int pair_passes, int copies, uint64_t* lb, Ctrl* ctrl,
     const uint32_t* __restrict__ block_base) {
     __shared__ uint32_t s_incl[kScanTile];
@@ -249,7 +255,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     __shared__ uint8_t s_start[kScanThreads / kWave][kWave];
     __shared__ uint32_t s_hist[kMaxPairPasses][kRadixBins];
     __shared__ uint32_t s_tmp[kScanThreads / kWave];
-    __shared__ uint32_t s_base, s_bid, s_agg;
+    __shared__ uint32_t s_base, s_bid, s_agg, s_ticket;
     const int tid = threadIdx.x;
     if (tid == 0) {
         // Single-level scans chain every block to its predecessor by
@@ -258,6 +264,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
         // a ticket instead.  The two-level scan waits on nothing.
         const bool ticket = !block_base && (ctrl->status & (uint32_t)DQO_STATUS_TIMEOUT) != 0u;
         s_bid = ticket ? atomicAdd(&ctrl->counters[kCounterScan], 1u) : blockIdx.x;
+        s_ticket = ticket ? 1u : 0u;
     }
     if (tid < kRadixBins) {
         for (int p = 0; p < kMaxPairPasses; ++p) s_hist[p][tid] = 0u;
@@ -304,7 +311,10 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
         if (block_base) {
             s_base = block_base[bid];
         } else {
-            const uint32_t excl = lookback_exclusive(lb, 1, (int)bid, agg, epoch, &ctrl->status);
+            // all blocks start at once unless the ticket order is in force
+            const uint32_t excl = s_ticket ? lookback_exclusive(lb, 1, (int)bid, agg, epoch, &ctrl->status)
+                                           : lookback_grouped(lb, lb + gridDim.x, 1, (int)bid, agg, epoch,
+                                                              &ctrl->status);
             s_base = excl;
             if (base + kScanTile >= M) {
                 const uint32_t total = excl + agg;
@@ -318,7 +328,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
 #pragma unroll
     for (int k = 0; k < kScanIpt; ++k) {
         const uint32_t q = tid * kScanIpt + k;
-        if (base + q < M) offsets[s_rec[q]] = gbase + s_incl[q] - c[k];
+        if (base + q < M) {
+            const uint32_t first = gbase + s_incl[q] - c[k];
+            offsets[s_rec[q]] = first;
+            // also in the splat record, beside the rectangle (unused when the item has no pairs)
+            if (c[k]) splats[(size_t)s_rec[q] * kSplatWords + kSpSlot] = id_to_word<T>((int)first);
+        }
     }
     // Emission, one wavefront per group of 64 consecutive records: each round
     // writes 64 consecutive pair slots.  The record owning slot o is the last
@@ -393,21 +408,21 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
         hipError_t e = launch_radix_pass(s.depth_keys[src], s.depth_vals[src], s.depth_keys[src ^ 1],
                                          s.depth_vals[src ^ 1], nullptr, (uint32_t)M, p * kRadixBits,
                                          &s.ctrl->hist_depth[0][p][0], kMaxDepthPasses * kRadixBins, s.hist_copies_depth,
-                                         s.lb_depth + (size_t)p * s.depth_blocks * kRadixBins,
+                                         s.lb_depth + (size_t)p * lb_blocks(s.depth_blocks) * kRadixBins,
                                          &s.ctrl->counters[kCounterDepth + p], s.ctrl, st, kDepthNt, depth_ipt(M));
         if (e != hipSuccess) return e;
         src ^= 1;
     }
     const int pf = s.pair_first_buf;
-    const bool two_level = s.scan_blocks > resident_blocks<scan_emit_kernel, kScanThreads>();
+    const bool two_level = s.scan_blocks > resident_blocks<scan_emit_kernel<T>, kScanThreads>();
     if (two_level) {
         hipLaunchKernelGGL(scan_block_sums_kernel, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st,
                            s.depth_vals[0], s.counts, (uint32_t)M, s.scan_base);
         hipLaunchKernelGGL(scan_block_base_kernel, dim3(1), dim3(kScanThreads), 0, st, s.scan_base, s.scan_blocks,
                            (uint32_t)s.capacity, s.ctrl);
     }
-    hipLaunchKernelGGL(scan_emit_kernel, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st, s.depth_vals[0],
-                       s.counts, s.rects, s.offsets, s.pair_keys[pf], s.pair_vals[pf], (uint32_t)M,
+    hipLaunchKernelGGL(scan_emit_kernel<T>, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st, s.depth_vals[0],
+                       s.counts, s.rects, s.offsets, (T*)s.splats, s.pair_keys[pf], s.pair_vals[pf], (uint32_t)M,
                        (uint32_t)s.capacity, f.n, f.views.tiles_x, f.views.tiles_per_view, s.pair_passes,
                        s.hist_copies_pair, s.lb_scan, s.ctrl, two_level ? (const uint32_t*)s.scan_base : nullptr);
     return hipGetLastError();

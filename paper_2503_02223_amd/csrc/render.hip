@@ -45,29 +45,15 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 template <typename T>
 __device__ __forceinline__ T falloff(T Q) { return fast_exp<T>(T(-0.5) * Q); }
 
+// The first kRecWords values of a splat record (what the render kernels
+// walk with) into registers, and from registers into LDS.
 template <typename T>
-__device__ __forceinline__ void copy_splat(T* dst, const T* src) {
+__device__ __forceinline__ void load_splat(T (&r)[kRecWords], const T* src) {
 #pragma unroll
-    for (int k = 0; k < kSplatWords; ++k) dst[k] = src[k];
+    for (int k = 0; k < kRecWords; ++k) r[k] = src[k];
 }
 template <>
-__device__ __forceinline__ void copy_splat<float>(float* dst, const float* src) {
-    const float4* s4 = reinterpret_cast<const float4*>(src);
-    float4* d4 = reinterpret_cast<float4*>(dst);
-    const float4 a = s4[0], b = s4[1], c = s4[2];
-    d4[0] = a;
-    d4[1] = b;
-    d4[2] = c;
-}
-
-// Splat record into registers (prefetch) and from registers into LDS.
-template <typename T>
-__device__ __forceinline__ void load_splat(T (&r)[kSplatWords], const T* src) {
-#pragma unroll
-    for (int k = 0; k < kSplatWords; ++k) r[k] = src[k];
-}
-template <>
-__device__ __forceinline__ void load_splat<float>(float (&r)[kSplatWords], const float* src) {
+__device__ __forceinline__ void load_splat<float>(float (&r)[kRecWords], const float* src) {
     const float4* s4 = reinterpret_cast<const float4*>(src);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -78,13 +64,39 @@ __device__ __forceinline__ void load_splat<float>(float (&r)[kSplatWords], const
         r[4 * q + 3] = a.w;
     }
 }
+// The walked values of a splat record and the slot of its (tile tx, ty) pair:
+// the item's first slot plus the tile's place in its rectangle, row-major
+// (the record's last four values, the same 64-byte line in FP32).
 template <typename T>
-__device__ __forceinline__ void store_splat_lds(T* dst, const T (&r)[kSplatWords]) {
-#pragma unroll
-    for (int k = 0; k < kSplatWords; ++k) dst[k] = r[k];
+__device__ __forceinline__ uint32_t load_splat_slot(T (&r)[kRecWords], const T* src, int tx, int ty) {
+    load_splat<T>(r, src);
+    const uint32_t base = (uint32_t)word_to_id<T>(src[kSpSlot]);
+    const uint32_t xy = (uint32_t)word_to_id<T>(src[kSpRect]);
+    const uint32_t w = (uint32_t)word_to_id<T>(src[kSpRectW]);
+    return base + (uint32_t)(ty - (int)(xy >> 16)) * w + (uint32_t)(tx - (int)(xy & 0xFFFFu));
 }
 template <>
-__device__ __forceinline__ void store_splat_lds<float>(float* dst, const float (&r)[kSplatWords]) {
+__device__ __forceinline__ uint32_t load_splat_slot<float>(float (&r)[kRecWords], const float* src, int tx, int ty) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const float4 a = s4[q];
+        r[4 * q] = a.x;
+        r[4 * q + 1] = a.y;
+        r[4 * q + 2] = a.z;
+        r[4 * q + 3] = a.w;
+    }
+    const float4 t = s4[3];
+    const uint32_t base = __float_as_uint(t.x), xy = __float_as_uint(t.y), w = __float_as_uint(t.z);
+    return base + (uint32_t)(ty - (int)(xy >> 16)) * w + (uint32_t)(tx - (int)(xy & 0xFFFFu));
+}
+template <typename T>
+__device__ __forceinline__ void store_splat_lds(T* dst, const T (&r)[kRecWords]) {
+#pragma unroll
+    for (int k = 0; k < kRecWords; ++k) dst[k] = r[k];
+}
+template <>
+__device__ __forceinline__ void store_splat_lds<float>(float* dst, const float (&r)[kRecWords]) {
     float4* d4 = reinterpret_cast<float4*>(dst);
 #pragma unroll
     for (int q = 0; q < 3; ++q) d4[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
@@ -101,7 +113,7 @@ __device__ __forceinline__ void store_splat_lds<float>(float* dst, const float (
 // this rejects: skipping the rejected ones leaves every result bitwise the
 // same (a rejected splat would carry zero weight at every pixel).
 template <typename T>
-__device__ __forceinline__ bool tile_may_contribute(const T (&sp)[kSplatWords], int px0, int px1, int py0, int py1,
+__device__ __forceinline__ bool tile_may_contribute(const T (&sp)[kRecWords], int px0, int px1, int py0, int py1,
                                                     const Consts<T>& cs) {
     if (px0 > px1 || py0 > py1) return false;
     const T bx0 = T(px0) + T(0.5), bx1 = T(px1) + T(0.5), by0 = T(py0) + T(0.5), by1 = T(py1) + T(0.5);
@@ -155,7 +167,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     int32_t* __restrict__ tile_last) {
     constexpr int BLOCK = TW * TH;
     constexpr int NW = BLOCK / kWave;
-    __shared__ __align__(16) T s_sp[BLOCK * kSplatWords];
+    __shared__ __align__(16) T s_sp[BLOCK * kRecWords];
     __shared__ int s_wc[NW];
     extern __shared__ unsigned char s_dyn[];
     T* s_P = reinterpret_cast<T*>(s_dyn);  // [K][BLOCK] when PROBS
@@ -187,7 +199,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     // Software prefetch: this lane's record of the next batch is loaded into
     // registers while the current batch is walked; the pair index one batch
     // further ahead is loaded one step earlier still.
-    T pf[kSplatWords];
+    T pf[kRecWords];
     uint32_t rec2 = 0u;
     if (rs + tid < re) load_splat<T>(pf, splats + (size_t)min(pvals[rs + tid], M - 1) * kSplatWords);
     if (rs + BLOCK + tid < re) rec2 = min(pvals[rs + BLOCK + tid], M - 1);
@@ -226,8 +238,8 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
             }
         }
         if (cand) {
-            pf[kSplatWords - 1] = id_to_word<T>((int)(b0 + tid));
-            store_splat_lds<T>(s_sp + (off + rank_below(bal)) * kSplatWords, pf);
+            pf[kRecWords - 1] = id_to_word<T>((int)(b0 + tid));
+            store_splat_lds<T>(s_sp + (off + rank_below(bal)) * kRecWords, pf);
         }
         __syncthreads();
         if (b0 + BLOCK + tid < re) load_splat<T>(pf, splats + (size_t)rec2 * kSplatWords);
@@ -241,14 +253,14 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
         // one-by-one walk.
         constexpr int kFwdGroup = fwd_group<T>();
         for (int j0 = 0; j0 < nb; j0 += kFwdGroup) {
-            T rec[kFwdGroup][kSplatWords];
+            T rec[kFwdGroup][kRecWords];
             T a0[kFwdGroup];
             bool c0k[kFwdGroup];
             bool any = false;
 #pragma unroll
             for (int k = 0; k < kFwdGroup; ++k) {
                 const int j = min(j0 + k, nb - 1);
-                load_splat<T>(rec[k], s_sp + j * kSplatWords);
+                load_splat<T>(rec[k], s_sp + j * kRecWords);
             }
 #pragma unroll
             for (int k = 0; k < kFwdGroup; ++k) {
@@ -273,7 +285,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
                 const int id = word_to_id<T>(rec[k][7]);
                 pt += (id == tgt) ? w : T(0);
                 if (w != T(0)) {
-                    lastpos = word_to_id<T>(rec[k][kSplatWords - 1]);
+                    lastpos = word_to_id<T>(rec[k][kRecWords - 1]);
                     ++nb_count;
                     if (PROBS && id >= 0 && id < K) s_P[id * BLOCK + tid] += w;
                 }
@@ -386,22 +398,17 @@ __device__ __forceinline__ void wave_transpose_sum<float>(float (&v)[64], int la
     dpp_step<0xB1, 1, 2>(v, lane);    // quad_perm [1,0,3,2]: lane ^ 1
 }
 
-__device__ __forceinline__ uint32_t pair_slot(const short4* rects, const uint32_t* offsets, uint32_t rec, int tx,
-                                              int ty) {
-    const short4 rc = rects[rec];
-    return offsets[rec] + (uint32_t)(ty - rc.y) * (uint32_t)(rc.z - rc.x + 1) + (uint32_t)(tx - rc.x);
-}
 
 template <typename T, int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
-    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
-    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
+    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats,
+    const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
     const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
     const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
     const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap, uint32_t M) {
     constexpr int BLOCK = TW * TH;
     constexpr int NW = BLOCK / kWave;
-    __shared__ __align__(16) T s_sp[BLOCK * kSplatWords];
+    __shared__ __align__(16) T s_sp[BLOCK * kRecWords];
     __shared__ uint32_t s_slot[BLOCK];
     __shared__ T s_red[2][NW][kWave];
     __shared__ int s_maxlast;
@@ -458,14 +465,13 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
         __syncthreads();
         // the batch's records that may contribute in the tile, compacted in
         // order with their positions in the pad word
-        T r[kSplatWords];
+        T r[kRecWords];
         uint32_t slot = 0u;
         bool cand = false;
         if (tid < nbr) {
             const uint32_t rec = min(pvals[bstart + tid], M - 1);
-            load_splat<T>(r, splats + (size_t)rec * kSplatWords);
+            slot = load_splat_slot<T>(r, splats + (size_t)rec * kSplatWords, tx, ty);
             cand = tile_may_contribute<T>(r, bx0, bx1, by0, by1, cs);
-            slot = pair_slot(rects, offsets, rec, tx, ty);
         }
         const uint64_t bal = __ballot(cand);
         if (lane == 0) s_wc[wave] = __popcll(bal);
@@ -478,8 +484,8 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
         }
         if (cand) {
             const int q = off + rank_below(bal);
-            r[kSplatWords - 1] = id_to_word<T>((int)(bstart + tid));
-            store_splat_lds<T>(s_sp + q * kSplatWords, r);
+            r[kRecWords - 1] = id_to_word<T>((int)(bstart + tid));
+            store_splat_lds<T>(s_sp + q * kRecWords, r);
             s_slot[q] = slot;
         }
         __syncthreads();
@@ -492,10 +498,10 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
             for (int c = 0; c < kChunk; ++c) {
                 const int jl = c0 - c;
                 if (jl < 0) break;
-                const T* sp = s_sp + jl * kSplatWords;
+                const T* sp = s_sp + jl * kRecWords;
                 T dx, dy;
                 const T Q = quad_form(sp, sx, sy, dx, dy);
-                const bool in = (Q <= cs.q_max) && (word_to_id<T>(sp[kSplatWords - 1]) <= lastp);
+                const bool in = (Q <= cs.q_max) && (word_to_id<T>(sp[kRecWords - 1]) <= lastp);
                 if (!wave_any(in)) continue;
                 const T G = falloff<T>(Q);
                 const T araw = sp[5] * G;
@@ -576,9 +582,15 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
 // ten values of its slot, so nothing is cleared between chunks: the values
 // past the NS filled slots are set to zero here, as constants.
 template <int NS, typename T>
-__device__ __forceinline__ void flush_slots(T (&v)[64], int lane, int lane_slot, T lane_factor,
-                                            const uint32_t (&chunk)[kChunk], T* __restrict__ partials,
+__device__ __forceinline__ void flush_slots(T (&v)[64], const uint32_t (&chunk)[kChunk], T* __restrict__ partials,
                                             uint8_t* __restrict__ written, uint32_t cap) {
+    // The lane's place in the transposed sums, derived here at each flush (an
+    // opaque copy of the lane index keeps the compiler from hoisting it out
+    // of the walk, where these values would only occupy registers).
+    int lane = (int)__lane_id();
+    asm volatile("" : "+v"(lane));
+    const int lane_slot = (lane * 205) >> 11;  // lane / kGradWords for lane < 64
+    const int word = lane - lane_slot * kGradWords;
 #pragma unroll
     for (int k = NS * kGradWords; k < 64; ++k) v[k] = T(0);
     wave_transpose_sum<T>(v, lane);
@@ -587,8 +599,9 @@ __device__ __forceinline__ void flush_slots(T (&v)[64], int lane, int lane_slot,
 #pragma unroll
         for (int c = 1; c < NS; ++c) slot = (lane_slot == c) ? chunk[c] : slot;
         if (slot < cap) {
-            partials[(size_t)slot * kGradWords + (lane - lane_slot * kGradWords)] = v[0] * lane_factor;
-            if (lane == lane_slot * kGradWords) written[slot] = 1;
+            const T factor = (word == 2 || word == 4) ? T(-0.5) : (word == 3) ? T(-1) : T(1);
+            partials[(size_t)slot * kGradWords + word] = v[0] * factor;
+            if (word == 0) written[slot] = 1;
         }
     }
 }
@@ -598,10 +611,10 @@ struct SlotIdx {
     static constexpr int value = C;
 };
 
-template <typename T, int TW, int TH, bool PROBS>
+template <typename T, int TW, int TH, bool PROBS, bool PREFETCH>
 __device__ __forceinline__ void backward_unit(
-    const Views<T>& V, const Consts<T>& cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
-    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges,
+    const Views<T>& V, const Consts<T>& cs, int K, const T* __restrict__ splats,
+    const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ schedule, const T* __restrict__ tfinal, const int32_t* __restrict__ last,
     const int32_t* __restrict__ target, const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT,
     const T* __restrict__ dP, const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written,
@@ -701,9 +714,6 @@ __device__ __forceinline__ void backward_unit(
 #pragma unroll
     for (int k = 0; k < 64; ++k) v[k] = T(0);
     uint32_t chunk[kChunk] = {};              // pair slot of the Gaussian in each reduction slot
-    const int lane_slot = lane / kGradWords;  // the reduction slot whose sum this lane stores
-    const int lane_word = lane - lane_slot * kGradWords;
-    const T lane_factor = (lane_word == 2 || lane_word == 4) ? T(-0.5) : (lane_word == 3) ? T(-1) : T(1);
     // the target-probability gradient joins a Gaussian's colour sum where its
     // object is the pixel's target (tgt -1: T_final's gradient carries it)
     const T gpt_obj = tgt >= 0 ? gpt : T(0);
@@ -719,28 +729,32 @@ __device__ __forceinline__ void backward_unit(
     const T* sp = s_sp;
     T dx = T(0), dy = T(0), a = T(0), a_free = T(0), G_free = T(0);
 
-    // Software prefetch: batch A = [a_s, a_e) is held in registers (record and
-    // slot) while the current batch is walked; the pair indices of the batch
-    // after it (B) are loaded one step earlier still.
+    // Batches of up to 64 pairs, from the walk's end down.  The first batch's
+    // records (A = [a_s, a_e)) are loaded here, beside the pixel loads.  With
+    // PREFETCH (whole tiles: many batches) the next batch's records are held
+    // in registers while the current one is walked, and the pair indices of
+    // the batch after it (B) are loaded one step earlier still; without it
+    // (segments: mostly one batch) later batches are loaded when reached, and
+    // the record registers are free during the walk.
     auto batch_lo = [&](uint32_t e) { return (e - s0 > (uint32_t)kWave) ? e - kWave : s0; };
     uint32_t a_e = hi, a_s = batch_lo(hi);
-    T pf[kSplatWords];
+    T pf[kRecWords];
     uint32_t pf_slot = 0u;
     if (lane < (int)(a_e - a_s)) {
         const uint32_t rec = min(pvals[a_s + lane], M - 1);
-        load_splat<T>(pf, splats + (size_t)rec * kSplatWords);
-        pf_slot = pair_slot(rects, offsets, rec, tx, ty);
+        pf_slot = load_splat_slot<T>(pf, splats + (size_t)rec * kSplatWords, tx, ty);
     }
-    uint32_t b_e = a_s, b_s = batch_lo(a_s);
-    uint32_t rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
+    uint32_t b_e = a_s, b_s = batch_lo(a_s), rec_b = 0u;
+    if constexpr (PREFETCH) rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
+    bool first_batch = true;
 
     // The record of the Gaussian being tested, read from LDS in one go (three
     // 16-byte broadcast reads at a 24-bit multiply of its index).
-    T cur[kSplatWords];
+    T cur[kRecWords];
     auto lds_rec = [&](int j) {
         if constexpr (sizeof(T) == 4) {
             const float4* s4 = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_sp) +
-                                                               __mul24(j, (int)(kSplatWords * sizeof(T))));
+                                                               __mul24(j, (int)(kRecWords * sizeof(T))));
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const float4 a = s4[q];
@@ -751,7 +765,7 @@ __device__ __forceinline__ void backward_unit(
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < kSplatWords; ++k) cur[k] = s_sp[j * kSplatWords + k];
+            for (int k = 0; k < kRecWords; ++k) cur[k] = s_sp[j * kRecWords + k];
         }
     };
     // Advances to the next Gaussian (descending) that contributes at some pixel
@@ -765,6 +779,13 @@ __device__ __forceinline__ void backward_unit(
                 bend = a_e;
                 bstart = a_s;
                 const int nbr = (int)(bend - bstart);
+                if constexpr (!PREFETCH) {
+                    if (!first_batch && lane < nbr) {
+                        const uint32_t rec = min(pvals[bstart + lane], M - 1);
+                        pf_slot = load_splat_slot<T>(pf, splats + (size_t)rec * kSplatWords, tx, ty);
+                    }
+                    first_batch = false;
+                }
                 __syncthreads();
                 // the records that may contribute in the tile, compacted in
                 // order with their positions in the pad word
@@ -772,21 +793,22 @@ __device__ __forceinline__ void backward_unit(
                 const uint64_t bal = __builtin_amdgcn_ballot_w64(cand);
                 if (cand) {
                     const int q = rank_below(bal);
-                    pf[kSplatWords - 1] = id_to_word<T>((int)(bstart + lane));
-                    store_splat_lds<T>(s_sp + q * kSplatWords, pf);
+                    pf[kRecWords - 1] = id_to_word<T>((int)(bstart + lane));
+                    store_splat_lds<T>(s_sp + q * kRecWords, pf);
                     s_slot[q] = pf_slot;
                 }
                 __syncthreads();
                 jl = __popcll(bal) - 1;
                 a_e = b_e;
                 a_s = b_s;
-                if (lane < (int)(a_e - a_s)) {
-                    load_splat<T>(pf, splats + (size_t)rec_b * kSplatWords);
-                    pf_slot = pair_slot(rects, offsets, rec_b, tx, ty);
-                }
                 b_e = a_s;
                 b_s = batch_lo(a_s);
-                rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
+                if constexpr (PREFETCH) {
+                    if (lane < (int)(a_e - a_s)) {
+                        pf_slot = load_splat_slot<T>(pf, splats + (size_t)rec_b * kSplatWords, tx, ty);
+                    }
+                    rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
+                }
             }
             lds_rec(jl);
             sp = cur;
@@ -796,7 +818,7 @@ __device__ __forceinline__ void backward_unit(
             const bool clamped = !(araw < cs.alpha_max);
             const T a0 = clamped ? cs.alpha_max : araw;  // min(araw, alpha_max), one select
             const bool contrib =
-                (Q <= cs.q_max) & (word_to_id<T>(sp[kSplatWords - 1]) <= lastp) & (a0 >= cs.alpha_min);
+                (Q <= cs.q_max) & (word_to_id<T>(sp[kRecWords - 1]) <= lastp) & (a0 >= cs.alpha_min);
             a = contrib ? a0 : T(0);
             if (__builtin_amdgcn_ballot_w64(a != T(0)) == 0ull) {
                 --jl;
@@ -848,40 +870,41 @@ __device__ __forceinline__ void backward_unit(
     for (;;) {
         if (!next()) break;
         take(SlotIdx<0>{});
-        if (!next()) { flush_slots<1>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
+        if (!next()) { flush_slots<1>(v, chunk, partials, written, cap); break; }
         take(SlotIdx<1>{});
         if constexpr (NS > 2) {
-            if (!next()) { flush_slots<2>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
+            if (!next()) { flush_slots<2>(v, chunk, partials, written, cap); break; }
             take(SlotIdx<2>{});
         }
         if constexpr (NS > 3) {
-            if (!next()) { flush_slots<3>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
+            if (!next()) { flush_slots<3>(v, chunk, partials, written, cap); break; }
             take(SlotIdx<3>{});
         }
         if constexpr (NS > 4) {
-            if (!next()) { flush_slots<4>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
+            if (!next()) { flush_slots<4>(v, chunk, partials, written, cap); break; }
             take(SlotIdx<4>{});
         }
         if constexpr (NS > 5) {
-            if (!next()) { flush_slots<5>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap); break; }
+            if (!next()) { flush_slots<5>(v, chunk, partials, written, cap); break; }
             take(SlotIdx<5>{});
         }
-        flush_slots<NS>(v, lane, lane_slot, lane_factor, chunk, partials, written, cap);
+        flush_slots<NS>(v, chunk, partials, written, cap);
     }
 }
 
-// PROBS: with gradients of the instance channels (an instantiation of its own)
-template <typename T, int TW, int TH, bool PROBS>
+// PROBS: with gradients of the instance channels; SEG: a launch over the
+// segment list (instantiations of their own)
+template <typename T, int TW, int TH, bool PROBS, bool SEG>
 __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
-    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const short4* __restrict__ rects,
-    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
+    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats,
+    const uint32_t* __restrict__ pvals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule,
     const T* __restrict__ tfinal, const int32_t* __restrict__ last, const int32_t* __restrict__ target,
     const T* __restrict__ dC, const T* __restrict__ dD, const T* __restrict__ dT, const T* __restrict__ dP,
     const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap, uint32_t M,
     const uint4* __restrict__ seg_list, const T* __restrict__ ckpt, uint32_t ckpt_cap, const T* __restrict__ color,
     const T* __restrict__ depth, const T* __restrict__ ptarget, const Ctrl* __restrict__ ctrl) {
     static_assert(TW * TH == kWave, "one wavefront per tile");
-    __shared__ __align__(16) T s_sp[kWave * kSplatWords];
+    __shared__ __align__(16) T s_sp[kWave * kRecWords];
     __shared__ uint32_t s_slot[kWave];
 
     const int lane = threadIdx.x;
@@ -902,9 +925,10 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     const uint32_t n_units = seg_list ? ctrl->counters[kCounterSegTotal] : n_tiles;
     const uint32_t unit = blockIdx.x;
     if (unit >= n_units) return;
-    backward_unit<T, TW, TH, PROBS>(V, cs, K, splats, rects, offsets, pvals, ranges, schedule, tfinal, last, target,
-                                    dC, dD, dT, dP, dPt, partials, written, cap, M, seg_list, ckpt, ckpt_cap, color,
-                                    depth, ptarget, s_sp, s_slot, unit);
+    // (a segmented launch walks a stale frame's whole tiles without prefetch)
+    backward_unit<T, TW, TH, PROBS, !SEG>(V, cs, K, splats, pvals, ranges, schedule, tfinal, last, target, dC, dD, dT,
+                                          dP, dPt, partials, written, cap, M, seg_list, ckpt, ckpt_cap, color, depth,
+                                          ptarget, s_sp, s_slot, unit);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -952,9 +976,11 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
                          (img.p_target || !g.d_p_target);
         // units = segments up to each tile's end <= tiles + pairs / kSegLen = seg_cap
         const unsigned grid = seg ? (unsigned)std::max<int64_t>(s.seg_cap, blocks) : (unsigned)blocks;
-        auto kern = g.d_probs ? render_backward_wave_kernel<T, TW, TH, true>
-                              : render_backward_wave_kernel<T, TW, TH, false>;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave), 0, st, f.views, f.consts, f.K, (const T*)s.splats, s.rects, s.offsets,
+        auto kern = g.d_probs ? (seg ? render_backward_wave_kernel<T, TW, TH, true, true>
+                                     : render_backward_wave_kernel<T, TW, TH, true, false>)
+                              : (seg ? render_backward_wave_kernel<T, TW, TH, false, true>
+                                     : render_backward_wave_kernel<T, TW, TH, false, false>);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave), 0, st, f.views, f.consts, f.K, (const T*)s.splats,
                            s.pair_vals[0], s.ranges, s.schedule, (const T*)img.t_final, img.last, img.target,
                            (const T*)g.d_color, (const T*)g.d_depth, (const T*)g.d_t_final, (const T*)g.d_probs,
                            (const T*)g.d_p_target, (T*)s.partials, s.written, (uint32_t)s.capacity,
@@ -963,7 +989,7 @@ static hipError_t bwd_tile(const Frame<T>& f, const dqo_images& img, const dqo_i
         return hipGetLastError();
     }
     hipLaunchKernelGGL((render_backward_kernel<T, TW, TH>), dim3(blocks), dim3(TW * TH), 0, st, f.views, f.consts,
-                       f.K, (const T*)s.splats, s.rects, s.offsets, s.pair_vals[0], s.ranges, s.schedule,
+                       f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule,
                        (const T*)img.t_final, img.last, img.target, (const T*)g.d_color, (const T*)g.d_depth,
                        (const T*)g.d_t_final, (const T*)g.d_probs, (const T*)g.d_p_target, (T*)s.partials, s.written,
                        (uint32_t)s.capacity, (uint32_t)s.items);

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
     __shared__ uint32_t s_dstart[kRadixBins];
     __shared__ uint32_t s_gbase[kRadixBins];
     __shared__ uint32_t s_tmp[kWaves];
-    __shared__ uint32_t s_bid, s_epoch;
+    __shared__ uint32_t s_bid, s_epoch, s_grouped;
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -41,8 +41,12 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
         // Workgroup-index order needs the whole grid on the device at once;
         // once a bounded wait has given up (status bit, kept until the caller
         // clears it) the order comes from the ticket instead, every frame.
+        // A resident grid, whose blocks all start together, sums its
+        // predecessors in groups; ticket order (blocks staggered in time)
+        // walks the chain.
         const bool ticket = !resident || (ctrl->status & (uint32_t)DQO_STATUS_TIMEOUT) != 0u;
         s_bid = ticket ? atomicAdd(counter, 1u) : blockIdx.x;
+        s_grouped = ticket ? 0u : 1u;
         s_epoch = ctrl->epoch;
     }
     for (int i = tid; i < kWaves * kRadixBins; i += NT) (&s_wcnt[0][0])[i] = 0;
@@ -104,8 +108,12 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
     if (owner) {
         s_dstart[t] = dstart;
         // A digit that no key has anywhere needs no chain: every block skips it.
-        const uint32_t excl =
-            gcount ? lookback_exclusive(lb + t, kRadixBins, (int)bid, total, epoch, &ctrl->status) : 0u;
+        uint32_t excl = 0u;
+        if (gcount) {
+            excl = s_grouped ? lookback_grouped(lb + t, lb + (size_t)gridDim.x * kRadixBins + t, kRadixBins, (int)bid,
+                                                total, epoch, &ctrl->status)
+                             : lookback_exclusive(lb + t, kRadixBins, (int)bid, total, epoch, &ctrl->status);
+        }
         s_gbase[t] = gdig + excl;
     }
     __syncthreads();
@@ -363,7 +371,7 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
     for (int p = 0; p < s.pair_passes; ++p) {
         hipError_t e = launch_radix_pass(s.pair_keys[src], s.pair_vals[src], s.pair_keys[src ^ 1],
                                          s.pair_vals[src ^ 1], n_dev, cap, p * kRadixBits,
-                                         &s.ctrl->hist_pair[0][p][0], kMaxPairPasses * kRadixBins, s.hist_copies_pair, s.lb_pair + (size_t)p * s.pair_blocks * kRadixBins,
+                                         &s.ctrl->hist_pair[0][p][0], kMaxPairPasses * kRadixBins, s.hist_copies_pair, s.lb_pair + (size_t)p * lb_blocks(s.pair_blocks) * kRadixBins,
                                          &s.ctrl->counters[kCounterPair + p], s.ctrl, st, kPairNt, ipt);
         if (e != hipSuccess) return e;
         src ^= 1;

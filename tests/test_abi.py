@@ -75,7 +75,7 @@ def test_layout_and_validation_on_host():
     assert L.pair_key_bits == 6
     assert all(L.offset[i] % 256 == 0 for i in range(12))
     assert L.total >= L.offset[11] + L.bytes[11]
-    assert L.bytes[0] == 100 * 12 * 4 and L.bytes[9] == 5000 * 10 * 4
+    assert L.bytes[0] == 100 * B.SPLAT_WORDS * 4 and L.bytes[9] == 5000 * 10 * 4
     for bad in (dict(n_views=0), dict(n_views=17), dict(K=65), dict(dtype=7), dict(n=-1),
                 dict(pair_capacity=(1 << 30) + 1)):
         kw = dict(n=100, n_views=1, K=3, pair_capacity=5000, dtype=B.F32)

@@ -33,7 +33,7 @@ def test_projection_binning_and_sort(oracle, seed):
     rc, st, P = f.read_status()
     assert rc == 0 and st == 0
     pr = oracle.project(sc["params"], cam)
-    spl = f.buf("splats", torch.float32, 2000 * 12).view(2000, 12).cpu().numpy()
+    spl = f.buf("splats", torch.float32, 2000 * B.SPLAT_WORDS).view(2000, B.SPLAT_WORDS).cpu().numpy()
     vis = pr["visible"]
     for k, name in ((0, "mx"), (1, "my"), (2, "A"), (3, "B"), (4, "C"), (5, "o"), (6, "z")):
         close(spl[vis, k], pr[name][vis], FWD_RTOL, what=name)
@@ -48,6 +48,16 @@ def test_projection_binning_and_sort(oracle, seed):
     both = ok & ~empty_o
     assert (rect_o[both] == rect_g[both]).all()
     assert amb.sum() < 20
+    # the record's pair-slot words: first slot (the emission offset), x0 | y0 << 16, width
+    cnt = f.buf("counts", torch.int32, 2000).cpu().numpy()
+    off = f.buf("offsets", torch.int32, 2000).cpu().numpy()
+    words = spl.view(np.int32)
+    has = cnt > 0
+    assert has.sum() > 1000
+    assert (words[has, 12] == off[has]).all()
+    assert (words[has, 13] == rect_g[has, 0] + (rect_g[has, 1] << 16)).all()
+    assert (words[has, 14] == rect_g[has, 2] - rect_g[has, 0] + 1).all()
+    assert (cnt[has] == (rect_g[has, 2] - rect_g[has, 0] + 1) * (rect_g[has, 3] - rect_g[has, 1] + 1)).all()
     # pair list: GPU order is exactly the stable (tile, depth bits, index) lexsort of its own keys
     keys = f.buf("pair_keys", torch.int32, P).cpu().numpy().astype(np.int64)
     vals = f.buf("pair_vals", torch.int32, P).cpu().numpy().astype(np.int64)
@@ -316,7 +326,7 @@ def test_jacobian_frustum_limit_parity(oracle):
     img = r.forward(p, ids, probs=True)
     torch.cuda.synchronize()
     pr = oracle.project(p0, cam)
-    spl = r.frame.buf("splats", torch.float32, 2000 * 12).view(2000, 12).cpu().numpy()
+    spl = r.frame.buf("splats", torch.float32, 2000 * B.SPLAT_WORDS).view(2000, B.SPLAT_WORDS).cpu().numpy()
     vis = pr["visible"] & clamped
     for k, name in ((2, "A"), (3, "B"), (4, "C")):
         close(spl[vis, k], pr[name][vis], FWD_RTOL, what=name)
