@@ -546,7 +546,7 @@ def main():
     ap.add_argument("--jobs", type=int, default=8, help="per-object jobs beside the 8 keyframes (at most 8)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--event-every", type=int, default=25,
-                    help="time the render backward with HIP events on every N-th timed step (default 10)")
+                    help="time the render backward with HIP events on every N-th timed step (default 25)")
     ap.add_argument("--no-graph", action="store_true",
                     help="issue every timed step eagerly instead of replaying the captured step")
     ap.add_argument("--cpu-pixels", type=int, default=49152)
