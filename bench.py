@@ -551,6 +551,8 @@ def main():
                     help="issue every timed step eagerly instead of replaying the captured step")
     ap.add_argument("--cpu-pixels", type=int, default=49152)
     ap.add_argument("--tile", default="8x8", help="pixel tile WxH (8x8, 16x8, 16x16, 32x8, 8x32)")
+    ap.add_argument("--depth-order", default="auto", choices=["auto", "global", "tile"],
+                    help="how each tile's pairs are put in depth order (dqo_depth_order)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -578,7 +580,8 @@ def main():
         return bench_tracking(args)
     log("building workload")
     sc, p, ids, targets = build_workload(n=args.n)
-    tr = B.Trainer(p, ids, sc["cams"], sc["K"], targets, ctx=B.Context(tile_w=tw, tile_h=th))
+    order = {"auto": B.DEPTH_ORDER_AUTO, "global": B.DEPTH_ORDER_GLOBAL, "tile": B.DEPTH_ORDER_TILE}[args.depth_order]
+    tr = B.Trainer(p, ids, sc["cams"], sc["K"], targets, ctx=B.Context(tile_w=tw, tile_h=th, depth_order=order))
     log(f"pair capacity {tr.r.frame.capacity}")
     for _ in range(args.warmup):
         tr.step()

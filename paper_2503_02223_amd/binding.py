@@ -51,7 +51,10 @@ class NetLayout(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("z_near", ctypes.c_double),
                 ("dilation", ctypes.c_double), ("q_max", ctypes.c_double), ("alpha_min", ctypes.c_double),
-                ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double), ("bg", ctypes.c_double * 3)]
+                ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double), ("bg", ctypes.c_double * 3),
+                ("depth_order", ctypes.c_int32), ("tile_sort_lds", ctypes.c_int32)]
+
+DEPTH_ORDER_AUTO, DEPTH_ORDER_GLOBAL, DEPTH_ORDER_TILE = 0, 1, 2
 
 
 class Camera(ctypes.Structure):

@@ -37,6 +37,8 @@ struct Geo {
     int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_sbase, off_seg, off_cbase,
         off_tlast, off_ckpt, off_lbd, off_lbs, off_lbp;
     int64_t seg_cap, ckpt_cap;
+    bool tile_sort;     // per-tile depth order (dqo_depth_order TILE)
+    int tile_sort_lds;  // pairs of a tile sorted in LDS
 };
 
 int validate_frame(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams) {
@@ -92,6 +94,9 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.pair_first_buf = g.pair_passes & 1;
     g.items = (int64_t)d->n * d->n_views;
     const int64_t M = g.items, cap = d->pair_capacity;
+    const int order = ctx->cfg.depth_order;
+    g.tile_sort = order == DQO_DEPTH_ORDER_TILE;  // AUTO: GLOBAL
+    g.tile_sort_lds = ctx->cfg.tile_sort_lds > 0 ? ctx->cfg.tile_sort_lds : 4096;
     const int64_t ts = d->dtype == DQO_F64 ? 8 : 4;
     g.depth_blocks = (int)((M + kDepthNt * depth_ipt(M) - 1) / (kDepthNt * depth_ipt(M)));
     g.scan_blocks = (int)((M + kScanTile - 1) / kScanTile);
@@ -182,6 +187,8 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.pair_blocks = g.pair_blocks;
     s.pair_passes = g.pair_passes;
     s.pair_first_buf = g.pair_first_buf;
+    s.tile_sort = g.tile_sort;
+    s.tile_sort_lds = g.tile_sort_lds;
     // One histogram copy per 64 producer workgroups (up to kHistCopies): enough
     // to spread the atomics, few enough for the radix passes to sum cheaply.
     const int64_t proj_blocks = (g.items + 256 * kProjItems - 1) / (256 * kProjItems);
@@ -352,6 +359,8 @@ void dqo_config_default(dqo_config* c) {
     c->alpha_max = 0.99;
     c->t_min = 1e-4;
     c->bg[0] = c->bg[1] = c->bg[2] = 0.0;
+    c->depth_order = DQO_DEPTH_ORDER_AUTO;
+    c->tile_sort_lds = 0;
 }
 
 int dqo_ctx_create(dqo_ctx** out, const dqo_config* cfg) {
@@ -361,7 +370,8 @@ int dqo_ctx_create(dqo_ctx** out, const dqo_config* cfg) {
     if (cfg) c = *cfg;
     if (!tile_ok(c.tile_w, c.tile_h)) return DQO_EINVAL;
     if (!(c.alpha_min > 0 && c.alpha_max <= 1 && c.alpha_min < c.alpha_max && c.t_min > 0 && c.t_min < 1 &&
-          c.q_max > 0 && c.dilation >= 0 && c.z_near > 0))
+          c.q_max > 0 && c.dilation >= 0 && c.z_near > 0 && c.depth_order >= DQO_DEPTH_ORDER_AUTO &&
+          c.depth_order <= DQO_DEPTH_ORDER_TILE && c.tile_sort_lds >= 0 && c.tile_sort_lds <= 4096))
         return DQO_EINVAL;
     dqo_ctx* x = new dqo_ctx;
     x->cfg = c;

@@ -226,19 +226,19 @@ __device__ __forceinline__ uint32_t lookback_exclusive(uint64_t* words, int stri
 }
 
 // Sum of the values published at words[j * stride], j in [lo, hi), waiting
-// for each to carry this epoch; the loads of up to 16 entries are in flight
-// at once and only the entries not yet published are read again.
+// for each to carry this epoch; the loads of up to 8 entries are in flight at
+// once and only the entries not yet published are read again.
 __device__ __forceinline__ uint32_t lb_sum_published(const uint64_t* words, int stride, int lo, int hi,
                                                      uint32_t epoch, uint32_t* status) {
     uint32_t sum = 0, spins = 0;
-    for (int j0 = lo; j0 < hi; j0 += 16) {
-        uint32_t pending = (hi - j0 >= 16) ? 0xFFFFu : ((1u << (hi - j0)) - 1u);
+    for (int j0 = lo; j0 < hi; j0 += 8) {
+        uint32_t pending = (hi - j0 >= 8) ? 0xFFu : ((1u << (hi - j0)) - 1u);
         while (pending) {
-            uint64_t w[16];
+            uint64_t w[8];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) w[k] = ((pending >> k) & 1u) ? lb_load(words + (size_t)(j0 + k) * stride) : 0ull;
+            for (int k = 0; k < 8; ++k) w[k] = ((pending >> k) & 1u) ? lb_load(words + (size_t)(j0 + k) * stride) : 0ull;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
+            for (int k = 0; k < 8; ++k) {
                 if (((pending >> k) & 1u) && lb_flag(w[k], epoch) != 0u) {
                     sum += (uint32_t)w[k];
                     pending &= ~(1u << k);
@@ -266,6 +266,9 @@ __device__ __forceinline__ uint32_t lb_sum_published(const uint64_t* words, int 
 // group: three round trips, and far fewer loads.  Blocks wait only on blocks
 // of lower index.
 constexpr int kLbGroup = 16;
+#ifndef DQO_LB_GROUPED
+#define DQO_LB_GROUPED 1
+#endif
 __host__ __device__ constexpr int lb_groups(int blocks) { return (blocks + kLbGroup - 1) / kLbGroup; }
 __host__ __device__ constexpr int lb_blocks(int blocks) { return blocks + lb_groups(blocks); }  // words per digit
 __device__ __forceinline__ uint32_t lookback_grouped(uint64_t* words, uint64_t* gwords, int stride, int slot,
@@ -361,6 +364,11 @@ struct StatePtrs {
     int pair_blocks;      // radix blocks over capacity
     int pair_passes;
     int pair_first_buf;   // buffer emission writes into so the sort ends in buffer 0
+    // Per-tile depth order: items are not sorted by depth; pairs are emitted
+    // in item order (order = identity) and each tile's pairs sorted after the
+    // tile sort.
+    bool tile_sort;
+    int tile_sort_lds;    // longest tile range sorted in LDS (longer ones: global-memory passes)
     int hist_copies_depth;  // histogram copies in use (1..kHistCopies), by producer workgroup count
     int hist_copies_pair;
 };
@@ -410,6 +418,10 @@ hipError_t launch_fit_quadric(int n_obj, int64_t n_boxes, const double* boxes, c
 hipError_t launch_clear_ctrl(Ctrl* ctrl, uint64_t* lb, int64_t lb_words, hipStream_t st);
 hipError_t launch_clear_status(Ctrl* ctrl, hipStream_t st);
 hipError_t launch_zero_words(uint32_t* p, int64_t n, hipStream_t st);
+
+// The order in which items emit their pairs (and own consecutive pair
+// slots): the depth order, or item order (nullptr) under per-tile depth order.
+inline const uint32_t* item_order(const StatePtrs& s) { return s.tile_sort ? nullptr : s.depth_vals[0]; }
 
 // Workgroups of Kernel (at Threads per group, no dynamic LDS) that the
 // current device holds at once, computed once per kernel; 0 if unknown.

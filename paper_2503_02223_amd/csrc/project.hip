@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_block_sums_kernel(const uin
 #pragma unroll
     for (int k = 0; k < kScanIpt; ++k) {
         const uint32_t q = base + tid * kScanIpt + k;
-        if (q < M) v += counts[min(order[q], M - 1)];
+        if (q < M) v += counts[order ? min(order[q], M - 1) : q];
     }
     const uint32_t excl = block_exclusive_scan<kScanThreads>(v, s_tmp);
     if (tid == kScanThreads - 1) sums[blockIdx.x] = excl + v;
@@ -257,6 +257,19 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     __shared__ uint32_t s_tmp[kScanThreads / kWave];
     __shared__ uint32_t s_base, s_bid, s_agg, s_ticket;
     const int tid = threadIdx.x;
+    // The block's records at its workgroup index (the order in force unless a
+    // ticket is drawn), loaded before anything waits; order is a permutation
+    // of [0, M) (the depth order), or the identity.
+    uint32_t c[kScanIpt], rec[kScanIpt], sum = 0;
+    auto load_recs = [&](uint32_t b) {
+#pragma unroll
+        for (int k = 0; k < kScanIpt; ++k) {
+            const uint32_t q = b * (uint32_t)kScanTile + tid * kScanIpt + k;
+            rec[k] = q < M ? (order ? min(order[q], M - 1) : q) : 0xffffffffu;
+        }
+    };
+    load_recs(blockIdx.x);
+    const uint32_t epoch = ctrl->epoch;
     if (tid == 0) {
         // Single-level scans chain every block to its predecessor by
         // workgroup index, which needs the whole grid on the device at once;
@@ -273,16 +286,10 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     const uint32_t bid = s_bid;
     const uint32_t base = bid * (uint32_t)kScanTile;
     if (base >= M) return;
-    const uint32_t epoch = ctrl->epoch;
+    if (bid != blockIdx.x) load_recs(bid);
     // The block's records with their counts and tile rectangles, gathered
     // with every load in flight at once and kept in LDS for the emission.
-    uint32_t c[kScanIpt], rec[kScanIpt], sum = 0;
     short4 rc[kScanIpt];
-#pragma unroll
-    for (int k = 0; k < kScanIpt; ++k) {
-        const uint32_t q = tid * kScanIpt + k;
-        rec[k] = base + q < M ? min(order[base + q], M - 1) : 0xffffffffu;  // order is a permutation of [0, M)
-    }
 #pragma unroll
     for (int k = 0; k < kScanIpt; ++k) {
         const bool ok = rec[k] != 0xffffffffu;
@@ -312,7 +319,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
             s_base = block_base[bid];
         } else {
             // all blocks start at once unless the ticket order is in force
-            const uint32_t excl = s_ticket ? lookback_exclusive(lb, 1, (int)bid, agg, epoch, &ctrl->status)
+            const uint32_t excl = (s_ticket || !DQO_LB_GROUPED) ? lookback_exclusive(lb, 1, (int)bid, agg, epoch, &ctrl->status)
                                            : lookback_grouped(lb, lb + gridDim.x, 1, (int)bid, agg, epoch,
                                                               &ctrl->status);
             s_base = excl;
@@ -404,7 +411,7 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
                        f.n, M, params, ids, (T*)s.splats, s.rects, s.counts, s.depth_keys[0], s.depth_vals[0],
                        s.ranges, range_words, s.hist_copies_depth, s.ctrl);
     int src = 0;
-    for (int p = 0; p < kMaxDepthPasses; ++p) {
+    for (int p = 0; p < (s.tile_sort ? 0 : kMaxDepthPasses); ++p) {
         hipError_t e = launch_radix_pass(s.depth_keys[src], s.depth_vals[src], s.depth_keys[src ^ 1],
                                          s.depth_vals[src ^ 1], nullptr, (uint32_t)M, p * kRadixBits,
                                          &s.ctrl->hist_depth[0][p][0], kMaxDepthPasses * kRadixBins, s.hist_copies_depth,
@@ -417,11 +424,11 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
     const bool two_level = s.scan_blocks > resident_blocks<scan_emit_kernel<T>, kScanThreads>();
     if (two_level) {
         hipLaunchKernelGGL(scan_block_sums_kernel, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st,
-                           s.depth_vals[0], s.counts, (uint32_t)M, s.scan_base);
+                           item_order(s), s.counts, (uint32_t)M, s.scan_base);
         hipLaunchKernelGGL(scan_block_base_kernel, dim3(1), dim3(kScanThreads), 0, st, s.scan_base, s.scan_blocks,
                            (uint32_t)s.capacity, s.ctrl);
     }
-    hipLaunchKernelGGL(scan_emit_kernel<T>, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st, s.depth_vals[0],
+    hipLaunchKernelGGL(scan_emit_kernel<T>, dim3((unsigned)s.scan_blocks), dim3(kScanThreads), 0, st, item_order(s),
                        s.counts, s.rects, s.offsets, (T*)s.splats, s.pair_keys[pf], s.pair_vals[pf], (uint32_t)M,
                        (uint32_t)s.capacity, f.n, f.views.tiles_x, f.views.tiles_per_view, s.pair_passes,
                        s.hist_copies_pair, s.lb_scan, s.ctrl, two_level ? (const uint32_t*)s.scan_base : nullptr);
@@ -500,7 +507,7 @@ __global__ __launch_bounds__(kSlotWaves * kWave) void slot_sum_kernel(const uint
     const uint32_t q = ((uint32_t)blockIdx.x * kSlotWaves + wave) * kWave + lane;
     uint32_t rec = 0, c = 0, off = 0;
     if (q < M) {
-        rec = min(order[q], M - 1);
+        rec = order ? min(order[q], M - 1) : q;  // emission order: depth order, or item order
         c = counts[rec];
         off = offsets[rec];
     }
@@ -765,7 +772,7 @@ hipError_t launch_project_backward(const Frame<T>& f, const T* params, T* grads,
     if (f.n == 0) return hipSuccess;
     const int64_t M = f.s.items;
     hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
-                       dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
+                       dim3(kSlotWaves * kWave), 0, st, item_order(f.s), f.s.counts, f.s.offsets,
                        (const T*)f.s.partials, f.s.written, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
     hipLaunchKernelGGL((project_backward_kernel<T>), dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st,
                        f.views, f.consts, f.n, const_cast<T*>(params), f.s.counts, f.s.offsets, (const T*)f.s.sums,
@@ -857,7 +864,7 @@ hipError_t launch_pose_backward(const Frame<T>& f, const T* params, double* pose
     if (f.n == 0) return launch_zero_words((uint32_t*)pose, 12 * (int64_t)V, st);
     const int64_t M = f.s.items;
     hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
-                       dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
+                       dim3(kSlotWaves * kWave), 0, st, item_order(f.s), f.s.counts, f.s.offsets,
                        (const T*)f.s.partials, f.s.written, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
     const int blocks = (int)((f.n + 255) / 256);
     hipLaunchKernelGGL(pose_grad_kernel<T>, dim3((unsigned)blocks, (unsigned)V), dim3(256), 0, st, f.views, f.consts,
@@ -874,7 +881,7 @@ hipError_t launch_project_backward_adam(const Frame<T>& f, T* params, T* grads, 
     if (f.n == 0) return launch_adam<T>(params, grads, m, v, 0, hp, 1, d_step, st, kParams);  // advances the step
     const int64_t M = f.s.items;
     hipLaunchKernelGGL(slot_sum_kernel<T>, dim3((unsigned)((M + kSlotWaves * kWave - 1) / (kSlotWaves * kWave))),
-                       dim3(kSlotWaves * kWave), 0, st, f.s.depth_vals[0], f.s.counts, f.s.offsets,
+                       dim3(kSlotWaves * kWave), 0, st, item_order(f.s), f.s.counts, f.s.offsets,
                        (const T*)f.s.partials, f.s.written, (uint32_t)M, (uint32_t)f.s.capacity, (T*)f.s.sums);
     hipLaunchKernelGGL((project_backward_kernel<T>), dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st,
                        f.views, f.consts, f.n, params, f.s.counts, f.s.offsets, (const T*)f.s.sums,

@@ -37,6 +37,29 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
+    // Every load that does not depend on another is issued before the first
+    // wait: the item count, the block's keys at its workgroup index (the order
+    // in force unless a ticket is drawn; bounded by the buffer's size n_host,
+    // the tail past the count is masked below), the digit totals and the
+    // control words.
+    const uint32_t n_read = n_dev ? *n_dev : n_host;
+    uint32_t key[IPT], val[IPT], rank[IPT];
+    auto load_block = [&](uint32_t b) {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const uint32_t pos = b * (uint32_t)kTile + wave * (kWave * IPT) + i * kWave + lane;
+            key[i] = pos < n_host ? kin[pos] : 0u;
+            val[i] = pos < n_host ? vin[pos] : 0u;
+        }
+    };
+    if (resident) load_block(blockIdx.x);
+    const int t = tid;
+    const bool owner = t < kRadixBins;
+    uint32_t gcount = 0;
+    if (owner) {
+        // the digit's count over all keys: the sum of the histogram copies
+        for (int c = 0; c < hist_copies; ++c) gcount += ghist[c * hist_stride + t];
+    }
     if (tid == 0) {
         // Workgroup-index order needs the whole grid on the device at once;
         // once a bounded wait has given up (status bit, kept until the caller
@@ -46,28 +69,20 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
         // walks the chain.
         const bool ticket = !resident || (ctrl->status & (uint32_t)DQO_STATUS_TIMEOUT) != 0u;
         s_bid = ticket ? atomicAdd(counter, 1u) : blockIdx.x;
-        s_grouped = ticket ? 0u : 1u;
+        s_grouped = (ticket || !DQO_LB_GROUPED) ? 0u : 1u;
         s_epoch = ctrl->epoch;
     }
     for (int i = tid; i < kWaves * kRadixBins; i += NT) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t bid = s_bid;
-    uint32_t n = n_host;
-    if (n_dev) n = min(*n_dev, n_host);
+    const uint32_t n = min(n_read, n_host);
     const uint32_t base = bid * (uint32_t)kTile;
     if (base >= n) return;  // uniform over the block; no later block waits on this one
     const uint32_t epoch = s_epoch;
+    // ticket order, or a grid not resident: the block's keys now
+    if (!resident || bid != blockIdx.x) load_block(bid);
 
-    uint32_t key[IPT], val[IPT], rank[IPT];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // All loads first: interleaved with the ballots below they were issued one
-    // at a time, each waiting a full memory latency.
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const uint32_t pos = base + wave * (kWave * IPT) + i * kWave + lane;
-        key[i] = pos < n ? kin[pos] : 0u;
-        val[i] = pos < n ? vin[pos] : 0u;
-    }
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const uint32_t pos = base + wave * (kWave * IPT) + i * kWave + lane;
@@ -90,9 +105,7 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
     __syncthreads();
 
     // Thread t < 256 owns digit t: per-wave exclusive offsets and the block total.
-    const int t = tid;
-    const bool owner = t < kRadixBins;
-    uint32_t total = 0, gcount = 0;
+    uint32_t total = 0;
     if (owner) {
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
@@ -100,8 +113,6 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
             s_wcnt[w][t] = total;
             total += c;
         }
-        // the digit's count over all keys: the sum of the histogram copies
-        for (int c = 0; c < hist_copies; ++c) gcount += ghist[c * hist_stride + t];
     }
     const uint32_t dstart = block_exclusive_scan<NT>(total, s_tmp);
     const uint32_t gdig = block_exclusive_scan<NT>(gcount, s_tmp);
@@ -361,6 +372,119 @@ hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
     return hipErrorInvalidValue;
 }
 
+// Per-tile depth order.  The pairs were emitted in item order and stably
+// sorted by tile, so each tile's range holds its items in index order; one
+// workgroup per tile sorts them by the item's depth key, ties by item index:
+// the order a stable sort of every item by depth followed by the stable tile
+// sort gives.  Up to kTileSortLds pairs: a bitonic network over (key << 32 |
+// item) in LDS.  Longer ranges: four stable 8-bit passes over global memory by
+// the workgroup, through tmp (slow; meant for rare long tiles).
+constexpr int kTileSortThreads = 256;
+constexpr int kTileSortLds = 4096;
+
+__global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const uint32_t* __restrict__ ranges,
+                                                                    const uint32_t* __restrict__ dkeys, uint32_t M,
+                                                                    uint32_t cap, uint32_t lds_max,
+                                                                    uint32_t* __restrict__ pvals,
+                                                                    uint32_t* __restrict__ tmp) {
+    __shared__ uint64_t s_k[kTileSortLds];
+    __shared__ uint32_t s_off[kRadixBins];
+    __shared__ uint32_t s_wcnt[kTileSortThreads / kWave][kRadixBins];
+    __shared__ uint32_t s_scan[kTileSortThreads / kWave];
+    const int tid = threadIdx.x;
+    const uint32_t re = min(ranges[2 * blockIdx.x + 1], cap), rs = min(ranges[2 * blockIdx.x], re);
+    const uint32_t n = re - rs;
+    if (n <= 1u) return;
+    if (n <= min(lds_max, (uint32_t)kTileSortLds)) {
+        uint32_t P = 2u;
+        while (P < n) P <<= 1;
+        for (uint32_t i = tid; i < P; i += kTileSortThreads) {
+            uint64_t k = ~0ull;  // padding sorts last
+            if (i < n) {
+                const uint32_t item = min(pvals[rs + i], M - 1);
+                k = ((uint64_t)dkeys[item] << 32) | item;
+            }
+            s_k[i] = k;
+        }
+        __syncthreads();
+        for (uint32_t k = 2u; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0u; j >>= 1) {
+                for (uint32_t i = tid; i < P / 2u; i += kTileSortThreads) {
+                    const uint32_t lo = ((i & ~(j - 1u)) << 1) | (i & (j - 1u));  // bit j of lo clear
+                    const uint32_t hi = lo | j;
+                    const uint64_t a = s_k[lo], b = s_k[hi];
+                    const bool up = (lo & k) == 0u;
+                    if ((a > b) == up) {
+                        s_k[lo] = b;
+                        s_k[hi] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = tid; i < n; i += kTileSortThreads) pvals[rs + i] = (uint32_t)s_k[i];
+        return;
+    }
+    // Long range: stable LSD passes, 256 items per round in index order,
+    // ranked inside each wavefront by match ballots.
+    const int lane = tid & (kWave - 1), wave = tid >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t* src = pvals + rs;
+    uint32_t* dst = tmp + rs;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = pass * kRadixBits;
+        for (int w = 0; w < kTileSortThreads / kWave; ++w)
+            if (tid < kRadixBins) s_wcnt[w][tid] = 0u;
+        if (tid < kRadixBins) s_off[tid] = 0u;
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += kTileSortThreads)
+            atomicAdd(&s_off[(dkeys[min(src[i], M - 1)] >> shift) & (kRadixBins - 1)], 1u);
+        __syncthreads();
+        {
+            const uint32_t c = tid < kRadixBins ? s_off[tid] : 0u;
+            const uint32_t ex = block_exclusive_scan<kTileSortThreads>(c, s_scan);
+            __syncthreads();
+            if (tid < kRadixBins) s_off[tid] = ex;
+            __syncthreads();
+        }
+        for (uint32_t c0 = 0; c0 < n; c0 += kTileSortThreads) {
+            const uint32_t i = c0 + (uint32_t)tid;
+            const bool valid = i < n;
+            const uint32_t item = valid ? src[i] : 0u;
+            const uint32_t d = valid ? (dkeys[min(item, M - 1)] >> shift) & (kRadixBins - 1) : 0u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < kRadixBits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+            const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+            if (valid && (peers >> lane) == 1ull) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t before = 0;
+                for (int w = 0; w < wave; ++w) before += s_wcnt[w][d];
+                dst[s_off[d] + before + below] = item;
+            }
+            __syncthreads();
+            if (tid < kRadixBins) {
+                uint32_t total = 0;
+                for (int w = 0; w < kTileSortThreads / kWave; ++w) {
+                    total += s_wcnt[w][tid];
+                    s_wcnt[w][tid] = 0u;
+                }
+                s_off[tid] += total;
+            }
+            __syncthreads();
+        }
+        uint32_t* t = src;
+        src = dst;
+        dst = t;
+    }
+    // four passes: the result is back in pvals
+}
+
 hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st) {
     const uint32_t cap = (uint32_t)s.capacity;
     const uint32_t* n_dev = &s.ctrl->num_pairs;
@@ -381,6 +505,10 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1 << 20, ((int64_t)cap + 255) / 256));
         hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges,
                            (uint32_t*)s.written);
+        if (s.tile_sort)
+            hipLaunchKernelGGL(tile_sort_kernel, dim3((unsigned)tiles_total), dim3(kTileSortThreads), 0, st, s.ranges,
+                               s.depth_keys[0], (uint32_t)s.items, cap, (uint32_t)s.tile_sort_lds, s.pair_vals[0],
+                               s.pair_vals[1]);
         hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
                            s.schedule, segmented_backward(s, tiles_total) ? s.ckpt_base : nullptr);
         return hipGetLastError();

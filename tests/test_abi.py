@@ -98,6 +98,11 @@ def test_bad_tile_config_rejected():
     cfg = B.default_config(tile_w=12, tile_h=12)
     with pytest.raises(B.DqoError):
         B.Context(cfg)
+    for bad in (dict(depth_order=3), dict(depth_order=-1), dict(tile_sort_lds=4097), dict(tile_sort_lds=-1)):
+        with pytest.raises(B.DqoError):
+            B.Context(B.default_config(**bad))
+    assert B.default_config().depth_order == B.DEPTH_ORDER_AUTO and B.default_config().tile_sort_lds == 0
+    B.Context(B.default_config(depth_order=B.DEPTH_ORDER_TILE, tile_sort_lds=4096))
 
 
 def test_null_pointers_rejected_before_launch():

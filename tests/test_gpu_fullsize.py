@@ -130,7 +130,7 @@ def test_sort_order_on_grids_too_large_to_be_resident():
     the stable (tile, depth bits, index) order with exact tile ranges."""
     sc = scenes.keyframe_scene(seed=0)
     n, V = sc["params"].shape[1], len(sc["cams"])
-    r = B.Rasterizer(sc["cams"], n, sc["K"], ctx=B.Context(tile_w=16, tile_h=8))
+    r = B.Rasterizer(sc["cams"], n, sc["K"], ctx=B.Context(tile_w=16, tile_h=8, depth_order=B.DEPTH_ORDER_GLOBAL))
     p = to_dev(sc["params"])
     ids = torch.tensor(sc["ids"], device="cuda")
     r.bin(p, ids, grow=True)

@@ -27,7 +27,8 @@ def _set_timeout_bit(f):
 
 def test_timeout_bit_switches_sort_to_ticket_order():
     sc = scenes.single_view_scene(seed=1, n=2000)
-    r = B.Rasterizer(sc["cams"], 2000, 3, ctx=B.Context(tile_w=8, tile_h=8))
+    # the global depth order, whose four depth passes take tickets too
+    r = B.Rasterizer(sc["cams"], 2000, 3, ctx=B.Context(tile_w=8, tile_h=8, depth_order=B.DEPTH_ORDER_GLOBAL))
     p = to_dev(sc["params"])
     ids = torch.tensor(sc["ids"], device="cuda")
     r.bin(p, ids)          # sizes the pair list (grows it on overflow)
