@@ -376,15 +376,68 @@ hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
 // sorted by tile, so each tile's range holds its items in index order; one
 // workgroup per tile sorts them by the item's depth key, ties by item index:
 // the order a stable sort of every item by depth followed by the stable tile
-// sort gives.  Up to kTileSortLds pairs: a bitonic network over (key << 32 |
-// item) in LDS.  Longer ranges: four stable 8-bit passes over global memory by
-// the workgroup, through tmp (slow; meant for rare long tiles).
+// sort gives.  Up to kTileSortLds pairs: a bitonic network over the 64-bit
+// values key << 32 | item, padded to P = 256 E (E = 1..16 values per thread,
+// held in registers in blocked order: value e = thread E + r).  Its stages
+// with a partner distance j < E run inside a thread, those with j < 64 E
+// across the lanes of a wavefront (shuffles), and only those with j >= 64 E
+// (three at P = 4096) through LDS with barriers.  Longer ranges: four stable
+// 8-bit passes over global memory by the workgroup, through tmp (slow; meant
+// for rare long tiles).  Tiles are taken in the launch order of the render
+// (longest first), so the longest sorts start first.
 constexpr int kTileSortThreads = 256;
 constexpr int kTileSortLds = 4096;
 
+__device__ __forceinline__ uint64_t keep_lo_hi(uint64_t mine, uint64_t other, bool keep_min) {
+    const bool lt = mine < other;
+    return (lt == keep_min) ? mine : other;
+}
+
+template <int E>
+__device__ __forceinline__ void tile_bitonic(uint64_t (&x)[16], uint64_t* s_x, int tid, uint32_t P) {
+    const int lane = tid & (kWave - 1);
+    for (uint32_t k = 2u; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0u; j >>= 1) {
+            if (j < (uint32_t)E) {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    if ((r & (int)j) == 0) {
+                        const uint32_t e = (uint32_t)tid * E + r;
+                        const bool up = (e & k) == 0u;
+                        const uint64_t a = x[r], b = x[r | (int)j];
+                        const bool swap = (a > b) == up;
+                        x[r] = swap ? b : a;
+                        x[r | (int)j] = swap ? a : b;
+                    }
+                }
+            } else if (j < (uint32_t)(kWave * E)) {
+                const int d = (int)(j / (uint32_t)E);
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const uint64_t y = (uint64_t)__shfl_xor((unsigned long long)x[r], d);
+                    const uint32_t e = (uint32_t)tid * E + r;
+                    x[r] = keep_lo_hi(x[r], y, ((e & j) == 0u) == ((e & k) == 0u));
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) s_x[tid * E + r] = x[r];
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const uint32_t e = (uint32_t)tid * E + r;
+                    x[r] = keep_lo_hi(x[r], s_x[e ^ j], ((e & j) == 0u) == ((e & k) == 0u));
+                }
+                __syncthreads();
+            }
+        }
+    }
+    (void)lane;
+}
+
 __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const uint32_t* __restrict__ ranges,
+                                                                    const uint32_t* __restrict__ schedule,
                                                                     const uint32_t* __restrict__ dkeys, uint32_t M,
-                                                                    uint32_t cap, uint32_t lds_max,
+                                                                    uint32_t cap, uint32_t lds_max, int tiles,
                                                                     uint32_t* __restrict__ pvals,
                                                                     uint32_t* __restrict__ tmp) {
     __shared__ uint64_t s_k[kTileSortLds];
@@ -392,37 +445,36 @@ __global__ __launch_bounds__(kTileSortThreads) void tile_sort_kernel(const uint3
     __shared__ uint32_t s_wcnt[kTileSortThreads / kWave][kRadixBins];
     __shared__ uint32_t s_scan[kTileSortThreads / kWave];
     const int tid = threadIdx.x;
-    const uint32_t re = min(ranges[2 * blockIdx.x + 1], cap), rs = min(ranges[2 * blockIdx.x], re);
+    const uint32_t tile = min(schedule[blockIdx.x], (uint32_t)(tiles - 1));
+    const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
     const uint32_t n = re - rs;
     if (n <= 1u) return;
     if (n <= min(lds_max, (uint32_t)kTileSortLds)) {
-        uint32_t P = 2u;
-        while (P < n) P <<= 1;
-        for (uint32_t i = tid; i < P; i += kTileSortThreads) {
-            uint64_t k = ~0ull;  // padding sorts last
-            if (i < n) {
-                const uint32_t item = min(pvals[rs + i], M - 1);
-                k = ((uint64_t)dkeys[item] << 32) | item;
-            }
-            s_k[i] = k;
-        }
-        __syncthreads();
-        for (uint32_t k = 2u; k <= P; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0u; j >>= 1) {
-                for (uint32_t i = tid; i < P / 2u; i += kTileSortThreads) {
-                    const uint32_t lo = ((i & ~(j - 1u)) << 1) | (i & (j - 1u));  // bit j of lo clear
-                    const uint32_t hi = lo | j;
-                    const uint64_t a = s_k[lo], b = s_k[hi];
-                    const bool up = (lo & k) == 0u;
-                    if ((a > b) == up) {
-                        s_k[lo] = b;
-                        s_k[hi] = a;
-                    }
-                }
-                __syncthreads();
+        int E = 1;
+        while ((uint32_t)(kTileSortThreads * E) < n) E <<= 1;
+        const uint32_t P = (uint32_t)(kTileSortThreads * E);
+        uint64_t x[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t e = (uint32_t)tid * E + r;
+            x[r] = ~0ull;  // padding sorts last
+            if (r < E && e < n) {
+                const uint32_t item = min(pvals[rs + e], M - 1);
+                x[r] = ((uint64_t)dkeys[item] << 32) | item;
             }
         }
-        for (uint32_t i = tid; i < n; i += kTileSortThreads) pvals[rs + i] = (uint32_t)s_k[i];
+        switch (E) {
+            case 1: tile_bitonic<1>(x, s_k, tid, P); break;
+            case 2: tile_bitonic<2>(x, s_k, tid, P); break;
+            case 4: tile_bitonic<4>(x, s_k, tid, P); break;
+            case 8: tile_bitonic<8>(x, s_k, tid, P); break;
+            default: tile_bitonic<16>(x, s_k, tid, P); break;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t e = (uint32_t)tid * E + r;
+            if (r < E && e < n) pvals[rs + e] = (uint32_t)x[r];
+        }
         return;
     }
     // Long range: stable LSD passes, 256 items per round in index order,
@@ -505,12 +557,12 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1 << 20, ((int64_t)cap + 255) / 256));
         hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges,
                            (uint32_t*)s.written);
-        if (s.tile_sort)
-            hipLaunchKernelGGL(tile_sort_kernel, dim3((unsigned)tiles_total), dim3(kTileSortThreads), 0, st, s.ranges,
-                               s.depth_keys[0], (uint32_t)s.items, cap, (uint32_t)s.tile_sort_lds, s.pair_vals[0],
-                               s.pair_vals[1]);
         hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
                            s.schedule, segmented_backward(s, tiles_total) ? s.ckpt_base : nullptr);
+        if (s.tile_sort)
+            hipLaunchKernelGGL(tile_sort_kernel, dim3((unsigned)tiles_total), dim3(kTileSortThreads), 0, st, s.ranges,
+                               s.schedule, s.depth_keys[0], (uint32_t)s.items, cap, (uint32_t)s.tile_sort_lds,
+                               tiles_total, s.pair_vals[0], s.pair_vals[1]);
         return hipGetLastError();
     }
     return launch_clear_written(s, st);
