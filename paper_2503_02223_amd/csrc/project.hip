@@ -462,6 +462,10 @@ hipError_t launch_clear_written(const StatePtrs& s, hipStream_t st) {
 // segment) and adds the segment totals to the item's accumulator in LDS in
 // round order: the result does not depend on timing.
 constexpr int kSlotWaves = 4;
+#ifndef DQO_SLOT_BATCH
+#define DQO_SLOT_BATCH 4
+#endif
+constexpr int kSlotBatch = DQO_SLOT_BATCH;  // rounds of 64 slots whose loads are issued together
 
 // Lane-shifted copy of x by DPP (row_shr:n within 16-lane rows, or the
 // row_bcast:15 / row_bcast:31 steps across rows); lanes without a source get 0.
@@ -521,35 +525,49 @@ __global__ __launch_bounds__(kSlotWaves * kWave) void slot_sum_kernel(const uint
     const uint32_t S0 = __shfl(off, first);
     const uint32_t S1 = (uint32_t)min((uint64_t)cap, (uint64_t)__shfl(off, lastl) + __shfl(c, lastl));
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t r0 = S0; r0 < S1; r0 += kWave) {
-        s_start[wave][lane] = 0;
-        if (has && off >= r0 && off < r0 + kWave) s_start[wave][off - r0] = 1;
-        __builtin_amdgcn_wave_barrier();
-        const uint64_t marks = __ballot(s_start[wave][lane] != 0);
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t before = (uint32_t)__popcll(__ballot(has && off < r0));
-        const uint32_t s = r0 + (uint32_t)lane;
-        const bool live = s < S1;
-        const uint64_t upto = marks & ((2ull << lane) - 1ull);
-        T v[kGradWords];
-        int owner = 0;
-        if (live) owner = s_nz[wave][before + (uint32_t)__popcll(upto) - 1u];
-        if (live && written[s]) {
+    // Rounds of 64 slots, kSlotBatch at a time: the marks of the batch's
+    // rounds are loaded together, then their marked partials together, so a
+    // batch costs two memory round trips instead of two per round.
+    for (uint32_t b0 = S0; b0 < S1; b0 += kSlotBatch * kWave) {
+        bool mk[kSlotBatch];
+        T vb[kSlotBatch][kGradWords];
 #pragma unroll
-            for (int k = 0; k < kGradWords; ++k) v[k] = partials[(size_t)s * kGradWords + k];
-        } else {
-#pragma unroll
-            for (int k = 0; k < kGradWords; ++k) v[k] = T(0);
+        for (int q = 0; q < kSlotBatch; ++q) {
+            const uint32_t s = b0 + q * kWave + (uint32_t)lane;
+            mk[q] = s < S1 && written[s] != 0;
         }
-        const int seg_lo = upto ? 63 - __clzll(upto) : 0;
 #pragma unroll
-        for (int k = 0; k < kGradWords; ++k) v[k] = segmented_scan<T>(v[k], lane, seg_lo);
-        const bool seg_end = live && (lane == kWave - 1 || ((marks >> (lane + 1)) & 1ull) || s + 1u >= S1);
-        if (seg_end) {
+        for (int q = 0; q < kSlotBatch; ++q) {
+            const uint32_t s = b0 + q * kWave + (uint32_t)lane;
 #pragma unroll
-            for (int k = 0; k < kGradWords; ++k) s_acc[wave][owner][k] += v[k];
+            for (int k = 0; k < kGradWords; ++k) vb[q][k] = mk[q] ? partials[(size_t)s * kGradWords + k] : T(0);
         }
-        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < kSlotBatch; ++q) {
+            const uint32_t r0 = b0 + q * kWave;
+            if (r0 >= S1) break;  // wave-uniform
+            s_start[wave][lane] = 0;
+            if (has && off >= r0 && off < r0 + kWave) s_start[wave][off - r0] = 1;
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t marks = __ballot(s_start[wave][lane] != 0);
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t before = (uint32_t)__popcll(__ballot(has && off < r0));
+            const uint32_t s = r0 + (uint32_t)lane;
+            const bool live = s < S1;
+            const uint64_t upto = marks & ((2ull << lane) - 1ull);
+            int owner = 0;
+            if (live) owner = s_nz[wave][before + (uint32_t)__popcll(upto) - 1u];
+            const int seg_lo = upto ? 63 - __clzll(upto) : 0;
+            T v[kGradWords];
+#pragma unroll
+            for (int k = 0; k < kGradWords; ++k) v[k] = segmented_scan<T>(vb[q][k], lane, seg_lo);
+            const bool seg_end = live && (lane == kWave - 1 || ((marks >> (lane + 1)) & 1ull) || s + 1u >= S1);
+            if (seg_end) {
+#pragma unroll
+                for (int k = 0; k < kGradWords; ++k) s_acc[wave][owner][k] += v[k];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
     }
     if (has && (uint64_t)off + c <= cap) {
 #pragma unroll
