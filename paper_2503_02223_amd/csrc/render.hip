@@ -52,6 +52,19 @@ __device__ __forceinline__ void load_splat(T (&r)[kRecWords], const T* src) {
 #pragma unroll
     for (int k = 0; k < kRecWords; ++k) r[k] = src[k];
 }
+// FP32 records from global memory: the pad value (word 11) is not loaded.
+// Every user overwrites it with the pair's position, and a load into a
+// register the compiler counts as free makes the next write of that register
+// wait for the load, and with it for every load before.
+__device__ __forceinline__ void load_words_0_10(float (&r)[kRecWords], const float* src) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+    const float4 a = s4[0], b = s4[1];
+    const float3 c = *reinterpret_cast<const float3*>(src + 8);
+    r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = a.w;
+    r[4] = b.x; r[5] = b.y; r[6] = b.z; r[7] = b.w;
+    r[8] = c.x; r[9] = c.y; r[10] = c.z;
+    r[11] = 0.0f;
+}
 template <>
 __device__ __forceinline__ void load_splat<float>(float (&r)[kRecWords], const float* src) {
     const float4* s4 = reinterpret_cast<const float4*>(src);
@@ -64,12 +77,21 @@ __device__ __forceinline__ void load_splat<float>(float (&r)[kRecWords], const f
         r[4 * q + 3] = a.w;
     }
 }
+// A record from global memory, whose pad value (word 11) the caller replaces.
+template <typename T>
+__device__ __forceinline__ void load_splat_global(T (&r)[kRecWords], const T* src) {
+    load_splat<T>(r, src);
+}
+template <>
+__device__ __forceinline__ void load_splat_global<float>(float (&r)[kRecWords], const float* src) {
+    load_words_0_10(r, src);
+}
 // The walked values of a splat record and the slot of its (tile tx, ty) pair:
 // the item's first slot plus the tile's place in its rectangle, row-major
 // (the record's last four values, the same 64-byte line in FP32).
 template <typename T>
 __device__ __forceinline__ uint32_t load_splat_slot(T (&r)[kRecWords], const T* src, int tx, int ty) {
-    load_splat<T>(r, src);
+    load_splat_global<T>(r, src);
     const uint32_t base = (uint32_t)word_to_id<T>(src[kSpSlot]);
     const uint32_t xy = (uint32_t)word_to_id<T>(src[kSpRect]);
     const uint32_t w = (uint32_t)word_to_id<T>(src[kSpRectW]);
@@ -77,16 +99,8 @@ __device__ __forceinline__ uint32_t load_splat_slot(T (&r)[kRecWords], const T* 
 }
 template <>
 __device__ __forceinline__ uint32_t load_splat_slot<float>(float (&r)[kRecWords], const float* src, int tx, int ty) {
-    const float4* s4 = reinterpret_cast<const float4*>(src);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const float4 a = s4[q];
-        r[4 * q] = a.x;
-        r[4 * q + 1] = a.y;
-        r[4 * q + 2] = a.z;
-        r[4 * q + 3] = a.w;
-    }
-    const float4 t = s4[3];
+    load_words_0_10(r, src);
+    const float3 t = *reinterpret_cast<const float3*>(src + kSpSlot);  // the pad after them is not loaded either
     const uint32_t base = __float_as_uint(t.x), xy = __float_as_uint(t.y), w = __float_as_uint(t.z);
     return base + (uint32_t)(ty - (int)(xy >> 16)) * w + (uint32_t)(tx - (int)(xy & 0xFFFFu));
 }
@@ -185,6 +199,22 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     const int64_t pix = (int64_t)py * V.W + px;
     const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
     const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
+#ifndef DQO_FWD_PRIO
+#define DQO_FWD_PRIO 0
+#endif
+    if constexpr (DQO_FWD_PRIO == 1) {
+        if (blockIdx.x < gridDim.x / 8u) __builtin_amdgcn_s_setprio(3);
+    } else if constexpr (DQO_FWD_PRIO == 2) {
+        const uint32_t len = re - rs;
+        if (len > 512u) __builtin_amdgcn_s_setprio(3);
+        else if (len > 256u) __builtin_amdgcn_s_setprio(2);
+        else if (len > 128u) __builtin_amdgcn_s_setprio(1);
+    } else if constexpr (DQO_FWD_PRIO == 3) {
+        const uint32_t q = blockIdx.x * 4u / gridDim.x;
+        if (q == 0u) __builtin_amdgcn_s_setprio(3);
+        else if (q == 1u) __builtin_amdgcn_s_setprio(2);
+        else if (q == 2u) __builtin_amdgcn_s_setprio(1);
+    }
     int tgt = -2;
     if (target && in_img) tgt = job_target(V.cam[view].job, target[view * HW + pix]);
     if (PROBS)
@@ -201,8 +231,10 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     // further ahead is loaded one step earlier still.
     T pf[kRecWords];
     uint32_t rec2 = 0u;
-    if (rs + tid < re) load_splat<T>(pf, splats + (size_t)min(pvals[rs + tid], M - 1) * kSplatWords);
-    if (rs + BLOCK + tid < re) rec2 = min(pvals[rs + BLOCK + tid], M - 1);
+    if (rs + tid < re) load_splat_global<T>(pf, splats + (size_t)min(pvals[rs + tid], M - 1) * kSplatWords);
+    // (the index is clamped where it is used: clamping it here would wait
+    // for the load, and with it for every load issued before)
+    if (rs + BLOCK + tid < re) rec2 = pvals[rs + BLOCK + tid];
     for (uint32_t b0 = rs; b0 < re; b0 += BLOCK) {
         if (__syncthreads_count(!done) == 0) break;
         if constexpr (BLOCK == kWave) {
@@ -242,8 +274,8 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
             store_splat_lds<T>(s_sp + (off + rank_below(bal)) * kRecWords, pf);
         }
         __syncthreads();
-        if (b0 + BLOCK + tid < re) load_splat<T>(pf, splats + (size_t)rec2 * kSplatWords);
-        if (b0 + 2 * BLOCK + tid < re) rec2 = min(pvals[b0 + 2 * BLOCK + tid], M - 1);
+        if (b0 + BLOCK + tid < re) load_splat_global<T>(pf, splats + (size_t)min(rec2, M - 1) * kSplatWords);
+        if (b0 + 2 * BLOCK + tid < re) rec2 = pvals[b0 + 2 * BLOCK + tid];
         if (!wave_any(!done)) continue;
         // Groups of fwd_group<T>() records: their contribution tests (quadratic
         // form, exponential, thresholds) are independent and evaluated side
@@ -650,15 +682,20 @@ __device__ __forceinline__ void backward_unit(
     const int64_t o = view * HW + pix;
     const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
 
+    // Batches of up to 64 pairs, from the walk's end down.  A listed
+    // segment knows where its walk ends, so the first batch's pair indices
+    // are loaded before the pixels' values, and its records (which need the
+    // indices) right after them; the pixel values are used only then.
+    auto batch_lo = [&](uint32_t e) { return (e - s0 > (uint32_t)kWave) ? e - kWave : s0; };
+    uint32_t rec_first = 0u;
+    if (seg_list && lane < (int)(hi_seg - batch_lo(hi_seg))) rec_first = pvals[batch_lo(hi_seg) + lane];
+
     int lastp = -1;
     T Tcur = T(1), gc0 = T(0), gc1 = T(0), gc2 = T(0), gd = T(0), gt = T(0), gpt = T(0);
-    int tgt = -2;
-    bool restart = false;
-    T S_restart = T(0);
+    int tgt = -2, tgt_raw = -1;
+    T ck[6] = {}, col0 = T(0), col1 = T(0), col2 = T(0), dep = T(0), ptg = T(0);
     if (inside) {
         lastp = last[o];
-        // nothing in this segment (whole tiles: nothing of this frame's)
-        if (lastp < (int)s0 || (!seg_list && lastp >= (int)s1)) lastp = -1;
         Tcur = tfinal[o];
         gc0 = dC[(view * 3 + 0) * HW + pix];
         gc1 = dC[(view * 3 + 1) * HW + pix];
@@ -666,22 +703,41 @@ __device__ __forceinline__ void backward_unit(
         gd = dD ? dD[o] : T(0);
         gt = dT ? dT[o] : T(0);
         if (dPt && target) {
-            tgt = job_target(V.cam[view].job, target[o]);
+            tgt_raw = target[o];
             gpt = dPt[o];
-            if (tgt == -1) gt += gpt;
         }
         if (bnd != kNoBoundary) {
             // Some pixels blend past this segment: they restart at its end
-            // from the state the forward stored there.  The sum behind the
-            // boundary is the total minus the part in front of it (colour
-            // without the background term, depth, target probability).  The
-            // loads are issued for every pixel, beside the ones above.
+            // from the state the forward stored there (loaded for every
+            // pixel, beside the values above).
             const T* c = ckpt + (size_t)min(bnd, ckpt_cap - 1u) * 6 * kWave + lane;
-            T ck[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q) ck[q] = c[q * kWave];
-            const T col0 = color[(view * 3 + 0) * HW + pix], col1 = color[(view * 3 + 1) * HW + pix],
-                    col2 = color[(view * 3 + 2) * HW + pix], dep = depth[o], ptg = ptarget ? ptarget[o] : T(0);
+            col0 = color[(view * 3 + 0) * HW + pix];
+            col1 = color[(view * 3 + 1) * HW + pix];
+            col2 = color[(view * 3 + 2) * HW + pix];
+            dep = depth[o];
+            ptg = ptarget ? ptarget[o] : T(0);
+        }
+    }
+    T pf[kRecWords];
+    uint32_t pf_slot = 0u;
+    if (seg_list && lane < (int)(hi_seg - batch_lo(hi_seg)))
+        pf_slot = load_splat_slot<T>(pf, splats + (size_t)min(rec_first, M - 1) * kSplatWords, tx, ty);
+
+    bool restart = false;
+    T S_restart = T(0);
+    if (inside) {
+        // nothing in this segment (whole tiles: nothing of this frame's)
+        if (lastp < (int)s0 || (!seg_list && lastp >= (int)s1)) lastp = -1;
+        if (dPt && target) {
+            tgt = job_target(V.cam[view].job, tgt_raw);
+            if (tgt == -1) gt += gpt;
+        }
+        if (bnd != kNoBoundary) {
+            // The sum behind the boundary is the total minus the part in front
+            // of it (colour without the background term, depth, target
+            // probability).
             if (lastp >= (int)s1) {
                 const T Tf = Tcur;
                 const T behind = gc0 * ((col0 - Tf * cs.bg[0]) - ck[1]) + gc1 * ((col1 - Tf * cs.bg[1]) - ck[2]) +
@@ -729,23 +785,20 @@ __device__ __forceinline__ void backward_unit(
     const T* sp = s_sp;
     T dx = T(0), dy = T(0), a = T(0), a_free = T(0), G_free = T(0);
 
-    // Batches of up to 64 pairs, from the walk's end down.  The first batch's
-    // records (A = [a_s, a_e)) are loaded here, beside the pixel loads.  With
-    // PREFETCH (whole tiles: many batches) the next batch's records are held
-    // in registers while the current one is walked, and the pair indices of
-    // the batch after it (B) are loaded one step earlier still; without it
-    // (segments: mostly one batch) later batches are loaded when reached, and
-    // the record registers are free during the walk.
-    auto batch_lo = [&](uint32_t e) { return (e - s0 > (uint32_t)kWave) ? e - kWave : s0; };
+    // The first batch is A = [a_s, a_e) (already loaded for a listed
+    // segment).  With PREFETCH (whole tiles: many batches) the next batch's
+    // records are held in registers while the current one is walked, and the
+    // pair indices of the batch after it (B) are loaded one step earlier
+    // still; without it (segments: mostly one batch) later batches are
+    // loaded when reached, and the record registers are free during the walk.
     uint32_t a_e = hi, a_s = batch_lo(hi);
-    T pf[kRecWords];
-    uint32_t pf_slot = 0u;
-    if (lane < (int)(a_e - a_s)) {
+    if (!seg_list && lane < (int)(a_e - a_s)) {
         const uint32_t rec = min(pvals[a_s + lane], M - 1);
         pf_slot = load_splat_slot<T>(pf, splats + (size_t)rec * kSplatWords, tx, ty);
     }
     uint32_t b_e = a_s, b_s = batch_lo(a_s), rec_b = 0u;
-    if constexpr (PREFETCH) rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
+    // (clamped where used, so that nothing waits for this load early)
+    if constexpr (PREFETCH) rec_b = (lane < (int)(b_e - b_s)) ? pvals[b_s + lane] : 0u;
     bool first_batch = true;
 
     // The record of the Gaussian being tested, read from LDS in one go (three
@@ -805,9 +858,9 @@ __device__ __forceinline__ void backward_unit(
                 b_s = batch_lo(a_s);
                 if constexpr (PREFETCH) {
                     if (lane < (int)(a_e - a_s)) {
-                        pf_slot = load_splat_slot<T>(pf, splats + (size_t)rec_b * kSplatWords, tx, ty);
+                        pf_slot = load_splat_slot<T>(pf, splats + (size_t)min(rec_b, M - 1) * kSplatWords, tx, ty);
                     }
-                    rec_b = (lane < (int)(b_e - b_s)) ? min(pvals[b_s + lane], M - 1) : 0u;
+                    rec_b = (lane < (int)(b_e - b_s)) ? pvals[b_s + lane] : 0u;
                 }
             }
             lds_rec(jl);
