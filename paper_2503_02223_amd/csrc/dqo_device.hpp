@@ -13,12 +13,12 @@ constexpr int kWave = 64;
 constexpr int kParams = DQO_NUM_PARAMS;
 // Splat record (one 64-byte line in FP32): mx,my,A,B,C,o,z,id,r,g,b,pad, then
 // the item's first pair slot, its tile rectangle's x0 | y0 << 16 and width,
-// pad.  The render kernels walk the first kRecWords (the pad word carries the
-// pair's position there).
+// pad.  The render kernels read the first kRecWords and build their walk
+// records from them.
 constexpr int kSplatWords = 16;
 constexpr int kRecWords = 12;
 constexpr int kSpSlot = 12, kSpRect = 13, kSpRectW = 14;
-constexpr int kGradWords = 10;    // dmx,dmy,dA,dB,dC,do,dr,dg,db,dz
+constexpr int kGradWords = 10;    // dmx,dmy,dA,dB,dC, o*do, dr,dg,db,dz
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;

@@ -576,7 +576,7 @@ __global__ __launch_bounds__(kSlotWaves * kWave) void slot_sum_kernel(const uint
 }
 
 // Chain rule of one (view, Gaussian) item from its pair-partial totals d
-// (mean2d, conic, opacity, colour, depth) to the 14 parameters (out) and to
+// (mean2d, conic, o dL/do, colour, depth) to the 14 parameters (out) and to
 // the camera-frame mean (dpc); false when the item is culled.
 template <typename T>
 __device__ __forceinline__ bool item_backward(const DevCam<T>& c, const Consts<T>& cs, const T (&p)[kParams],
@@ -679,7 +679,7 @@ __device__ __forceinline__ bool item_backward(const DevCam<T>& c, const Consts<T
     const T iq = T(1) / pr.qnorm;
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[6 + k] = (dq[k] - pr.qn[k] * dot) * iq;
-    out[10] = d[5] * pr.o * (T(1) - pr.o);
+    out[10] = d[5] * (T(1) - pr.o);  // d[5] = o dL/do, sigmoid opacity
     out[11] = d[6];
     out[12] = d[7];
     out[13] = d[8];

@@ -29,34 +29,96 @@ namespace dqo {
 template <typename T>
 __device__ __forceinline__ T fmadd(T a, T b, T c) { return fma(a, b, c); }
 
-// Mahalanobis form of the pixel sample against a splat record (shared by the
-// forward and the backward so that both take bitwise identical decisions).
-template <typename T>
-__device__ __forceinline__ T quad_form(const T* sp, T sx, T sy, T& dx, T& dy) {
-    dx = sx - sp[0];
-    dy = sy - sp[1];
-    return fmadd(sp[2] * dx, dx, fmadd(T(2) * sp[3] * dx, dy, sp[4] * dy * dy));
-}
-
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
-// The Gaussian falloff exp(-Q/2), one expression for the forward and the
-// backward so that both take bitwise identical decisions.
+// Walk records: what the render kernels keep in LDS for each pair of a batch,
+// the splat restated in the coordinates of the pair's tile.  With (du, dv) a
+// pixel centre's offset from the splat's mean, the pixel's alpha before the
+// clamp is 2^E with E = a du^2 + 2b du dv + c dv^2 + log2(o): the conic of
+// Eq. (12)'s Gaussian scaled by -log2(e)/2 and the opacity folded in.  A
+// pair contributes at a pixel exactly when E reaches the record's threshold,
+// max(log2 o - q_max log2(e)/2, log2 alpha_min), which is Q <= q_max and
+// alpha >= alpha_min at once.  Forward and backward evaluate E with the same
+// code from the same record, so both take the same decisions.
+//   [0, 1] mean relative to the tile's corner (mu, mv); [2, 3, 4] a, b, c;
+//   [5] log2 o; [6] threshold; [7] the pair's position; [8] depth; [9] object
+//   id; [10, 11, 12] colour; [13..15] unused.
+constexpr int kWalkWords = 16;
+enum WalkWord { kWMu = 0, kWMv = 1, kWA = 2, kWM = 3, kWC = 4, kWLop = 5, kWThr = 6, kWPos = 7, kWZ = 8,
+                kWId = 9, kWR = 10, kWG = 11, kWB = 12 };
 template <typename T>
-__device__ __forceinline__ T falloff(T Q) { return fast_exp<T>(T(-0.5) * Q); }
+__device__ __forceinline__ T neg_half_log2e() { return T(-0.72134752044448170368); }
 
-// The first kRecWords values of a splat record (what the render kernels
-// walk with) into registers, and from registers into LDS.
 template <typename T>
-__device__ __forceinline__ void load_splat(T (&r)[kRecWords], const T* src) {
+__device__ __forceinline__ T log2_of(T x);
+template <>
+__device__ __forceinline__ float log2_of<float>(float x) { return log2f(x); }
+template <>
+__device__ __forceinline__ double log2_of<double>(double x) { return log2(x); }
+template <typename T>
+__device__ __forceinline__ T exp2_of(T x);
+template <>
+__device__ __forceinline__ float exp2_of<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <>
+__device__ __forceinline__ double exp2_of<double>(double x) { return exp2(x); }
+
+// Walk record of splat record r (mx, my, A, B, C, o, z, id, r, g, b) for the
+// tile whose first pixel's corner is (ox, oy), stored at dst (LDS).
+template <typename T>
+__device__ __forceinline__ void store_walk_record(T* dst, const T (&r)[kRecWords], T ox, T oy, int pos,
+                                                  const Consts<T>& cs) {
+    const T kq = neg_half_log2e<T>();
+    const T lop = log2_of<T>(r[5]);
+    T w[kWalkWords];
+    w[kWMu] = r[0] - ox;
+    w[kWMv] = r[1] - oy;
+    w[kWA] = kq * r[2];
+    w[kWM] = kq * r[3];
+    w[kWC] = kq * r[4];
+    w[kWLop] = lop;
+    w[kWThr] = max(fmadd(kq, cs.q_max, lop), log2_of<T>(cs.alpha_min));
+    w[kWPos] = id_to_word<T>(pos);
+    w[kWZ] = r[6];
+    w[kWId] = r[7];
+    w[kWR] = r[8];
+    w[kWG] = r[9];
+    w[kWB] = r[10];
+    w[13] = w[14] = w[15] = T(0);
+    if constexpr (sizeof(T) == 4) {
+        float4* d4 = reinterpret_cast<float4*>(dst);
 #pragma unroll
-    for (int k = 0; k < kRecWords; ++k) r[k] = src[k];
+        for (int q = 0; q < 4; ++q) d4[q] = make_float4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kWalkWords; ++k) dst[k] = w[k];
+    }
 }
-// FP32 records from global memory: the pad value (word 11) is not loaded.
-// Every user overwrites it with the pair's position, and a load into a
-// register the compiler counts as free makes the next write of that register
-// wait for the load, and with it for every load before.
-__device__ __forceinline__ void load_words_0_10(float (&r)[kRecWords], const float* src) {
+
+// The exponent E at the pixel centre (u, v) of the tile (offsets from its
+// corner), as du p + dv r + log2 o with (du, dv) its offset from the mean and
+// (p, r) = (a du + b dv, b du + c dv), the scaled conic times (du, dv): half
+// the gradient of E with respect to (du, dv), which the backward reuses.
+template <typename T>
+__device__ __forceinline__ T walk_exponent(const T* w, T u, T v, T& du, T& dv, T& p, T& r) {
+    du = u - w[kWMu];
+    dv = v - w[kWMv];
+    p = fmadd(w[kWA], du, w[kWM] * dv);
+    r = fmadd(w[kWC], dv, w[kWM] * du);
+    return fmadd(du, p, fmadd(dv, r, w[kWLop]));
+}
+
+// The first kRecWords values of a splat record from global memory into
+// registers; the pad value (word 11) is not loaded (set to zero).  Loading it
+// into a register the compiler counts as free would make the next write of
+// that register wait for the load, and with it for every load before.
+template <typename T>
+__device__ __forceinline__ void load_splat_global(T (&r)[kRecWords], const T* src) {
+#pragma unroll
+    for (int k = 0; k < kRecWords - 1; ++k) r[k] = src[k];
+    r[kRecWords - 1] = T(0);
+}
+template <>
+__device__ __forceinline__ void load_splat_global<float>(float (&r)[kRecWords], const float* src) {
     const float4* s4 = reinterpret_cast<const float4*>(src);
     const float4 a = s4[0], b = s4[1];
     const float3 c = *reinterpret_cast<const float3*>(src + 8);
@@ -64,27 +126,6 @@ __device__ __forceinline__ void load_words_0_10(float (&r)[kRecWords], const flo
     r[4] = b.x; r[5] = b.y; r[6] = b.z; r[7] = b.w;
     r[8] = c.x; r[9] = c.y; r[10] = c.z;
     r[11] = 0.0f;
-}
-template <>
-__device__ __forceinline__ void load_splat<float>(float (&r)[kRecWords], const float* src) {
-    const float4* s4 = reinterpret_cast<const float4*>(src);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const float4 a = s4[q];
-        r[4 * q] = a.x;
-        r[4 * q + 1] = a.y;
-        r[4 * q + 2] = a.z;
-        r[4 * q + 3] = a.w;
-    }
-}
-// A record from global memory, whose pad value (word 11) the caller replaces.
-template <typename T>
-__device__ __forceinline__ void load_splat_global(T (&r)[kRecWords], const T* src) {
-    load_splat<T>(r, src);
-}
-template <>
-__device__ __forceinline__ void load_splat_global<float>(float (&r)[kRecWords], const float* src) {
-    load_words_0_10(r, src);
 }
 // The walked values of a splat record and the slot of its (tile tx, ty) pair:
 // the item's first slot plus the tile's place in its rectangle, row-major
@@ -99,21 +140,10 @@ __device__ __forceinline__ uint32_t load_splat_slot(T (&r)[kRecWords], const T* 
 }
 template <>
 __device__ __forceinline__ uint32_t load_splat_slot<float>(float (&r)[kRecWords], const float* src, int tx, int ty) {
-    load_words_0_10(r, src);
+    load_splat_global<float>(r, src);
     const float3 t = *reinterpret_cast<const float3*>(src + kSpSlot);  // the pad after them is not loaded either
     const uint32_t base = __float_as_uint(t.x), xy = __float_as_uint(t.y), w = __float_as_uint(t.z);
     return base + (uint32_t)(ty - (int)(xy >> 16)) * w + (uint32_t)(tx - (int)(xy & 0xFFFFu));
-}
-template <typename T>
-__device__ __forceinline__ void store_splat_lds(T* dst, const T (&r)[kRecWords]) {
-#pragma unroll
-    for (int k = 0; k < kRecWords; ++k) dst[k] = r[k];
-}
-template <>
-__device__ __forceinline__ void store_splat_lds<float>(float* dst, const float (&r)[kRecWords]) {
-    float4* d4 = reinterpret_cast<float4*>(dst);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) d4[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
 }
 
 // Whether a splat can contribute at any rendered pixel centre of a tile,
@@ -181,7 +211,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     int32_t* __restrict__ tile_last) {
     constexpr int BLOCK = TW * TH;
     constexpr int NW = BLOCK / kWave;
-    __shared__ __align__(16) T s_sp[BLOCK * kRecWords];
+    __shared__ __align__(16) T s_sp[BLOCK * kWalkWords];
     __shared__ int s_wc[NW];
     extern __shared__ unsigned char s_dyn[];
     T* s_P = reinterpret_cast<T*>(s_dyn);  // [K][BLOCK] when PROBS
@@ -197,7 +227,9 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     const bool inside = in_img && in_window(V.cam[view], px, py);
     const int64_t HW = (int64_t)V.W * V.H;
     const int64_t pix = (int64_t)py * V.W + px;
-    const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
+    // the pixel centre relative to the tile's corner
+    const T u = T(tid % TW) + T(0.5), v = T(tid / TW) + T(0.5);
+    const T ox = T(tx * TW), oy = T(ty * TH);
     const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
 #ifndef DQO_FWD_PRIO
 #define DQO_FWD_PRIO 0
@@ -270,57 +302,72 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
             }
         }
         if (cand) {
-            pf[kRecWords - 1] = id_to_word<T>((int)(b0 + tid));
-            store_splat_lds<T>(s_sp + (off + rank_below(bal)) * kRecWords, pf);
+            store_walk_record<T>(s_sp + (off + rank_below(bal)) * kWalkWords, pf, ox, oy, (int)(b0 + tid), cs);
         }
         __syncthreads();
         if (b0 + BLOCK + tid < re) load_splat_global<T>(pf, splats + (size_t)min(rec2, M - 1) * kSplatWords);
         if (b0 + 2 * BLOCK + tid < re) rec2 = pvals[b0 + 2 * BLOCK + tid];
         if (!wave_any(!done)) continue;
-        // Groups of fwd_group<T>() records: their contribution tests (quadratic
-        // form, exponential, thresholds) are independent and evaluated side
+        // Groups of fwd_group<T>() records: their contribution tests (exponent,
+        // exponential, threshold) are independent and evaluated side
         // by side, which hides the VALU and LDS latency that one wavefront
         // per SIMD would otherwise expose; only the transmittance recurrence
         // then runs serially, in depth order, with the same arithmetic as a
         // one-by-one walk.
         constexpr int kFwdGroup = fwd_group<T>();
         for (int j0 = 0; j0 < nb; j0 += kFwdGroup) {
-            T rec[kFwdGroup][kRecWords];
+            // the test words (and positions) of the group first; the blending
+            // words are read only where the group has a contribution
+            T rec[kFwdGroup][kWPos + 1];
             T a0[kFwdGroup];
             bool c0k[kFwdGroup];
             bool any = false;
 #pragma unroll
             for (int k = 0; k < kFwdGroup; ++k) {
-                const int j = min(j0 + k, nb - 1);
-                load_splat<T>(rec[k], s_sp + j * kRecWords);
+                const T* w = s_sp + min(j0 + k, nb - 1) * kWalkWords;
+#pragma unroll
+                for (int q = 0; q <= kWPos; ++q) rec[k][q] = w[q];
             }
 #pragma unroll
             for (int k = 0; k < kFwdGroup; ++k) {
-                T dx, dy;
-                const T Q = quad_form(rec[k], sx, sy, dx, dy);
-                a0[k] = min(rec[k][5] * falloff<T>(Q), cs.alpha_max);
-                c0k[k] = (j0 + k < nb) && (Q <= cs.q_max) && (a0[k] >= cs.alpha_min);
+                T dx, dy, pp, rr;
+                const T E = walk_exponent(rec[k], u, v, dx, dy, pp, rr);
+                a0[k] = min(exp2_of<T>(E), cs.alpha_max);
+                c0k[k] = (j0 + k < nb) && (E >= rec[k][kWThr]);
                 any = any || c0k[k];
             }
             if (!wave_any(any && !done)) continue;
+            T bl[kFwdGroup][kWB - kWZ + 1];  // depth, id, colour of each record
 #pragma unroll
             for (int k = 0; k < kFwdGroup; ++k) {
+                const T* w = s_sp + min(j0 + k, nb - 1) * kWalkWords;
+#pragma unroll
+                for (int q = kWZ; q <= kWB; ++q) bl[k][q - kWZ] = w[q];
+            }
+            // (taken as written here: the reads are issued together and
+            // waited for once, not one record at a time inside the recurrence)
+#pragma unroll
+            for (int k = 0; k < kFwdGroup; ++k)
+#pragma unroll
+                for (int q = 0; q <= kWB - kWZ; ++q) asm volatile("" : "+v"(bl[k][q]));
+#pragma unroll
+            for (int k = 0; k < kFwdGroup; ++k) {
+                const T* bw = bl[k] - kWZ;
                 const bool contrib = c0k[k] && !done;
                 const T a = contrib ? a0[k] : T(0);
                 const T Tn = Tt * (T(1) - a);
                 const bool stop = contrib && (Tn < cs.t_min);
                 const T w = stop ? T(0) : a * Tt;
-                c0 = fmadd(w, rec[k][8], c0);
-                c1 = fmadd(w, rec[k][9], c1);
-                c2 = fmadd(w, rec[k][10], c2);
-                dd = fmadd(w, rec[k][6], dd);
-                const int id = word_to_id<T>(rec[k][7]);
+                c0 = fmadd(w, bw[kWR], c0);
+                c1 = fmadd(w, bw[kWG], c1);
+                c2 = fmadd(w, bw[kWB], c2);
+                dd = fmadd(w, bw[kWZ], dd);
+                const int id = word_to_id<T>(bw[kWId]);
                 pt += (id == tgt) ? w : T(0);
-                if (w != T(0)) {
-                    lastpos = word_to_id<T>(rec[k][kRecWords - 1]);
-                    ++nb_count;
-                    if (PROBS && id >= 0 && id < K) s_P[id * BLOCK + tid] += w;
-                }
+                const bool blended = w != T(0);
+                lastpos = blended ? word_to_id<T>(rec[k][kWPos]) : lastpos;
+                nb_count += blended ? 1 : 0;
+                if (PROBS && blended && id >= 0 && id < K) s_P[id * BLOCK + tid] += w;
                 Tt = stop ? Tt : Tn;
                 done = done || stop;
             }
@@ -440,7 +487,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     const T* __restrict__ dPt, T* __restrict__ partials, uint8_t* __restrict__ written, uint32_t cap, uint32_t M) {
     constexpr int BLOCK = TW * TH;
     constexpr int NW = BLOCK / kWave;
-    __shared__ __align__(16) T s_sp[BLOCK * kRecWords];
+    __shared__ __align__(16) T s_sp[BLOCK * kWalkWords];
     __shared__ uint32_t s_slot[BLOCK];
     __shared__ T s_red[2][NW][kWave];
     __shared__ int s_maxlast;
@@ -458,7 +505,9 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     const int64_t HW = (int64_t)V.W * V.H;
     const int64_t pix = (int64_t)py * V.W + px;
     const int64_t o = view * HW + pix;
-    const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
+    // the pixel centre relative to the tile's corner
+    const T u = T(tid % TW) + T(0.5), v_px = T(tid / TW) + T(0.5);
+    const T ox = T(tx * TW), oy = T(ty * TH);
     const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
 
     int lastp = -1;
@@ -516,8 +565,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
         }
         if (cand) {
             const int q = off + rank_below(bal);
-            r[kRecWords - 1] = id_to_word<T>((int)(bstart + tid));
-            store_splat_lds<T>(s_sp + q * kRecWords, r);
+            store_walk_record<T>(s_sp + q * kWalkWords, r, ox, oy, (int)(bstart + tid), cs);
             s_slot[q] = slot;
         }
         __syncthreads();
@@ -530,24 +578,21 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
             for (int c = 0; c < kChunk; ++c) {
                 const int jl = c0 - c;
                 if (jl < 0) break;
-                const T* sp = s_sp + jl * kRecWords;
-                T dx, dy;
-                const T Q = quad_form(sp, sx, sy, dx, dy);
-                const bool in = (Q <= cs.q_max) && (word_to_id<T>(sp[kRecWords - 1]) <= lastp);
-                if (!wave_any(in)) continue;
-                const T G = falloff<T>(Q);
-                const T araw = sp[5] * G;
+                const T* sp = s_sp + jl * kWalkWords;
+                T dx, dy, pp, rr;
+                const T E = walk_exponent(sp, u, v_px, dx, dy, pp, rr);
+                const bool contrib = (E >= sp[kWThr]) && (word_to_id<T>(sp[kWPos]) <= lastp);
+                if (!wave_any(contrib)) continue;
+                const T araw = exp2_of<T>(E);
                 const bool clamped = !(araw < cs.alpha_max);
                 const T a0 = clamped ? cs.alpha_max : araw;
-                const bool contrib = in && (a0 >= cs.alpha_min);
-                if (!wave_any(contrib)) continue;
                 any = true;
                 const T a = contrib ? a0 : T(0);
                 const T roma = fast_rcp<T>(T(1) - a);
                 const T Ti = Tcur * roma;
                 const T w = a * Ti;
-                const int id = word_to_id<T>(sp[7]);
-                T vv = fmadd(gc0, sp[8], fmadd(gc1, sp[9], fmadd(gc2, sp[10], gd * sp[6])));
+                const int id = word_to_id<T>(sp[kWId]);
+                T vv = fmadd(gc0, sp[kWR], fmadd(gc1, sp[kWG], fmadd(gc2, sp[kWB], gd * sp[kWZ])));
                 vv += (tgt >= 0 && id == tgt) ? gpt : T(0);
                 if (dP && contrib && id >= 0 && id < K) vv += dP[((int64_t)view * K + id) * HW + pix];
                 const T dalpha = contrib ? (Ti * vv - S * roma) : T(0);
@@ -557,13 +602,15 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
                 v[c * kGradWords + 7] = gc1 * w;
                 v[c * kGradWords + 8] = gc2 * w;
                 v[c * kGradWords + 9] = gd * w;
-                const T dQ = clamped ? T(0) : dalpha * (T(-0.5) * a);
-                v[c * kGradWords + 5] = clamped ? T(0) : dalpha * G;
-                v[c * kGradWords + 0] = dQ * (T(-2) * (sp[2] * dx + sp[3] * dy));
-                v[c * kGradWords + 1] = dQ * (T(-2) * (sp[3] * dx + sp[4] * dy));
-                v[c * kGradWords + 2] = dQ * dx * dx;
-                v[c * kGradWords + 3] = dQ * T(2) * dx * dy;
-                v[c * kGradWords + 4] = dQ * dy * dy;
+                // dq = -2 dL/dQ; the conic rows from the exponent's (p, r)
+                const T dq = clamped ? T(0) : dalpha * a;
+                const T iq = T(1) / neg_half_log2e<T>();
+                v[c * kGradWords + 5] = dq;  // o dL/do (the opacity's sum is divided by o)
+                v[c * kGradWords + 0] = dq * iq * pp;
+                v[c * kGradWords + 1] = dq * iq * rr;
+                v[c * kGradWords + 2] = T(-0.5) * dq * dx * dx;
+                v[c * kGradWords + 3] = -dq * dx * dy;
+                v[c * kGradWords + 4] = T(-0.5) * dq * dy * dy;
             }
             if (wave_any(any)) wave_transpose_sum<T>(v, lane);
             if constexpr (NW == 1) {
@@ -614,7 +661,7 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
 // ten values of its slot, so nothing is cleared between chunks: the values
 // past the NS filled slots are set to zero here, as constants.
 template <int NS, typename T>
-__device__ __forceinline__ void flush_slots(T (&v)[64], const uint32_t (&chunk)[kChunk], T* __restrict__ partials,
+__device__ __forceinline__ void flush_slots(T (&v)[64], uint32_t chunk, T* __restrict__ partials,
                                             uint8_t* __restrict__ written, uint32_t cap) {
     // The lane's place in the transposed sums, derived here at each flush (an
     // opaque copy of the lane index keeps the compiler from hoisting it out
@@ -626,12 +673,11 @@ __device__ __forceinline__ void flush_slots(T (&v)[64], const uint32_t (&chunk)[
 #pragma unroll
     for (int k = NS * kGradWords; k < 64; ++k) v[k] = T(0);
     wave_transpose_sum<T>(v, lane);
+    const uint32_t slot = (uint32_t)__shfl((int)chunk, lane_slot);
     if (lane < NS * kGradWords) {
-        uint32_t slot = chunk[0];
-#pragma unroll
-        for (int c = 1; c < NS; ++c) slot = (lane_slot == c) ? chunk[c] : slot;
         if (slot < cap) {
-            const T factor = (word == 2 || word == 4) ? T(-0.5) : (word == 3) ? T(-1) : T(1);
+            const T factor = (word <= 1) ? T(1) / neg_half_log2e<T>()
+                             : (word == 2 || word == 4) ? T(-0.5) : (word == 3) ? T(-1) : T(1);
             partials[(size_t)slot * kGradWords + word] = v[0] * factor;
             if (word == 0) written[slot] = 1;
         }
@@ -680,7 +726,9 @@ __device__ __forceinline__ void backward_unit(
     const int64_t HW = (int64_t)V.W * V.H;
     const int64_t pix = (int64_t)py * V.W + px;
     const int64_t o = view * HW + pix;
-    const T sx = T(px) + T(0.5), sy = T(py) + T(0.5);
+    // the pixel centre relative to the tile's corner
+    const T u = T(lane % TW) + T(0.5), v_px = T(lane / TW) + T(0.5);
+    const T ox = T(tx * TW), oy = T(ty * TH);
 
     // Batches of up to 64 pairs, from the walk's end down.  A listed
     // segment knows where its walk ends, so the first batch's pair indices
@@ -769,7 +817,7 @@ __device__ __forceinline__ void backward_unit(
     T v[64];
 #pragma unroll
     for (int k = 0; k < 64; ++k) v[k] = T(0);
-    uint32_t chunk[kChunk] = {};              // pair slot of the Gaussian in each reduction slot
+    uint32_t chunk = 0u;  // lane c < kChunk: the pair slot of the Gaussian in reduction slot c
     // the target-probability gradient joins a Gaussian's colour sum where its
     // object is the pixel's target (tgt -1: T_final's gradient carries it)
     const T gpt_obj = tgt >= 0 ? gpt : T(0);
@@ -780,10 +828,10 @@ __device__ __forceinline__ void backward_unit(
     uint32_t bend = hi, bstart = hi;
     int jl = -1;
     // contribution state of the Gaussian found by `next`, zero in the lanes
-    // it does not blend: alpha, alpha where it is not clamped (the factor of
-    // alpha's derivatives), the falloff where not clamped
+    // it does not blend: alpha, and alpha where it is not clamped (the factor
+    // of alpha's derivatives)
     const T* sp = s_sp;
-    T dx = T(0), dy = T(0), a = T(0), a_free = T(0), G_free = T(0);
+    T dx = T(0), dy = T(0), a = T(0), a_free = T(0), pp = T(0), rr = T(0);
 
     // The first batch is A = [a_s, a_e) (already loaded for a listed
     // segment).  With PREFETCH (whole tiles: many batches) the next batch's
@@ -801,15 +849,16 @@ __device__ __forceinline__ void backward_unit(
     if constexpr (PREFETCH) rec_b = (lane < (int)(b_e - b_s)) ? pvals[b_s + lane] : 0u;
     bool first_batch = true;
 
-    // The record of the Gaussian being tested, read from LDS in one go (three
-    // 16-byte broadcast reads at a 24-bit multiply of its index).
-    T cur[kRecWords];
+    // The walk record of the Gaussian being tested, read from LDS (16-byte
+    // broadcast reads at a 24-bit multiply of its index; the compiler issues
+    // each where its values are first used).
+    T cur[kWPos + 1];
     auto lds_rec = [&](int j) {
         if constexpr (sizeof(T) == 4) {
             const float4* s4 = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(s_sp) +
-                                                               __mul24(j, (int)(kRecWords * sizeof(T))));
+                                                               __mul24(j, (int)(kWalkWords * sizeof(T))));
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
+            for (int q = 0; q < 2; ++q) {
                 const float4 a = s4[q];
                 cur[4 * q] = a.x;
                 cur[4 * q + 1] = a.y;
@@ -818,7 +867,7 @@ __device__ __forceinline__ void backward_unit(
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < kRecWords; ++k) cur[k] = s_sp[j * kRecWords + k];
+            for (int k = 0; k <= kWPos; ++k) cur[k] = s_sp[j * kWalkWords + k];
         }
     };
     // Advances to the next Gaussian (descending) that contributes at some pixel
@@ -846,8 +895,7 @@ __device__ __forceinline__ void backward_unit(
                 const uint64_t bal = __builtin_amdgcn_ballot_w64(cand);
                 if (cand) {
                     const int q = rank_below(bal);
-                    pf[kRecWords - 1] = id_to_word<T>((int)(bstart + lane));
-                    store_splat_lds<T>(s_sp + q * kRecWords, pf);
+                    store_walk_record<T>(s_sp + q * kWalkWords, pf, ox, oy, (int)(bstart + lane), cs);
                     s_slot[q] = pf_slot;
                 }
                 __syncthreads();
@@ -862,36 +910,35 @@ __device__ __forceinline__ void backward_unit(
                     }
                     rec_b = (lane < (int)(b_e - b_s)) ? pvals[b_s + lane] : 0u;
                 }
+                if (jl < 0) continue;  // nothing in this batch can contribute
             }
             lds_rec(jl);
             sp = cur;
-            const T Q = quad_form(sp, sx, sy, dx, dy);
-            const T G = falloff<T>(Q);
-            const T araw = sp[5] * G;
+            const T E = walk_exponent(sp, u, v_px, dx, dy, pp, rr);
+            const T araw = exp2_of<T>(E);
             const bool clamped = !(araw < cs.alpha_max);
             const T a0 = clamped ? cs.alpha_max : araw;  // min(araw, alpha_max), one select
-            const bool contrib =
-                (Q <= cs.q_max) & (word_to_id<T>(sp[kRecWords - 1]) <= lastp) & (a0 >= cs.alpha_min);
+            const bool contrib = (E >= sp[kWThr]) & (word_to_id<T>(sp[kWPos]) <= lastp);
             a = contrib ? a0 : T(0);
             if (__builtin_amdgcn_ballot_w64(a != T(0)) == 0ull) {
                 --jl;
                 continue;
             }
             a_free = clamped ? T(0) : a;
-            G_free = (a_free != T(0)) ? G : T(0);
             return true;
         }
     };
     // Gradient of the found Gaussian into slot C; advances the walk.
     // In the lanes the Gaussian does not blend, a = 0 leaves T and S as they
-    // are and zeroes every word (w = 0, a_free = G_free = 0).
+    // are and zeroes every word (w = 0, a_free = 0).
     auto take = [&](auto cidx) {
         constexpr int C = decltype(cidx)::value;
         const T roma = fast_rcp<T>(T(1) - a);
         const T Ti = Tcur * roma;
         const T w = a * Ti;
-        const int id = word_to_id<T>(sp[7]);
-        T vv = fmadd(gc0, sp[8], fmadd(gc1, sp[9], fmadd(gc2, sp[10], gd * sp[6])));
+        const T* bw = s_sp + jl * kWalkWords;  // the blending words
+        const int id = word_to_id<T>(bw[kWId]);
+        T vv = fmadd(gc0, bw[kWR], fmadd(gc1, bw[kWG], fmadd(gc2, bw[kWB], gd * bw[kWZ])));
         vv += (id == tgt) ? gpt_obj : T(0);
         if constexpr (PROBS) {
             if (a != T(0) && id >= 0 && id < K) vv += dP[((int64_t)view * K + id) * HW + pix];
@@ -899,21 +946,23 @@ __device__ __forceinline__ void backward_unit(
         const T dalpha = fmadd(Ti, vv, -(S * roma));
         S = fmadd(w, vv, S);
         Tcur = Ti;
-        // dQ' = -2 dL/dQ: the mean words are dQ' (conic row . d), the conic
-        // words dQ' dx^2, dQ' dx dy, dQ' dy^2 before their factors
+        // dq = -2 dL/dQ: the mean words are dq (p, r) (the scaled conic
+        // times the offset), the conic words dq dx^2, dq dx dy, dq dy^2, each
+        // before its constant factor; the opacity word is dq = o dL/do
         const T dq = dalpha * a_free;
         const T t1 = dq * dx, t2 = dq * dy;
-        v[C * kGradWords + 0] = fmadd(sp[2], t1, sp[3] * t2);
-        v[C * kGradWords + 1] = fmadd(sp[3], t1, sp[4] * t2);
+        v[C * kGradWords + 0] = dq * pp;
+        v[C * kGradWords + 1] = dq * rr;
         v[C * kGradWords + 2] = t1 * dx;
         v[C * kGradWords + 3] = t1 * dy;
         v[C * kGradWords + 4] = t2 * dy;
-        v[C * kGradWords + 5] = dalpha * G_free;
+        v[C * kGradWords + 5] = dq;
         v[C * kGradWords + 6] = gc0 * w;
         v[C * kGradWords + 7] = gc1 * w;
         v[C * kGradWords + 8] = gc2 * w;
         v[C * kGradWords + 9] = gd * w;
-        chunk[C] = s_slot[jl];
+        const uint32_t pslot = s_slot[jl];
+        chunk = (lane == C) ? pslot : chunk;
         --jl;
     };
     // Six slots: four and five (fewer registers, five waves per SIMD with
@@ -957,7 +1006,7 @@ __global__ __launch_bounds__(kWave, 4) void render_backward_wave_kernel(
     const uint4* __restrict__ seg_list, const T* __restrict__ ckpt, uint32_t ckpt_cap, const T* __restrict__ color,
     const T* __restrict__ depth, const T* __restrict__ ptarget, const Ctrl* __restrict__ ctrl) {
     static_assert(TW * TH == kWave, "one wavefront per tile");
-    __shared__ __align__(16) T s_sp[kWave * kRecWords];
+    __shared__ __align__(16) T s_sp[kWave * kWalkWords];
     __shared__ uint32_t s_slot[kWave];
 
     const int lane = threadIdx.x;

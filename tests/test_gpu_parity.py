@@ -158,6 +158,52 @@ def test_render_backward_parity(oracle, seed, tile):
     close(g.cpu().numpy(), go, GRAD_RTOL, what="param grads")
 
 
+
+@pytest.mark.parametrize("probs", [True, False])
+def test_backward_past_batches_that_cannot_contribute(oracle, probs):
+    """A veil of faint Gaussians (opacity below alpha_min: they never blend)
+    in front of an opaque background: every tile's pair range opens with more
+    than 128 of them, so the backward meets whole 64-pair batches (and, on the
+    segmented path, whole segments) in which no record can contribute, and
+    walks past them.  Whole tiles with instance channels (probs) and the
+    segmented path without them, against the oracle's adjoint."""
+    rng = np.random.default_rng(5)
+    nb, nf = 80, 400
+    mu = np.concatenate([np.stack([rng.uniform(-1.6, 1.6, nb), rng.uniform(-1.6, 1.6, nb), rng.uniform(3.8, 4.2, nb)]),
+                         np.stack([rng.uniform(-0.9, 0.9, nf), rng.uniform(-0.9, 0.9, nf), rng.uniform(1.9, 2.1, nf)])],
+                        axis=1)
+    ls = np.concatenate([rng.normal(-1.8, 0.2, (3, nb)), rng.normal(-1.5, 0.1, (3, nf))], axis=1)
+    q = rng.normal(size=(4, nb + nf))
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    eta = np.concatenate([rng.normal(1.0, 0.5, nb), np.full(nf, -9.0)])
+    rgb = rng.uniform(0, 1, (3, nb + nf))
+    ids = rng.integers(0, 3, nb + nf).astype(np.int32)
+    cam = scenes.camera(fx=40.0, fy=40.0, cx=16.0, cy=16.0, width=32, height=32)
+    sc = dict(params=scenes.pack(mu, ls, q, eta, rgb), ids=ids, cams=[cam], K=3)
+    H, W, K = 32, 32, 3
+    r, p, ids_d = _frame(sc, ctx=B.Context(tile_w=8, tile_h=8))
+    img = r.forward(p, ids_d, probs=probs)
+    ref = _oracle_fwd(oracle, sc)
+    keep = unambiguous(ref, grads=True)
+    up = _sparse_upstream(77, ref, H, W, K, keep)
+    grads = dict(d_color=to_dev(up["gC"][None]), d_depth=to_dev(up["gD"][None]), d_t_final=to_dev(up["gT"][None]))
+    if probs:
+        grads["d_probs"] = to_dev(up["gP"][None])
+    else:
+        up["gP"] = None
+    g = r.backward(p, img, grads)
+    torch.cuda.synchronize()
+    # the case arises: tiles whose range opens with >= 128 faint pairs while
+    # some pixel blends a background Gaussian behind them
+    rng_t = r.frame.buf("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
+    vals = r.frame.buf("pair_vals", torch.int32).cpu().numpy()
+    last = img["last"][0].cpu().numpy().reshape(H // 8, 8, W // 8, 8).transpose(0, 2, 1, 3).reshape(-1, 64)
+    lead = np.array([np.argmax(np.append(vals[s:e], 0) < nb) for s, e in rng_t])
+    assert ((lead >= 128) & (last.max(1) >= rng_t[:, 0] + lead)).sum() >= 4
+    go, _ = oracle.render_backward(sc["params"], sc["ids"], cam, K=K, **up)
+    assert np.abs(go[:, nb:]).max() == 0.0
+    close(g.cpu().numpy(), go, GRAD_RTOL, what="param grads")
+
 def test_reproducible_bitwise():
     sc = scenes.single_view_scene(seed=7, n=2000)
     res = []
