@@ -154,7 +154,9 @@ enum dqo_buf {
     DQO_BUF_DEPTH_KEYS,  /* [V*n] uint32 sorted depth keys (float bits of z; culled = 0xffffffff) */
     DQO_BUF_DEPTH_ORDER, /* [V*n] uint32 item index (view*n + g) in depth order (GLOBAL depth order only) */
     DQO_BUF_PAIR_KEYS,   /* [cap] uint32 sorted global tile id (view*tiles + tile) */
-    DQO_BUF_PAIR_VALS,   /* [cap] uint32 item index, in (tile, depth, index) order */
+    DQO_BUF_PAIR_VALS,   /* [cap] uint32 item index, in (tile, depth, index) order; after a render
+                            forward, bit 31 is set on the pairs whose Gaussian cannot contribute at
+                            any pixel of their tile (the render backward skips them) */
     DQO_BUF_RANGES,      /* [V*tiles][2] uint32 [start, end) of each tile in the sorted pairs */
     DQO_BUF_PARTIALS,    /* [cap][10] per-pair gradient partials (render backward; valid only for the pairs
                             it marks written, the others are left as they were and count as zero) */
@@ -274,7 +276,9 @@ int dqo_sort(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* c
  * o_i exp(-Q_i/2)) >= alpha_min; w_i = alpha_i T_i; blending stops before a
  * Gaussian that would take T below t_min.  P_k = sum of w_i over Gaussians with
  * id k, so sum_k P_k + T_final = 1.  Needs dqo_project_cull_bin and dqo_sort
- * on the same state.  probs requires K >= 1. */
+ * on the same state.  probs requires K >= 1.  Also marks, in the pair list
+ * (DQO_BUF_PAIR_VALS bit 31), the pairs whose Gaussian cannot contribute at
+ * any pixel of their tile; marking is idempotent and changes no result. */
 int dqo_render_forward(const dqo_ctx* ctx, const dqo_frame_desc* desc, const dqo_camera* cams,
                        const void* state, const dqo_images* img, void* stream);
 

@@ -203,7 +203,7 @@ constexpr int fwd_group() { return (sizeof(T) == 8 && DQO_FWD_GROUP > 4) ? 4 : D
 
 template <typename T, int TW, int TH, bool PROBS>
 __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
-    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, const uint32_t* __restrict__ pvals,
+    Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, uint32_t* __restrict__ pvals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule, T* __restrict__ color, T* __restrict__ depth, T* __restrict__ tfinal,
     int32_t* __restrict__ last, T* __restrict__ probs, int32_t* __restrict__ idmap,
     const int32_t* __restrict__ target, T* __restrict__ ptarget, int32_t* __restrict__ nblend, uint32_t cap,
@@ -262,10 +262,10 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     // registers while the current batch is walked; the pair index one batch
     // further ahead is loaded one step earlier still.
     T pf[kRecWords];
-    uint32_t rec2 = 0u;
-    if (rs + tid < re) load_splat_global<T>(pf, splats + (size_t)min(pvals[rs + tid], M - 1) * kSplatWords);
-    // (the index is clamped where it is used: clamping it here would wait
-    // for the load, and with it for every load issued before)
+    uint32_t pv = (rs + tid < re) ? pvals[rs + tid] : 0u, rec2 = 0u;
+    if (rs + tid < re) load_splat_global<T>(pf, splats + (size_t)min(pv & kPairItem, M - 1) * kSplatWords);
+    // (the index is masked and clamped where it is used: doing it here would
+    // wait for the load, and with it for every load issued before)
     if (rs + BLOCK + tid < re) rec2 = pvals[rs + BLOCK + tid];
     for (uint32_t b0 = rs; b0 < re; b0 += BLOCK) {
         if (__syncthreads_count(!done) == 0) break;
@@ -289,6 +289,8 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
         // The batch's records that may contribute somewhere in the tile, in
         // order, compacted into LDS with their positions in the pad word.
         const bool cand = (b0 + tid < re) && tile_may_contribute<T>(pf, bx0, bx1, by0, by1, cs);
+        // the others are marked for the backward, which then skips them
+        if (b0 + tid < re && !cand && !(pv & kPairSkip)) pvals[b0 + tid] = pv | kPairSkip;
         const uint64_t bal = __ballot(cand);
         int nb = __popcll(bal), off = 0;
         if constexpr (NW > 1) {
@@ -305,7 +307,8 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
             store_walk_record<T>(s_sp + (off + rank_below(bal)) * kWalkWords, pf, ox, oy, (int)(b0 + tid), cs);
         }
         __syncthreads();
-        if (b0 + BLOCK + tid < re) load_splat_global<T>(pf, splats + (size_t)min(rec2, M - 1) * kSplatWords);
+        pv = rec2;
+        if (b0 + BLOCK + tid < re) load_splat_global<T>(pf, splats + (size_t)min(pv & kPairItem, M - 1) * kSplatWords);
         if (b0 + 2 * BLOCK + tid < re) rec2 = pvals[b0 + 2 * BLOCK + tid];
         if (!wave_any(!done)) continue;
         // Groups of fwd_group<T>() records: their contribution tests (exponent,
@@ -409,6 +412,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
 }
 
 // ---------------------------------------------------------------- backward
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // pair slot of a record that is not loaded
 constexpr int kChunk = 6;  // Gaussians per transposed reduction (6 x 10 = 60 of 64 lanes)
 
 template <typename T, int D, int M>
@@ -537,22 +541,22 @@ __global__ __launch_bounds__(TW* TH) void render_backward_kernel(
     // stay unmarked (their partials count as zero).
     const uint32_t hi = (maxlast >= (int)rs) ? (uint32_t)(maxlast + 1) : rs;
     T S = Tcur * (gc0 * cs.bg[0] + gc1 * cs.bg[1] + gc2 * cs.bg[2] + gt);
-    int bx0, bx1, by0, by1;
-    tile_pixel_box<T>(V, view, tx, ty, TW, TH, bx0, bx1, by0, by1);
     int buf = 0;
     for (uint32_t bend = hi; bend > rs;) {
         const uint32_t bstart = (bend - rs > (uint32_t)BLOCK) ? bend - BLOCK : rs;
         const int nbr = (int)(bend - bstart);
         __syncthreads();
-        // the batch's records that may contribute in the tile, compacted in
-        // order with their positions in the pad word
+        // the batch's records that may contribute in the tile (those the
+        // forward did not mark), compacted in order
         T r[kRecWords];
         uint32_t slot = 0u;
         bool cand = false;
         if (tid < nbr) {
-            const uint32_t rec = min(pvals[bstart + tid], M - 1);
-            slot = load_splat_slot<T>(r, splats + (size_t)rec * kSplatWords, tx, ty);
-            cand = tile_may_contribute<T>(r, bx0, bx1, by0, by1, cs);
+            const uint32_t pv = pvals[bstart + tid];
+            if (!(pv & kPairSkip)) {
+                slot = load_splat_slot<T>(r, splats + (size_t)min(pv, M - 1) * kSplatWords, tx, ty);
+                cand = true;
+            }
         }
         const uint64_t bal = __ballot(cand);
         if (lane == 0) s_wc[wave] = __popcll(bal);
@@ -768,10 +772,15 @@ __device__ __forceinline__ void backward_unit(
             ptg = ptarget ? ptarget[o] : T(0);
         }
     }
+    // A lane's record of a batch and its pair slot (kNoSlot: a pair the
+    // forward marked as contributing nowhere in the tile, not loaded).
     T pf[kRecWords];
-    uint32_t pf_slot = 0u;
-    if (seg_list && lane < (int)(hi_seg - batch_lo(hi_seg)))
-        pf_slot = load_splat_slot<T>(pf, splats + (size_t)min(rec_first, M - 1) * kSplatWords, tx, ty);
+    uint32_t pf_slot = kNoSlot;
+    auto load_pair = [&](uint32_t pv) {
+        if (pv & kPairSkip) pf_slot = kNoSlot;
+        else pf_slot = load_splat_slot<T>(pf, splats + (size_t)min(pv, M - 1) * kSplatWords, tx, ty);
+    };
+    if (seg_list && lane < (int)(hi_seg - batch_lo(hi_seg))) load_pair(rec_first);
 
     bool restart = false;
     T S_restart = T(0);
@@ -821,9 +830,6 @@ __device__ __forceinline__ void backward_unit(
     // the target-probability gradient joins a Gaussian's colour sum where its
     // object is the pixel's target (tgt -1: T_final's gradient carries it)
     const T gpt_obj = tgt >= 0 ? gpt : T(0);
-    int bx0, bx1, by0, by1;
-    tile_pixel_box<T>(V, view, tx, ty, TW, TH, bx0, bx1, by0, by1);
-
     // walk state (wave-uniform): the LDS batch holds positions [bstart, bend)
     uint32_t bend = hi, bstart = hi;
     int jl = -1;
@@ -840,10 +846,7 @@ __device__ __forceinline__ void backward_unit(
     // still; without it (segments: mostly one batch) later batches are
     // loaded when reached, and the record registers are free during the walk.
     uint32_t a_e = hi, a_s = batch_lo(hi);
-    if (!seg_list && lane < (int)(a_e - a_s)) {
-        const uint32_t rec = min(pvals[a_s + lane], M - 1);
-        pf_slot = load_splat_slot<T>(pf, splats + (size_t)rec * kSplatWords, tx, ty);
-    }
+    if (!seg_list && lane < (int)(a_e - a_s)) load_pair(pvals[a_s + lane]);
     uint32_t b_e = a_s, b_s = batch_lo(a_s), rec_b = 0u;
     // (clamped where used, so that nothing waits for this load early)
     if constexpr (PREFETCH) rec_b = (lane < (int)(b_e - b_s)) ? pvals[b_s + lane] : 0u;
@@ -882,16 +885,13 @@ __device__ __forceinline__ void backward_unit(
                 bstart = a_s;
                 const int nbr = (int)(bend - bstart);
                 if constexpr (!PREFETCH) {
-                    if (!first_batch && lane < nbr) {
-                        const uint32_t rec = min(pvals[bstart + lane], M - 1);
-                        pf_slot = load_splat_slot<T>(pf, splats + (size_t)rec * kSplatWords, tx, ty);
-                    }
+                    if (!first_batch && lane < nbr) load_pair(pvals[bstart + lane]);
                     first_batch = false;
                 }
                 __syncthreads();
-                // the records that may contribute in the tile, compacted in
-                // order with their positions in the pad word
-                const bool cand = lane < nbr && tile_may_contribute<T>(pf, bx0, bx1, by0, by1, cs);
+                // the records that may contribute in the tile (those the
+                // forward did not mark), compacted in order
+                const bool cand = lane < nbr && pf_slot != kNoSlot;
                 const uint64_t bal = __builtin_amdgcn_ballot_w64(cand);
                 if (cand) {
                     const int q = rank_below(bal);
@@ -905,9 +905,7 @@ __device__ __forceinline__ void backward_unit(
                 b_e = a_s;
                 b_s = batch_lo(a_s);
                 if constexpr (PREFETCH) {
-                    if (lane < (int)(a_e - a_s)) {
-                        pf_slot = load_splat_slot<T>(pf, splats + (size_t)min(rec_b, M - 1) * kSplatWords, tx, ty);
-                    }
+                    if (lane < (int)(a_e - a_s)) load_pair(rec_b);
                     rec_b = (lane < (int)(b_e - b_s)) ? pvals[b_s + lane] : 0u;
                 }
                 if (jl < 0) continue;  // nothing in this batch can contribute

@@ -24,6 +24,12 @@ def skip_no_gpu():
     return pytest.mark.skipif(not GPU, reason="needs a GPU")
 
 
+def pair_items(vals):
+    """Item indices of pair values read after a forward (which marks the
+    pairs that cannot contribute in their tile with the top bit)."""
+    return np.asarray(vals) & 0x7FFFFFFF
+
+
 def to_dev(a, dtype=torch.float32):
     return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 

@@ -11,7 +11,7 @@ import torch
 
 from paper_2503_02223_amd import binding as B
 from paper_2503_02223_amd import scenes
-from tests.gpu_util import to_dev
+from tests.gpu_util import pair_items, to_dev
 
 
 pytestmark = pytest.mark.gpu
@@ -61,7 +61,7 @@ def test_tile_depth_order_matches_global(n, tile, lds):
         # both paths of the per-tile sort ran
         assert (lens > lds).sum() > 0 and ((lens > 1) & (lens <= lds)).sum() > 0
     # the order itself: by tile, then the item's depth key, then item index
-    item = t["vals"].astype(np.int64)
+    item = pair_items(t["vals"]).astype(np.int64)
     order = np.lexsort((item, t["dkeys"][item], t["keys"]))
     assert (order == np.arange(t["P"])).all()
     for k in ("color", "depth", "t_final", "last"):

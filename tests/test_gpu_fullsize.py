@@ -9,7 +9,7 @@ import torch
 
 from paper_2503_02223_amd import binding as B
 from paper_2503_02223_amd import scenes
-from tests.gpu_util import FWD_RTOL, GRAD_RTOL, close, to_dev, unambiguous
+from tests.gpu_util import FWD_RTOL, GRAD_RTOL, close, pair_items, to_dev, unambiguous
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,7 @@ def test_fullsize_sampled_forward(oracle, room):
     close(img["t_final"][0].reshape(-1)[pix].cpu().numpy(), ref["Tf"], FWD_RTOL, ok, "T_final")
     P = img["probs"][0].reshape(sc["K"], -1)[:, pix].cpu().numpy()
     close(P, ref["P"], FWD_RTOL, ok, "instance")
-    vals = r.frame.buf("pair_vals", torch.int32).cpu().numpy()
+    vals = pair_items(r.frame.buf("pair_vals", torch.int32).cpu().numpy())
     lastpos = img["last"][0].reshape(-1)[pix].cpu().numpy()
     lastg = np.where(lastpos >= 0, vals[np.maximum(lastpos, 0)], -1)
     assert (lastg[ok] == ref["last"][ok]).all()

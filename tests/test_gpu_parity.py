@@ -8,7 +8,7 @@ import torch
 
 from paper_2503_02223_amd import binding as B
 from paper_2503_02223_amd import scenes
-from tests.gpu_util import BAND, FWD_RTOL, GRAD_RTOL, close, to_dev, unambiguous
+from tests.gpu_util import BAND, FWD_RTOL, GRAD_RTOL, close, pair_items, to_dev, unambiguous
 
 pytestmark = pytest.mark.gpu
 
@@ -104,7 +104,7 @@ def test_render_forward_parity(oracle, seed, tile):
     close(img["t_final"][0].cpu().numpy(), ref["Tf"], FWD_RTOL, ok, "T_final")
     close(img["probs"][0].cpu().numpy(), ref["P"], FWD_RTOL, ok, "instance")
     # last blended Gaussian: exact
-    vals = r.frame.buf("pair_vals", torch.int32).cpu().numpy()
+    vals = pair_items(r.frame.buf("pair_vals", torch.int32).cpu().numpy())
     lastpos = img["last"][0].cpu().numpy()
     lastg = np.where(lastpos >= 0, vals[np.maximum(lastpos, 0)], -1)
     assert (lastg[ok] == ref["last"][ok]).all()
@@ -163,10 +163,11 @@ def test_render_backward_parity(oracle, seed, tile):
 def test_backward_past_batches_that_cannot_contribute(oracle, probs):
     """A veil of faint Gaussians (opacity below alpha_min: they never blend)
     in front of an opaque background: every tile's pair range opens with more
-    than 128 of them, so the backward meets whole 64-pair batches (and, on the
-    segmented path, whole segments) in which no record can contribute, and
-    walks past them.  Whole tiles with instance channels (probs) and the
-    segmented path without them, against the oracle's adjoint."""
+    than 128 of them, all of which the forward marks as contributing nowhere,
+    so the backward meets whole 64-pair batches (and, on the segmented path,
+    whole segments) with no record to load, and walks past them.  Whole tiles
+    with instance channels (probs) and the segmented path without them,
+    against the oracle's adjoint."""
     rng = np.random.default_rng(5)
     nb, nf = 80, 400
     mu = np.concatenate([np.stack([rng.uniform(-1.6, 1.6, nb), rng.uniform(-1.6, 1.6, nb), rng.uniform(3.8, 4.2, nb)]),
@@ -196,13 +197,19 @@ def test_backward_past_batches_that_cannot_contribute(oracle, probs):
     # the case arises: tiles whose range opens with >= 128 faint pairs while
     # some pixel blends a background Gaussian behind them
     rng_t = r.frame.buf("ranges", torch.int32).cpu().numpy().reshape(-1, 2)
-    vals = r.frame.buf("pair_vals", torch.int32).cpu().numpy()
+    rc, st, P = r.frame.read_status()
+    assert rc == 0
+    raw = r.frame.buf("pair_vals", torch.int32, P).cpu().numpy()
+    vals = pair_items(raw)
+    # the forward marked every faint pair (the backward skips them unloaded)
+    assert (raw[vals >= nb] < 0).all()
     last = img["last"][0].cpu().numpy().reshape(H // 8, 8, W // 8, 8).transpose(0, 2, 1, 3).reshape(-1, 64)
     lead = np.array([np.argmax(np.append(vals[s:e], 0) < nb) for s, e in rng_t])
     assert ((lead >= 128) & (last.max(1) >= rng_t[:, 0] + lead)).sum() >= 4
     go, _ = oracle.render_backward(sc["params"], sc["ids"], cam, K=K, **up)
     assert np.abs(go[:, nb:]).max() == 0.0
     close(g.cpu().numpy(), go, GRAD_RTOL, what="param grads")
+
 
 def test_reproducible_bitwise():
     sc = scenes.single_view_scene(seed=7, n=2000)
@@ -422,7 +429,7 @@ def test_dense_view_loss_mode_parity(oracle):
     close(img["color"][0].cpu().numpy(), ref["C"], FWD_RTOL, ok, "colour")
     close(img["depth"][0].cpu().numpy(), ref["D"], FWD_RTOL, ok, "depth")
     close(img["t_final"][0].cpu().numpy(), ref["Tf"], FWD_RTOL, ok, "T_final")
-    vals = r.frame.buf("pair_vals", torch.int32).cpu().numpy()
+    vals = pair_items(r.frame.buf("pair_vals", torch.int32).cpu().numpy())
     lastpos = img["last"][0].cpu().numpy()
     lastg = np.where(lastpos >= 0, vals[np.maximum(lastpos, 0)], -1)
     assert (lastg[ok] == ref["last"][ok]).all()
