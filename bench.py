@@ -528,11 +528,11 @@ def main():
                          "1.2M Gaussians in a HIP graph; large: 1M at 1200x680 through autograd; learned-init: "
                          "train the initialization network and measure time-to-PSNR; tracking: camera pose "
                          "optimisation through the rasterizer on the 200k view")
-    ap.add_argument("--n-train", type=int, default=5000)
+    ap.add_argument("--n-train", type=int, default=16000)
     ap.add_argument("--n-val", type=int, default=256)
     ap.add_argument("--n-test", type=int, default=20)
     ap.add_argument("--label-iters", type=int, default=300)
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-steps", type=int, default=12000)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--workers", type=int, default=16)
