@@ -61,7 +61,10 @@ constexpr uint32_t kNoBoundary = 0xFFFFFFFFu;  // segment-list entry of a tile's
 // backward skips those pairs without loading their records.
 constexpr uint32_t kPairSkip = 0x80000000u;
 constexpr uint32_t kPairItem = 0x7FFFFFFFu;
-constexpr int kScanThreads = 1024;
+#ifndef DQO_SCAN_THREADS
+#define DQO_SCAN_THREADS 1024
+#endif
+constexpr int kScanThreads = DQO_SCAN_THREADS;
 constexpr int kScanIpt = 1;  // 2 and 4 measured slower at 200k items (1646 -> 1627 / 1573 it/s)
 constexpr int kScanTile = kScanThreads * kScanIpt;
 constexpr int kMaxDepthPasses = 4;

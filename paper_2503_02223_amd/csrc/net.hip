@@ -12,8 +12,9 @@
 // output-channel N-blocks, the K loop running over the 9 taps x cin.
 // Weight gradients are GEMMs over pixels: one workgroup per (pixel split,
 // tap) accumulates dW_tap[cout][cin] over its tiles from transposed LDS
-// copies of the activation window and the output gradient; a second kernel
-// sums the splits in a fixed order.
+// copies of the activation window and the output gradient (transposed in
+// registers, 8x8 blocks of 16-bit values); a second kernel sums the splits
+// in a fixed order.
 #include "dqo_device.hpp"
 #include "dqo_learned.h"
 #include "net.hpp"
@@ -149,6 +150,46 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const uint16
     }
 }
 
+// Stages C channels of a tile's 256 pixels (row-major in the tile) into LDS
+// transposed, channel-major rows of KP elements, from NHWC BF16 at pixel
+// offset (dy, dx) (zero outside the image).  Each thread takes a block of 8
+// consecutive pixels (half a tile row) x 8 channels: 8 16-byte loads, an 8x8
+// transpose of the 16-bit values in registers (v_perm_b32), and 8 16-byte
+// stores, one per channel.  Consecutive lanes take consecutive pixel groups,
+// so 16 lanes' stores cover the 64 LDS banks once.
+template <int C, int KP>
+__device__ __forceinline__ void stage_transposed(uint16_t* __restrict__ s, const uint16_t* __restrict__ src, int img,
+                                                 int H, int W, int ty0, int tx0, int dy, int dx, int tid) {
+    constexpr int NB = (kT * kT / 8) * (C / 8);
+    for (int b = tid; b < NB; b += 256) {
+        const int pg = b % (kT * kT / 8), cg = b / (kT * kT / 8);
+        const int px0 = pg * 8;
+        const int y = ty0 + px0 / kT + dy, x0 = tx0 + px0 % kT + dx;
+        uint4 r[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int x = x0 + k;
+            r[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (y >= 0 && y < H && x >= 0 && x < W)
+                r[k] = *reinterpret_cast<const uint4*>(src + (((size_t)img * H + y) * W + x) * C + cg * 8);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            // channel cg*8 + j: dword d of pixel k holds channels 2d (low half) and 2d+1
+            const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
+            uint32_t o[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint4 lo = r[2 * e], hi = r[2 * e + 1];
+                const uint32_t a = (j >> 1) == 0 ? lo.x : (j >> 1) == 1 ? lo.y : (j >> 1) == 2 ? lo.z : lo.w;
+                const uint32_t c = (j >> 1) == 0 ? hi.x : (j >> 1) == 1 ? hi.y : (j >> 1) == 2 ? hi.z : hi.w;
+                o[e] = __builtin_amdgcn_perm(c, a, sel);  // pixels 2e (low half) and 2e+1
+            }
+            *reinterpret_cast<uint4*>(s + (cg * 8 + j) * KP + px0) = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+    }
+}
+
 // Partial weight gradients of one (pixel split, tap):
 // part[split][co][tap][ci] = sum over the split's pixels p of g[p][co] * act[p + offset(tap)][ci],
 // part_b[split][co] = sum_p g[p][co] (written by the centre-tap workgroups).
@@ -176,26 +217,8 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(int H, int W, int n_
         const int img = t / tiles_img, tt = t - img * tiles_img;
         const int ty0 = (tt / tiles_x) * kT, tx0 = (tt % tiles_x) * kT;
         __syncthreads();
-        for (int c = tid; c < kT * kT * (COUT / 8); c += 256) {
-            const int px = c / (COUT / 8), c8 = c - px * (COUT / 8);
-            const int y = ty0 + px / kT, x = tx0 + px % kT;
-            const uint4 v = *reinterpret_cast<const uint4*>(g + (((size_t)img * H + y) * W + x) * COUT + c8 * 8);
-            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                s_g[(c8 * 8 + j) * KP + px] = (uint16_t)(w4[j >> 1] >> (16 * (j & 1)));
-        }
-        for (int c = tid; c < kT * kT * (CIN / 8); c += 256) {
-            const int px = c / (CIN / 8), c8 = c - px * (CIN / 8);
-            const int y = ty0 + px / kT + dy, x = tx0 + px % kT + dx;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (y >= 0 && y < H && x >= 0 && x < W)
-                v = *reinterpret_cast<const uint4*>(act + (((size_t)img * H + y) * W + x) * CIN + c8 * 8);
-            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                s_a[(c8 * 8 + j) * KP + px] = (uint16_t)(w4[j >> 1] >> (16 * (j & 1)));
-        }
+        stage_transposed<COUT, KP>(s_g, g, img, H, W, ty0, tx0, 0, 0, tid);
+        stage_transposed<CIN, KP>(s_a, act, img, H, W, ty0, tx0, dy, dx, tid);
         __syncthreads();
 #pragma unroll 2
         for (int k0 = 0; k0 < kT * kT; k0 += 32) {
