@@ -11,10 +11,10 @@
 // computes tile rows 4w..4w+3 (four M-blocks of 16 pixels) against all
 // output-channel N-blocks, the K loop running over the 9 taps x cin.
 // Weight gradients are GEMMs over pixels: one workgroup per (pixel split,
-// tap) accumulates dW_tap[cout][cin] over its tiles from transposed LDS
-// copies of the activation window and the output gradient (transposed in
-// registers, 8x8 blocks of 16-bit values); a second kernel sums the splits
-// in a fixed order.
+// tap column) accumulates the three taps' dW_tap[cout][cin] over its tiles
+// from transposed LDS copies of the activation window and the output
+// gradient (transposed in registers, 8x8 blocks of 16-bit values); a second
+// kernel sums the splits in a fixed order.
 #include "dqo_device.hpp"
 #include "dqo_learned.h"
 #include "net.hpp"
@@ -150,25 +150,26 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(int H, int W, const uint16
     }
 }
 
-// Stages C channels of a tile's 256 pixels (row-major in the tile) into LDS
-// transposed, channel-major rows of KP elements, from NHWC BF16 at pixel
-// offset (dy, dx) (zero outside the image).  Each thread takes a block of 8
-// consecutive pixels (half a tile row) x 8 channels: 8 16-byte loads, an 8x8
+// Stages C channels of ROWS x 16 pixels (row-major; image rows y0..,
+// columns x0..x0+15) into LDS transposed, channel-major rows of KP elements,
+// from NHWC BF16 (zero outside the image).  Each thread takes a block of 8
+// consecutive pixels (half a row) x 8 channels: 8 16-byte loads, an 8x8
 // transpose of the 16-bit values in registers (v_perm_b32), and 8 16-byte
 // stores, one per channel.  Consecutive lanes take consecutive pixel groups,
 // so 16 lanes' stores cover the 64 LDS banks once.
-template <int C, int KP>
+template <int C, int KP, int ROWS>
 __device__ __forceinline__ void stage_transposed(uint16_t* __restrict__ s, const uint16_t* __restrict__ src, int img,
-                                                 int H, int W, int ty0, int tx0, int dy, int dx, int tid) {
-    constexpr int NB = (kT * kT / 8) * (C / 8);
+                                                 int H, int W, int y0, int x0, int tid) {
+    constexpr int PG = ROWS * kT / 8;  // pixel groups
+    constexpr int NB = PG * (C / 8);
     for (int b = tid; b < NB; b += 256) {
-        const int pg = b % (kT * kT / 8), cg = b / (kT * kT / 8);
+        const int pg = b % PG, cg = b / PG;
         const int px0 = pg * 8;
-        const int y = ty0 + px0 / kT + dy, x0 = tx0 + px0 % kT + dx;
+        const int y = y0 + px0 / kT, xb = x0 + px0 % kT;
         uint4 r[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int x = x0 + k;
+            const int x = xb + k;
             r[k] = make_uint4(0u, 0u, 0u, 0u);
             if (y >= 0 && y < H && x >= 0 && x < W)
                 r[k] = *reinterpret_cast<const uint4*>(src + (((size_t)img * H + y) * W + x) * C + cg * 8);
@@ -190,26 +191,32 @@ __device__ __forceinline__ void stage_transposed(uint16_t* __restrict__ s, const
     }
 }
 
-// Partial weight gradients of one (pixel split, tap):
-// part[split][co][tap][ci] = sum over the split's pixels p of g[p][co] * act[p + offset(tap)][ci],
-// part_b[split][co] = sum_p g[p][co] (written by the centre-tap workgroups).
+// Partial weight gradients of the three taps (dy, dx), dy = -1, 0, 1, of one
+// column dx = blockIdx.y - 1, over one pixel split:
+// part[split][co][tap][ci] = sum over the split's pixels p of g[p][co] * act[p + (dy, dx)][ci],
+// part_b[split][co] = sum_p g[p][co] (written by the centre-column workgroups).
+// Per tile the output gradient is staged once and the activations once, as
+// 18 rows (the tile's rows -1..16 shifted by dx), so a tap's operand is that
+// copy offset by dy rows; a wave's A operand serves its three taps.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(int H, int W, int n_tiles, int tiles_per_split,
                                                             const uint16_t* __restrict__ act,
                                                             const uint16_t* __restrict__ g, float* __restrict__ part,
                                                             float* __restrict__ part_b) {
-    constexpr int KP = kT * kT + 8;  // LDS row (pixels of a tile) + 16-byte pad
-    constexpr int MT = COUT / 16, NTL = CIN / 16, TILES = MT * NTL, PER_WAVE = (TILES + 3) / 4;
+    constexpr int KP = kT * kT + 8;        // LDS row of the output gradient (pixels of a tile) + 16-byte pad
+    constexpr int KA = (kT + 2) * kT + 8;  // LDS row of the activations (18 x 16 pixels) + pad
+    constexpr int MT = COUT / 16, NTL = CIN / 16, PAIRS = MT * NTL, PER_WAVE = (PAIRS + 3) / 4;
     __shared__ __attribute__((aligned(16))) uint16_t s_g[COUT * KP];
-    __shared__ __attribute__((aligned(16))) uint16_t s_a[CIN * KP];
-    const int split = blockIdx.x, tap = blockIdx.y;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    __shared__ __attribute__((aligned(16))) uint16_t s_a[CIN * KA];
+    const int split = blockIdx.x, dxi = blockIdx.y, dx = dxi - 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lg = lane >> 4;
     const int tiles_x = W / kT, tiles_img = tiles_x * (H / kT);
-    floatx4 acc[PER_WAVE];
+    floatx4 acc[PER_WAVE][3];
 #pragma unroll
-    for (int i = 0; i < PER_WAVE; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < PER_WAVE; ++i)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[i][d] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.0f;
     const int t_begin = split * tiles_per_split;
     const int t_end = min(n_tiles, t_begin + tiles_per_split);
@@ -217,54 +224,77 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(int H, int W, int n_
         const int img = t / tiles_img, tt = t - img * tiles_img;
         const int ty0 = (tt / tiles_x) * kT, tx0 = (tt % tiles_x) * kT;
         __syncthreads();
-        stage_transposed<COUT, KP>(s_g, g, img, H, W, ty0, tx0, 0, 0, tid);
-        stage_transposed<CIN, KP>(s_a, act, img, H, W, ty0, tx0, dy, dx, tid);
+        stage_transposed<COUT, KP, kT>(s_g, g, img, H, W, ty0, tx0, tid);
+        stage_transposed<CIN, KA, kT + 2>(s_a, act, img, H, W, ty0 - 1, tx0 + dx, tid);
         __syncthreads();
 #pragma unroll 2
         for (int k0 = 0; k0 < kT * kT; k0 += 32) {
 #pragma unroll
             for (int i = 0; i < PER_WAVE; ++i) {
-                const int tile = wave + 4 * i;
-                if (tile < TILES) {
-                    const int mt = tile / NTL, nt = tile - mt * NTL;
+                const int pr = wave + 4 * i;
+                if (pr < PAIRS) {
+                    const int mt = pr / NTL, nt = pr - mt * NTL;
                     const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(s_g + (mt * 16 + lr) * KP + k0 + 8 * lg);
-                    const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(s_a + (nt * 16 + lr) * KP + k0 + 8 * lg);
-                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i], 0, 0, 0);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        // output pixel k reads activation row (k / 16) + d of the staged copy
+                        const bf16x8_t b =
+                            *reinterpret_cast<const bf16x8_t*>(s_a + (nt * 16 + lr) * KA + k0 + 8 * lg + d * kT);
+                        acc[i][d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][d], 0, 0, 0);
+                    }
                 }
             }
         }
-        if (tap == 4 && tid < COUT)
+        if (dxi == 1 && tid < COUT)
             for (int px = 0; px < kT * kT; ++px) bsum += bf2f(s_g[tid * KP + px]);
     }
-    // acc[i][r] = dW[co = 16 mt + 4 lg + r][ci = 16 nt + lr]
+    // acc[i][d][r] = dW[co = 16 mt + 4 lg + r][tap = 3 d + dxi][ci = 16 nt + lr]
 #pragma unroll
     for (int i = 0; i < PER_WAVE; ++i) {
-        const int tile = wave + 4 * i;
-        if (tile < TILES) {
-            const int mt = tile / NTL, nt = tile - mt * NTL;
+        const int pr = wave + 4 * i;
+        if (pr < PAIRS) {
+            const int mt = pr / NTL, nt = pr - mt * NTL;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int co = mt * 16 + 4 * lg + r, ci = nt * 16 + lr;
-                part[((size_t)split * COUT + co) * 9 * CIN + tap * CIN + ci] = acc[i][r];
-            }
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int co = mt * 16 + 4 * lg + r, ci = nt * 16 + lr;
+                    part[((size_t)split * COUT + co) * 9 * CIN + (3 * d + dxi) * CIN + ci] = acc[i][d][r];
+                }
         }
     }
-    if (tap == 4 && tid < COUT) part_b[split * COUT + tid] = bsum;
+    if (dxi == 1 && tid < COUT) part_b[split * COUT + tid] = bsum;
 }
 
+// Sums the splits' partial weight gradients: a workgroup takes 64 entries,
+// its four waves a quarter of the splits each (split q, q + 4, ... in order),
+// and the four partial sums are added in wave order (a fixed order: the
+// result does not depend on timing).
 __global__ __launch_bounds__(256) void wgrad_reduce_kernel(int S, int64_t E, int cout, const float* __restrict__ part,
                                                            const float* __restrict__ part_b, float* __restrict__ gw,
                                                            float* __restrict__ gb) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < E) {
-        float s = 0.0f;
-        for (int k = 0; k < S; ++k) s += part[(int64_t)k * E + e];
-        gw[e] = s;
-    }
-    if (e < cout) {
-        float s = 0.0f;
-        for (int k = 0; k < S; ++k) s += part_b[k * cout + e];
-        gb[e] = s;
+    __shared__ float s_sum[4][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;  // entries E.. are the biases
+    const bool is_w = e < E, is_b = !is_w && e < E + cout;
+    const float* src = is_w ? part + e : part_b + (e - E);
+    const int64_t stride = is_w ? E : (int64_t)cout;
+    float s = 0.0f;
+    if (is_w || is_b)
+        for (int k0 = q; k0 < S; k0 += 32) {
+            // eight loads in flight, then added in split order
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (k0 + 4 * j < S) ? src[(int64_t)(k0 + 4 * j) * stride] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += v[j];
+        }
+    s_sum[q][lane] = s;
+    __syncthreads();
+    if (q == 0 && (is_w || is_b)) {
+        const float t = ((s_sum[0][lane] + s_sum[1][lane]) + s_sum[2][lane]) + s_sum[3][lane];
+        if (is_w) gw[e] = t;
+        else gb[e - E] = t;
     }
 }
 
@@ -512,10 +542,10 @@ static void wgrad(const Work& w, int B, int H, int W, const uint16_t* act, const
     const int n_tiles = B * (H / kT) * (W / kT);
     const int S = w.splits;
     const int per = (n_tiles + S - 1) / S;
-    hipLaunchKernelGGL((conv3x3_wgrad_kernel<CIN, COUT>), dim3(S, 9), dim3(256), 0, st, H, W, n_tiles, per, act, g,
+    hipLaunchKernelGGL((conv3x3_wgrad_kernel<CIN, COUT>), dim3(S, 3), dim3(256), 0, st, H, W, n_tiles, per, act, g,
                        w.part, w.part_b);
     const int64_t E = (int64_t)COUT * 9 * CIN;
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, st, S, E, COUT, w.part,
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((E + COUT + 63) / 64)), dim3(256), 0, st, S, E, COUT, w.part,
                        w.part_b, gw, gb);
 }
 
