@@ -201,7 +201,8 @@ __device__ __forceinline__ int rank_below(uint64_t bal) {
 template <typename T>
 constexpr int fwd_group() { return (sizeof(T) == 8 && DQO_FWD_GROUP > 4) ? 4 : DQO_FWD_GROUP; }
 
-template <typename T, int TW, int TH, bool PROBS>
+// PROBS: with the instance channels; NB: with the per-pixel blend count.
+template <typename T, int TW, int TH, bool PROBS, bool NB = true>
 __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     Views<T> V, Consts<T> cs, int K, const T* __restrict__ splats, uint32_t* __restrict__ pvals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule, T* __restrict__ color, T* __restrict__ depth, T* __restrict__ tfinal,
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
                 pt += (id == tgt) ? w : T(0);
                 const bool blended = w != T(0);
                 lastpos = blended ? word_to_id<T>(rec[k][kWPos]) : lastpos;
-                nb_count += blended ? 1 : 0;
+                if constexpr (NB) nb_count += blended ? 1 : 0;
                 if (PROBS && blended && id >= 0 && id < K) s_P[id * BLOCK + tid] += w;
                 Tt = stop ? Tt : Tn;
                 done = done || stop;
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     depth[o] = dd;
     tfinal[o] = Tt;
     last[o] = lastpos;
-    if (nblend) nblend[o] = nb_count;
+    if (NB && nblend) nblend[o] = nb_count;
     if (ptarget && target) ptarget[o] = (tgt == -1) ? Tt : pt;
     if (PROBS) {
         int best = K;
@@ -1065,7 +1066,8 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
                            (T*)(seg ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
     } else {
-        hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, false>), dim3(blocks), dim3(TW * TH), 0, st, f.views,
+        auto kern = img.n_blend ? render_forward_kernel<T, TW, TH, false, true> : render_forward_kernel<T, TW, TH, false, false>;
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)nullptr, (int32_t*)nullptr, img.target,
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
