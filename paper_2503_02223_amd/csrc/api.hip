@@ -133,7 +133,7 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.off_ckpt = so; so = align256(so + g.ckpt_cap * 6 * kWave * ts);
     // look-back words: every block's, then every group's (grouped look-back)
     g.off_lbd = so; so = align256(so + (int64_t)kMaxDepthPasses * lb_blocks(g.depth_blocks) * kRadixBins * 8);
-    g.off_lbs = so; so = align256(so + (int64_t)lb_blocks(g.scan_blocks) * 8);
+    g.off_lbs = so; so = align256(so + (int64_t)lb_blocks(g.scan_blocks) * (kRadixBins + 1) * 8);
     g.off_lbp = so; so = align256(so + (int64_t)kMaxPairPasses * lb_blocks(g.pair_blocks) * kRadixBins * 8);
     g.lb_words = (so - g.off_lbd) / 8;
     sz[DQO_BUF_SCRATCH] = so;
@@ -189,6 +189,10 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.pair_first_buf = g.pair_first_buf;
     s.tile_sort = g.tile_sort;
     s.tile_sort_lds = g.tile_sort_lds;
+#ifndef DQO_FUSED_EMIT
+#define DQO_FUSED_EMIT 1
+#endif
+    s.fused_emit = DQO_FUSED_EMIT && g.pair_passes >= 1 && g.scan_blocks <= scan_emit_resident(true);
     // One histogram copy per 64 producer workgroups (up to kHistCopies): enough
     // to spread the atomics, few enough for the radix passes to sum cheaply.
     const int64_t proj_blocks = (g.items + 256 * kProjItems - 1) / (256 * kProjItems);

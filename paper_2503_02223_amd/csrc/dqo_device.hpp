@@ -363,7 +363,7 @@ struct StatePtrs {
     uint32_t* scan_base;  // [scan blocks] pair offset of each scan block (two-level scan)
     Ctrl* ctrl;
     uint64_t* lb_depth;   // [kMaxDepthPasses][blocks][256]
-    uint64_t* lb_scan;    // [blocks]
+    uint64_t* lb_scan;    // [blocks][257]: 256 digits of the fused first pair pass, then the pair count
     uint64_t* lb_pair;    // [kMaxPairPasses][blocks][256]
     int64_t items;        // V * n
     int64_t capacity;
@@ -376,6 +376,7 @@ struct StatePtrs {
     // in item order (order = identity) and each tile's pairs sorted after the
     // tile sort.
     bool tile_sort;
+    bool fused_emit;      // the emission performs the first pair pass (resident scan grid)
     int tile_sort_lds;    // longest tile range sorted in LDS (longer ones: global-memory passes)
     int hist_copies_depth;  // histogram copies in use (1..kHistCopies), by producer workgroup count
     int hist_copies_pair;
@@ -393,6 +394,9 @@ struct Frame {
 template <typename T>
 hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t* ids, hipStream_t st);
 hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st);
+// Workgroups of the scan + emission (fused with the first pair pass or not)
+// that the device holds at once.
+int scan_emit_resident(bool fused);
 template <typename T>
 hipError_t launch_render_forward(const Frame<T>& f, const dqo_images& img, hipStream_t st);
 template <typename T>

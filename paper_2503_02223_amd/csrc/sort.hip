@@ -186,26 +186,11 @@ __global__ __launch_bounds__(256) void tile_bounds_kernel(const uint32_t* __rest
 constexpr int kSchedThreads = 1024;
 constexpr int kSchedBins = 4096;
 
-// Exclusive scan, in index order, of count(i) for i in [0, n) by one block:
-// each thread takes a contiguous chunk.  Writes out[i] and returns the total.
-template <typename F>
-__device__ __forceinline__ uint32_t block_chunk_scan(int n, F count, uint32_t* __restrict__ out, uint32_t* s_tmp,
-                                                     uint32_t* s_total) {
-    const int tid = threadIdx.x;
-    const int per = (n + kSchedThreads - 1) / kSchedThreads;
-    const int lo = min(n, tid * per), hi = min(n, lo + per);
-    uint32_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += count(i);
-    uint32_t off = block_exclusive_scan<kSchedThreads>(sum, s_tmp);
-    for (int i = lo; i < hi; ++i) {
-        out[i] = off;
-        off += count(i);
-    }
-    if (tid == kSchedThreads - 1) *s_total = off;
-    __syncthreads();
-    return *s_total;
-}
-
+// Up to kSchedRegs tiles per thread are loaded once, all at once, and kept in
+// registers (their ranges are read by three dependent phases: the count
+// histogram, the scatter and the boundary bases); more tiles loop over
+// global memory.
+constexpr int kSchedRegs = 8;
 __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint32_t* __restrict__ ranges,
                                                                      int tiles, uint32_t* __restrict__ schedule,
                                                                      uint32_t* __restrict__ ckpt_base) {
@@ -213,13 +198,29 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
     __shared__ uint32_t s_tmp[kSchedThreads / kWave];
     constexpr int kPer = kSchedBins / kSchedThreads;
     const int tid = threadIdx.x;
+    auto bin_of_w = [](uint32_t w) { return kSchedBins - 1 - (int)min(w, (uint32_t)(kSchedBins - 1)); };
+    auto width = [&](int t) {
+        const uint2 r = reinterpret_cast<const uint2*>(ranges)[t];
+        return r.y - r.x;
+    };
+    // thread tid holds tiles [tid * per, tid * per + per): contiguous, for the index-order scan below
+    const int per = (tiles + kSchedThreads - 1) / kSchedThreads;
+    const bool regs = per <= kSchedRegs;
+    const int lo = min(tiles, tid * per), hi = min(tiles, lo + per);
+    uint32_t w[kSchedRegs];
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kSchedRegs; ++k) w[k] = lo + k < hi ? width(lo + k) : 0u;
+    }
     for (int b = tid; b < kSchedBins; b += kSchedThreads) s_cnt[b] = 0u;
     __syncthreads();
-    auto bin_of = [&](int t) {
-        const uint32_t w = ranges[2 * t + 1] - ranges[2 * t];
-        return kSchedBins - 1 - (int)min(w, (uint32_t)(kSchedBins - 1));
-    };
-    for (int t = tid; t < tiles; t += kSchedThreads) atomicAdd(&s_cnt[bin_of(t)], 1u);
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kSchedRegs; ++k)
+            if (lo + k < hi) atomicAdd(&s_cnt[bin_of_w(w[k])], 1u);
+    } else {
+        for (int t = lo; t < hi; ++t) atomicAdd(&s_cnt[bin_of_w(width(t))], 1u);
+    }
     __syncthreads();
     uint32_t c[kPer], sum = 0;
 #pragma unroll
@@ -234,19 +235,41 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
         off += c[k];
     }
     __syncthreads();
-    for (int t = tid; t < tiles; t += kSchedThreads) schedule[atomicAdd(&s_cnt[bin_of(t)], 1u)] = (uint32_t)t;
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kSchedRegs; ++k)
+            if (lo + k < hi) schedule[atomicAdd(&s_cnt[bin_of_w(w[k])], 1u)] = (uint32_t)(lo + k);
+    } else {
+        for (int t = lo; t < hi; ++t) schedule[atomicAdd(&s_cnt[bin_of_w(width(t))], 1u)] = (uint32_t)t;
+    }
     if (!ckpt_base) return;  // uniform
     // Segmented backward of 64-pixel tiles: the first boundary record of
     // each tile (index order), where the forward stores its boundary states.
-    __shared__ uint32_t s_total;
-    __syncthreads();
-    block_chunk_scan(
-        tiles,
-        [&](int t) {
-            const uint32_t k = tile_segments(ranges[2 * t + 1] - ranges[2 * t]);
-            return k ? k - 1u : 0u;
-        },
-        ckpt_base, s_tmp, &s_total);
+    auto bounds = [](uint32_t wt) {
+        const uint32_t k = tile_segments(wt);
+        return k ? k - 1u : 0u;
+    };
+    uint32_t own = 0;
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kSchedRegs; ++k) own += lo + k < hi ? bounds(w[k]) : 0u;
+    } else {
+        for (int t = lo; t < hi; ++t) own += bounds(width(t));
+    }
+    uint32_t run = block_exclusive_scan<kSchedThreads>(own, s_tmp);
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kSchedRegs; ++k)
+            if (lo + k < hi) {
+                ckpt_base[lo + k] = run;
+                run += bounds(w[k]);
+            }
+    } else {
+        for (int t = lo; t < hi; ++t) {
+            ckpt_base[t] = run;
+            run += bounds(width(t));
+        }
+    }
 }
 
 // The backward's work list, built after the forward: every 64-pair segment
@@ -346,6 +369,7 @@ bool radix_resident(int nt, int ipt, int64_t items) {
     DQO_RADIX_RES(256, 8)
     DQO_RADIX_RES(256, 16)
     DQO_RADIX_RES(256, 32)
+    DQO_RADIX_RES(1024, 2)
     DQO_RADIX_RES(1024, 4)
     DQO_RADIX_RES(1024, 8)
     DQO_RADIX_RES(1024, 16)
@@ -365,6 +389,7 @@ hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
     DQO_RADIX_CASE(256, 8)
     DQO_RADIX_CASE(256, 16)
     DQO_RADIX_CASE(256, 32)
+    DQO_RADIX_CASE(1024, 2)
     DQO_RADIX_CASE(1024, 4)
     DQO_RADIX_CASE(1024, 8)
     DQO_RADIX_CASE(1024, 16)
@@ -543,8 +568,10 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
     // short blocks while that grid is resident at once, else long ones
     const bool short_ok = radix_resident(kPairNt, kPairIptShort, cap);
     const int ipt = short_ok ? kPairIptShort : kPairIptLong;
-    int src = s.pair_first_buf;
-    for (int p = 0; p < s.pair_passes; ++p) {
+    // the fused emission has done pass 0 (its output is in the other buffer)
+    const int p0 = s.fused_emit ? 1 : 0;
+    int src = s.pair_first_buf ^ p0;
+    for (int p = p0; p < s.pair_passes; ++p) {
         hipError_t e = launch_radix_pass(s.pair_keys[src], s.pair_vals[src], s.pair_keys[src ^ 1],
                                          s.pair_vals[src ^ 1], n_dev, cap, p * kRadixBits,
                                          &s.ctrl->hist_pair[0][p][0], kMaxPairPasses * kRadixBins, s.hist_copies_pair, s.lb_pair + (size_t)p * lb_blocks(s.pair_blocks) * kRadixBins,

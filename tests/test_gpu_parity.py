@@ -85,6 +85,41 @@ def test_projection_binning_and_sort(oracle, seed):
         assert e - s == (keys == t).sum()
 
 
+def test_pair_list_of_large_splats(oracle):
+    """Gaussians four times the usual size (about 36 tiles each), so that an
+    emission block (1024 items in depth order) holds more pairs than the
+    emission stages in LDS and stores each pair where it goes: the pair list
+    is still the stable (tile, depth bits, index) order of exactly the pairs
+    of the tile rectangles, and the images match the oracle."""
+    sc = scenes.single_view_scene(seed=7, n=3000)
+    sc["params"][3:6] += 1.4
+    r, p, ids = _frame(sc, ctx=B.Context(tile_w=8, tile_h=8))
+    img = r.forward(p, ids, probs=True)
+    torch.cuda.synchronize()
+    f = r.frame
+    rc, st, P = f.read_status()
+    assert rc == 0 and st == 0
+    cnt = f.buf("counts", torch.int32, 3000).cpu().numpy().astype(np.int64)
+    dorder = f.buf("depth_order", torch.int32, 3000).cpu().numpy()
+    per_block = [int(cnt[dorder[i:i + 1024]].sum()) for i in range(0, 3000, 1024)]
+    assert max(per_block) > 12288, per_block
+    keys = f.buf("pair_keys", torch.int32, P).cpu().numpy().astype(np.int64)
+    vals = pair_items(f.buf("pair_vals", torch.int32, P).cpu().numpy()).astype(np.int64)
+    spl = f.buf("splats", torch.float32, 3000 * B.SPLAT_WORDS).view(3000, B.SPLAT_WORDS).cpu().numpy()
+    zbits = spl[:, 6].astype(np.float32).view(np.uint32).astype(np.int64)
+    assert (np.lexsort((vals, zbits[vals], keys)) == np.arange(P)).all()
+    rect = f.buf("rects", torch.int16, 3000 * 4).view(3000, 4).cpu().numpy().astype(np.int64)
+    want = sorted((int(y * 16 + x), g) for g in range(3000) if cnt[g]
+                  for y in range(rect[g, 1], rect[g, 3] + 1) for x in range(rect[g, 0], rect[g, 2] + 1))
+    assert P == len(want) and sorted(zip(keys.tolist(), vals.tolist())) == want
+    ref = _oracle_fwd(oracle, sc)
+    ok = unambiguous(ref)
+    assert ok.mean() > 0.9
+    close(img["color"][0].cpu().numpy(), ref["C"], FWD_RTOL, ok, "colour")
+    close(img["depth"][0].cpu().numpy(), ref["D"], FWD_RTOL, ok, "depth")
+    close(img["t_final"][0].cpu().numpy(), ref["Tf"], FWD_RTOL, ok, "T_final")
+
+
 def _oracle_fwd(oracle, sc, cfg=None, pix=None):
     return oracle.render(sc["params"], sc["ids"], sc["cams"][0], cfg=cfg, K=sc["K"], pix=pix)
 

@@ -25,10 +25,14 @@ def _set_timeout_bit(f):
     ctrl[STATUS] = ctrl[STATUS] | B.STATUS_TIMEOUT
 
 
-def test_timeout_bit_switches_sort_to_ticket_order():
-    sc = scenes.single_view_scene(seed=1, n=2000)
+@pytest.mark.parametrize("view", ["128x96", "640x480"])
+def test_timeout_bit_switches_sort_to_ticket_order(view):
+    # 128x96: 192 tiles, one 8-bit pair pass; 640x480: 4800 tiles, two
+    n = 2000 if view == "128x96" else 20000
+    sc = scenes.single_view_scene(seed=1, n=n) if view == "128x96" else scenes.slam_view_scene(seed=1, n=n)
     # the global depth order, whose four depth passes take tickets too
-    r = B.Rasterizer(sc["cams"], 2000, 3, ctx=B.Context(tile_w=8, tile_h=8, depth_order=B.DEPTH_ORDER_GLOBAL))
+    r = B.Rasterizer(sc["cams"], n, 3 if view == "128x96" else sc["K"],
+                     ctx=B.Context(tile_w=8, tile_h=8, depth_order=B.DEPTH_ORDER_GLOBAL))
     p = to_dev(sc["params"])
     ids = torch.tensor(sc["ids"], device="cuda")
     r.bin(p, ids)          # sizes the pair list (grows it on overflow)
@@ -41,7 +45,7 @@ def test_timeout_bit_switches_sort_to_ticket_order():
     ctrl = f.buf("control", torch.int32)
     assert npairs > 4096   # two pair blocks at least
     ref = {k: f.buf(k, torch.int32)[:npairs].clone() for k in ("pair_keys", "pair_vals")}
-    ref["depth_order"] = f.buf("depth_order", torch.int32)[:2000].clone()
+    ref["depth_order"] = f.buf("depth_order", torch.int32)[:n].clone()
     ref["ranges"] = f.buf("ranges", torch.int32).clone()
     assert (ctrl[DEPTH_TICKETS] == 0).all() and int(ctrl[SCAN_TICKET]) == 0 and (ctrl[PAIR_TICKETS] == 0).all()
 
@@ -52,14 +56,20 @@ def test_timeout_bit_switches_sort_to_ticket_order():
     rc, st, npairs2 = f.read_status()
     assert rc == B.EINTERNAL and st & B.STATUS_TIMEOUT and npairs2 == npairs
     ctrl = f.buf("control", torch.int32)
-    # every block of every pass took a ticket: the depth passes' one block, the
-    # scan's two blocks, the pair pass's blocks (192 tiles: one 8-bit pass)
-    assert (ctrl[DEPTH_TICKETS] == 1).all(), ctrl[DEPTH_TICKETS]
-    assert int(ctrl[SCAN_TICKET]) == 2
-    assert int(ctrl[PAIR_TICKETS][0]) >= 2 and int(ctrl[PAIR_TICKETS][1]) == 0, ctrl[PAIR_TICKETS]
+    # every block of every pass took a ticket: the depth passes' blocks of
+    # 2048 items, the scan's blocks of 1024; the emission performs the first
+    # pair pass itself (its grid fits on the device), so only a second pair
+    # pass runs (its grid is sized by the pair capacity)
+    assert (ctrl[DEPTH_TICKETS] == (n + 2047) // 2048).all(), ctrl[DEPTH_TICKETS]
+    assert int(ctrl[SCAN_TICKET]) == (n + 1023) // 1024
+    assert int(ctrl[PAIR_TICKETS][0]) == 0, ctrl[PAIR_TICKETS]
+    if view == "640x480":
+        assert int(ctrl[PAIR_TICKETS][1]) >= 2, ctrl[PAIR_TICKETS]
+    else:
+        assert int(ctrl[PAIR_TICKETS][1]) == 0, ctrl[PAIR_TICKETS]
     for k in ("pair_keys", "pair_vals"):
         assert torch.equal(f.buf(k, torch.int32)[:npairs], ref[k]), k
-    assert torch.equal(f.buf("depth_order", torch.int32)[:2000], ref["depth_order"])
+    assert torch.equal(f.buf("depth_order", torch.int32)[:n], ref["depth_order"])
     assert torch.equal(f.buf("ranges", torch.int32), ref["ranges"])
 
     f.clear_status()
