@@ -34,7 +34,7 @@ struct Geo {
     int depth_blocks, scan_blocks, pair_blocks, pair_passes, pair_first_buf;
     int64_t lb_words;
     // scratch sub-offsets (relative to DQO_BUF_SCRATCH)
-    int64_t off_dk1, off_dv1, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_sbase, off_seg, off_cbase,
+    int64_t off_dk1, off_dv1, off_dk2, off_dv2, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_sbase, off_seg, off_cbase,
         off_tlast, off_ckpt, off_lbd, off_lbs, off_lbp;
     int64_t seg_cap, ckpt_cap;
     bool tile_sort;     // per-tile depth order (dqo_depth_order TILE)
@@ -116,6 +116,8 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     int64_t so = 0;
     g.off_dk1 = so; so = align256(so + M * 4);
     g.off_dv1 = so; so = align256(so + M * 4);
+    g.off_dk2 = so; so = align256(so + M * 4);
+    g.off_dv2 = so; so = align256(so + M * 4);
     g.off_pk1 = so; so = align256(so + cap * 4);
     g.off_pv1 = so; so = align256(so + cap * 4);
     g.off_sched = so; so = align256(so + tiles_total * 4);
@@ -159,6 +161,8 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.depth_vals[0] = (uint32_t*)(b + g.L.offset[DQO_BUF_DEPTH_ORDER]);
     s.depth_keys[1] = (uint32_t*)(sc + g.off_dk1);
     s.depth_vals[1] = (uint32_t*)(sc + g.off_dv1);
+    s.depth_keys[2] = (uint32_t*)(sc + g.off_dk2);
+    s.depth_vals[2] = (uint32_t*)(sc + g.off_dv2);
     s.pair_keys[0] = (uint32_t*)(b + g.L.offset[DQO_BUF_PAIR_KEYS]);
     s.pair_vals[0] = (uint32_t*)(b + g.L.offset[DQO_BUF_PAIR_VALS]);
     s.pair_keys[1] = (uint32_t*)(sc + g.off_pk1);

@@ -104,6 +104,10 @@ struct Ctrl {
     uint32_t hist_depth[kHistCopies][kMaxDepthPasses][kRadixBins];
     uint32_t hist_pair[kHistCopies][kMaxPairPasses][kRadixBins];
     double loss_partials[kLossBlocks][kLossParts];
+    // The frame's visible depth keys in kHistCopies copies (projection
+    // workgroup w adds to copy w mod kHistCopies): max of ~key (so that the
+    // cleared word is neutral) and max of key.
+    uint32_t dkey_range[kHistCopies][2];
 };
 
 template <typename T>
@@ -342,8 +346,8 @@ struct StatePtrs {
     short4* rects;
     uint32_t* counts;
     uint32_t* offsets;
-    uint32_t* depth_keys[2];
-    uint32_t* depth_vals[2];
+    uint32_t* depth_keys[3];  // [0]: the state buffer; [1], [2]: scratch of the depth passes
+    uint32_t* depth_vals[3];
     uint32_t* pair_keys[2];
     uint32_t* pair_vals[2];
     uint32_t* ranges;

@@ -29,6 +29,7 @@ __global__ __launch_bounds__(256) void prep_kernel(Ctrl* ctrl, int copies_depth,
         if (t == 0) ctrl->epoch = ctrl->epoch + 1u;
         if (t < kNumCounters) ctrl->counters[t] = 0u;
         if (t == 0) ctrl->num_pairs = 0u;
+        if (t < 2 * kHistCopies) (&ctrl->dkey_range[0][0])[t] = 0u;
     }
     if (c < copies_depth)
         for (int p = 0; p < kMaxDepthPasses; ++p) ctrl->hist_depth[c][p][t] = 0u;
@@ -123,7 +124,8 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
                                                       uint32_t* __restrict__ dvals, uint32_t* __restrict__ ranges,
                                                       int64_t range_words, int copies, Ctrl* ctrl,
                                                       uint32_t* __restrict__ pair_hist0, int copies_pair) {
-    __shared__ uint32_t s_hist[kMaxDepthPasses][kRadixBins];
+    __shared__ uint32_t s_hist[kRadixBins];  // low byte of the depth keys
+    __shared__ uint32_t s_krange[2];         // visible depth keys: max of ~key, max of key
     // Low-byte histogram of the pairs' tile ids (when the emission sorts by
     // that byte itself): a difference array over the 256 digits, one range
     // per rectangle row, and the count of whole 256-tile cycles.
@@ -133,9 +135,9 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
     const int tid = threadIdx.x;
     // Tile ranges start empty: the sort writes only the bounds of tiles that hold pairs.
     for (int64_t w = (int64_t)blockIdx.x * 256 + tid; w < range_words; w += (int64_t)gridDim.x * 256) ranges[w] = 0u;
-#pragma unroll
-    for (int p = 0; p < kMaxDepthPasses; ++p) s_hist[p][tid] = 0u;
+    s_hist[tid] = 0u;
     s_pd[tid] = 0u;
+    if (tid < 2) s_krange[tid] = 0u;
     if (tid == 0) {
         s_pd[kRadixBins] = 0u;
         s_pall = 0u;
@@ -143,6 +145,7 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
     __syncthreads();
     // kProjItems items per thread (coalesced per item step): fewer workgroups
     // flush histogram counts to the shared copies.
+    uint32_t kmin_inv = 0u, kmax = 0u;  // visible depth keys: max of ~key, max of key
     for (int it = 0; it < kProjItems; ++it) {
         const int64_t i = ((int64_t)blockIdx.x * kProjItems + it) * 256 + tid;
         if (i < M) {
@@ -210,15 +213,28 @@ __global__ __launch_bounds__(256) void project_kernel(Views<T> V, Consts<T> cs, 
             const uint32_t key = pr.visible ? __float_as_uint((float)pr.z) : 0xffffffffu;
             dkeys[i] = key;
             dvals[i] = (uint32_t)i;
-#pragma unroll
-            for (int ps = 0; ps < kMaxDepthPasses; ++ps) atomicAdd(&s_hist[ps][(key >> (8 * ps)) & 255u], 1u);
+            // the depth passes count their later digits themselves (relative to the smallest key)
+            atomicAdd(&s_hist[key & 255u], 1u);
+            if (pr.visible) {
+                kmin_inv = max(kmin_inv, ~key);
+                kmax = max(kmax, key);
+            }
         }
     }
-    __syncthreads();
 #pragma unroll
-    for (int ps = 0; ps < kMaxDepthPasses; ++ps) {
-        const uint32_t c = s_hist[ps][tid];
-        if (c) atomicAdd(&ctrl->hist_depth[blockIdx.x % copies][ps][tid], c);
+    for (int d = 1; d < kWave; d <<= 1) {
+        kmin_inv = max(kmin_inv, (uint32_t)__shfl_xor(kmin_inv, d));
+        kmax = max(kmax, (uint32_t)__shfl_xor(kmax, d));
+    }
+    if ((tid & (kWave - 1)) == 0) {
+        atomicMax(&s_krange[0], kmin_inv);
+        atomicMax(&s_krange[1], kmax);
+    }
+    __syncthreads();
+    if (tid < 2 && s_krange[tid]) atomicMax(&ctrl->dkey_range[blockIdx.x % kHistCopies][tid], s_krange[tid]);
+    {
+        const uint32_t c = s_hist[tid];
+        if (c) atomicAdd(&ctrl->hist_depth[blockIdx.x % copies][0][tid], c);
     }
     if (pair_hist0) {  // uniform
         const uint32_t d = s_pd[tid];
@@ -582,17 +598,23 @@ hipError_t launch_project_bin(const Frame<T>& f, const T* params, const int32_t*
     // Below 2^18 items the 2048-item blocks run as 1024 threads x 2 items
     // (4 wavefronts per SIMD instead of 1 hide more of the load latency:
     // 12.6 -> 12.0 us per pass at 200k items); the block length is the same.
-    const int dnt = M < (int64_t(1) << 18) ? 1024 : kDepthNt;
+#ifndef DQO_DEPTH_SMALL_NT
+#define DQO_DEPTH_SMALL_NT 1024
+#endif
+    const int dnt = M < (int64_t(1) << 18) ? DQO_DEPTH_SMALL_NT : kDepthNt;
     const int dipt = kDepthNt * depth_ipt(M) / dnt;
-    int src = 0;
+    // Buffers of the four passes: 0 -> 1 -> 2 -> 1 -> 0, or 0 -> 1 -> 2 -> 0
+    // when three passes suffice (decided on the device from the key range).
+    static const int kIn[kMaxDepthPasses] = {0, 1, 2, 1}, kOut[kMaxDepthPasses] = {1, 2, 1, 0};
     for (int p = 0; p < (s.tile_sort ? 0 : kMaxDepthPasses); ++p) {
-        hipError_t e = launch_radix_pass(s.depth_keys[src], s.depth_vals[src], s.depth_keys[src ^ 1],
-                                         s.depth_vals[src ^ 1], nullptr, (uint32_t)M, p * kRadixBits,
+        const DepthRel rel{p, p == 2 ? s.depth_keys[0] : nullptr, p == 2 ? s.depth_vals[0] : nullptr,
+                           p + 1 < kMaxDepthPasses ? &s.ctrl->hist_depth[0][p + 1][0] : nullptr};
+        hipError_t e = launch_radix_pass(s.depth_keys[kIn[p]], s.depth_vals[kIn[p]], s.depth_keys[kOut[p]],
+                                         s.depth_vals[kOut[p]], nullptr, (uint32_t)M, p * kRadixBits,
                                          &s.ctrl->hist_depth[0][p][0], kMaxDepthPasses * kRadixBins, s.hist_copies_depth,
                                          s.lb_depth + (size_t)p * lb_blocks(s.depth_blocks) * kRadixBins,
-                                         &s.ctrl->counters[kCounterDepth + p], s.ctrl, st, dnt, dipt);
+                                         &s.ctrl->counters[kCounterDepth + p], s.ctrl, st, dnt, dipt, &rel);
         if (e != hipSuccess) return e;
-        src ^= 1;
     }
     // the fused emission writes the first pair pass's output buffer
     const int pf = s.pair_first_buf ^ (s.fused_emit ? 1 : 0);

@@ -17,12 +17,12 @@
 
 namespace dqo {
 
-template <int NT, int IPT>
+template <int NT, int IPT, bool REL>
 __global__ __launch_bounds__(NT) void radix_pass_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
     const uint32_t* __restrict__ ghist, int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter,
-    int resident, Ctrl* ctrl) {
+    int resident, Ctrl* ctrl, DepthRel rel) {
     static_assert(NT >= kRadixBins && NT % kWave == 0, "one thread per digit at least");
     constexpr int kTile = NT * IPT;
     constexpr int kWaves = NT / kWave;
@@ -33,8 +33,19 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
     __shared__ uint32_t s_gbase[kRadixBins];
     __shared__ uint32_t s_tmp[kWaves];
     __shared__ uint32_t s_bid, s_epoch, s_grouped;
+    __shared__ uint32_t s_next[REL ? kRadixBins : 1];  // REL: counts of the next pass's digit
 
     const int tid = threadIdx.x;
+    // REL: the digits of key - base (clamped to 2^24 - 1 when three passes
+    // suffice), from the key range the projection left in copies
+    __shared__ uint32_t s_krange[2];
+    if (REL && tid < kWave) {
+        uint32_t v = tid < 2 * kHistCopies ? (&ctrl->dkey_range[0][0])[tid] : 0u;
+        // lanes of even index hold max(~key) copies, odd ones max(key)
+#pragma unroll
+        for (int d = 2; d < 2 * kHistCopies; d <<= 1) v = max(v, (uint32_t)__shfl_xor(v, d));
+        if (tid < 2) s_krange[tid] = v;
+    }
     const int lane = tid & (kWave - 1);
     const int wave = tid >> 6;
     // Every load that does not depend on another is issued before the first
@@ -73,7 +84,25 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
         s_epoch = ctrl->epoch;
     }
     for (int i = tid; i < kWaves * kRadixBins; i += NT) (&s_wcnt[0][0])[i] = 0;
+    if (REL && tid < kRadixBins) s_next[tid] = 0u;
     __syncthreads();
+    uint32_t kbase = 0u, clamp = 0xFFFFFFFFu;
+    if constexpr (REL) {
+        const uint32_t kmin = ~s_krange[0], kmax = s_krange[1];
+        const bool any = kmax >= kmin;
+        kbase = any ? (kmin & ~(uint32_t)(kRadixBins - 1)) : 0u;
+        const bool three = any && kmax - kbase < 0xFFFFFFu;
+        if (three) clamp = 0xFFFFFFu;
+        if (rel.pass == 3 && three) return;  // uniform: nothing left to sort
+        if (rel.pass == 2 && three) {
+            kout = rel.kout_final;
+            vout = rel.vout_final;
+        }
+    }
+    auto digit = [&](uint32_t k, int sh) -> uint32_t {
+        if constexpr (REL) k = min(k - kbase, clamp);
+        return (k >> sh) & (kRadixBins - 1);
+    };
     const uint32_t bid = s_bid;
     const uint32_t n = min(n_read, n_host);
     const uint32_t base = bid * (uint32_t)kTile;
@@ -87,7 +116,8 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
     for (int i = 0; i < IPT; ++i) {
         const uint32_t pos = base + wave * (kWave * IPT) + i * kWave + lane;
         const bool valid = pos < n;
-        const uint32_t d = (key[i] >> shift) & (kRadixBins - 1);
+        const uint32_t d = digit(key[i], shift);
+        if (REL && rel.next_hist && valid) atomicAdd(&s_next[digit(key[i], shift + kRadixBits)], 1u);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
@@ -133,7 +163,7 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
     for (int i = 0; i < IPT; ++i) {
         const uint32_t pos = base + wave * (kWave * IPT) + i * kWave + lane;
         if (pos < n) {
-            const uint32_t d = (key[i] >> shift) & (kRadixBins - 1);
+            const uint32_t d = digit(key[i], shift);
             const uint32_t p = s_dstart[d] + s_wcnt[wave][d] + rank[i];
             if (p < (uint32_t)kTile) {
                 s_keys[p] = key[i];
@@ -145,11 +175,17 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
     const uint32_t cnt = min((uint32_t)kTile, n - base);
     for (uint32_t q = tid; q < cnt; q += NT) {
         const uint32_t k = s_keys[q];
-        const uint32_t d = (k >> shift) & (kRadixBins - 1);
+        const uint32_t d = digit(k, shift);
         const uint32_t o = s_gbase[d] + (q - s_dstart[d]);
         if (o < n) {  // always true unless a bounded wait gave up (status bit set)
             kout[o] = k;
             vout[o] = s_vals[q];
+        }
+    }
+    if constexpr (REL) {
+        if (rel.next_hist && owner) {
+            const uint32_t c = s_next[t];
+            if (c) atomicAdd(&rel.next_hist[(size_t)(blockIdx.x % hist_copies) * hist_stride + t], c);
         }
     }
 }
@@ -352,12 +388,19 @@ template <int NT, int IPT>
 static hipError_t radix_launch(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                                const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
                                int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter, Ctrl* ctrl,
-                               hipStream_t st) {
+                               hipStream_t st, const DepthRel* rel) {
     const int blocks = (int)((n_host + NT * IPT - 1) / (NT * IPT));
     // the whole grid is resident: workgroup index order (unless a wait has timed out)
-    const int res = blocks <= resident_blocks<radix_pass_kernel<NT, IPT>, NT>() ? 1 : 0;
-    hipLaunchKernelGGL((radix_pass_kernel<NT, IPT>), dim3(blocks), dim3(NT), 0, st, kin, vin, kout, vout, n_dev,
-                       n_host, shift, ghist, hist_stride, hist_copies, lb, counter, res, ctrl);
+    const DepthRel r = rel ? *rel : DepthRel{0, nullptr, nullptr, nullptr};
+    if (rel) {
+        const int res = blocks <= resident_blocks<radix_pass_kernel<NT, IPT, true>, NT>() ? 1 : 0;
+        hipLaunchKernelGGL((radix_pass_kernel<NT, IPT, true>), dim3(blocks), dim3(NT), 0, st, kin, vin, kout, vout,
+                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, res, ctrl, r);
+    } else {
+        const int res = blocks <= resident_blocks<radix_pass_kernel<NT, IPT, false>, NT>() ? 1 : 0;
+        hipLaunchKernelGGL((radix_pass_kernel<NT, IPT, false>), dim3(blocks), dim3(NT), 0, st, kin, vin, kout, vout,
+                           n_dev, n_host, shift, ghist, hist_stride, hist_copies, lb, counter, res, ctrl, r);
+    }
     return hipGetLastError();
 }
 
@@ -365,10 +408,13 @@ bool radix_resident(int nt, int ipt, int64_t items) {
     const int64_t blocks = (items + (int64_t)nt * ipt - 1) / ((int64_t)nt * ipt);
     int res = 0;
 #define DQO_RADIX_RES(NT_, IPT_) \
-    if (nt == NT_ && ipt == IPT_) res = resident_blocks<radix_pass_kernel<NT_, IPT_>, NT_>();
+    if (nt == NT_ && ipt == IPT_) res = resident_blocks<radix_pass_kernel<NT_, IPT_, false>, NT_>();
     DQO_RADIX_RES(256, 8)
     DQO_RADIX_RES(256, 16)
     DQO_RADIX_RES(256, 32)
+    DQO_RADIX_RES(512, 4)
+    DQO_RADIX_RES(512, 9)
+    DQO_RADIX_RES(512, 18)
     DQO_RADIX_RES(1024, 2)
     DQO_RADIX_RES(1024, 4)
     DQO_RADIX_RES(1024, 8)
@@ -380,15 +426,18 @@ bool radix_resident(int nt, int ipt, int64_t items) {
 hipError_t launch_radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, uint32_t n_host, int shift, const uint32_t* ghist,
                              int hist_stride, int hist_copies, uint64_t* lb, uint32_t* counter, Ctrl* ctrl,
-                             hipStream_t st, int nt, int ipt) {
+                             hipStream_t st, int nt, int ipt, const DepthRel* rel) {
     if (n_host == 0) return hipSuccess;
 #define DQO_RADIX_CASE(NT_, IPT_)                                                                            \
     if (nt == NT_ && ipt == IPT_)                                                                            \
         return radix_launch<NT_, IPT_>(kin, vin, kout, vout, n_dev, n_host, shift, ghist, hist_stride, hist_copies, \
-                                       lb, counter, ctrl, st);
+                                       lb, counter, ctrl, st, rel);
     DQO_RADIX_CASE(256, 8)
     DQO_RADIX_CASE(256, 16)
     DQO_RADIX_CASE(256, 32)
+    DQO_RADIX_CASE(512, 4)
+    DQO_RADIX_CASE(512, 9)
+    DQO_RADIX_CASE(512, 18)
     DQO_RADIX_CASE(1024, 2)
     DQO_RADIX_CASE(1024, 4)
     DQO_RADIX_CASE(1024, 8)

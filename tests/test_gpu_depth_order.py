@@ -67,3 +67,39 @@ def test_tile_depth_order_matches_global(n, tile, lds):
     for k in ("color", "depth", "t_final", "last"):
         assert np.array_equal(g[k], t[k]), k
     np.testing.assert_allclose(t["grad"], g["grad"], rtol=1e-5, atol=1e-6 * np.abs(g["grad"]).max())
+
+
+# z spans: one octave (three depth passes), 0.3 - 30 m (four); some items
+# behind the camera (culled, key 0xffffffff) in both
+@pytest.mark.parametrize("zlo,zhi", [(3.0, 4.5), (0.3, 30.0)])
+def test_depth_order_is_the_stable_key_order(zlo, zhi):
+    n = 5000
+    sc = scenes.single_view_scene(seed=11, n=n)
+    rng = np.random.default_rng(12)
+    z = np.exp(rng.uniform(np.log(zlo), np.log(zhi), size=n))
+    sc["params"][0:2] *= z / 3.0  # keep the means in view
+    sc["params"][2] = z
+    sc["params"][2, :200] = -1.0  # behind the camera
+    sc["params"][2, 200:400] = sc["params"][2, 400:600]  # equal depths: ties by index
+    ctx = B.Context(tile_w=8, tile_h=8, depth_order=B.DEPTH_ORDER_GLOBAL)
+    r = B.Rasterizer(sc["cams"], n, sc["K"], ctx=ctx)
+    p = to_dev(sc["params"])
+    ids = torch.tensor(sc["ids"], device="cuda")
+    r.bin(p, ids)
+    torch.cuda.synchronize()
+    f = r.frame
+    rc, st, P = f.read_status()
+    assert rc == 0 and st == 0
+    spl = f.buf("splats", torch.float32, n * B.SPLAT_WORDS).view(n, B.SPLAT_WORDS).cpu().numpy()
+    # a culled item's record is all zero and its key 0xffffffff
+    visible = spl[:, 6] > 0
+    key = np.where(visible, spl[:, 6].astype(np.float32).view(np.uint32), np.uint32(0xFFFFFFFF)).astype(np.int64)
+    assert (~visible[:200]).all() and visible.sum() > n // 2
+    order = f.buf("depth_order", torch.int32, n).cpu().numpy()
+    skeys = f.buf("depth_keys", torch.int32, n).cpu().numpy().view(np.uint32).astype(np.int64)
+    want = np.lexsort((np.arange(n), key))
+    assert (order == want).all()
+    assert (skeys == key[want]).all()
+    kv = key[visible]
+    three = kv.max() - (kv.min() & ~255) < 0xFFFFFF
+    assert three == (zhi / zlo < 2.0)

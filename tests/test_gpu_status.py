@@ -60,7 +60,9 @@ def test_timeout_bit_switches_sort_to_ticket_order(view):
     # 2048 items, the scan's blocks of 1024; the emission performs the first
     # pair pass itself (its grid fits on the device), so only a second pair
     # pass runs (its grid is sized by the pair capacity)
-    assert (ctrl[DEPTH_TICKETS] == (n + 2047) // 2048).all(), ctrl[DEPTH_TICKETS]
+    # (the fourth depth pass draws none when three passes suffice for the key range)
+    dt = ctrl[DEPTH_TICKETS].cpu().numpy()
+    assert (dt[:3] == (n + 2047) // 2048).all() and dt[3] in (0, (n + 2047) // 2048), dt
     assert int(ctrl[SCAN_TICKET]) == (n + 1023) // 1024
     assert int(ctrl[PAIR_TICKETS][0]) == 0, ctrl[PAIR_TICKETS]
     if view == "640x480":
