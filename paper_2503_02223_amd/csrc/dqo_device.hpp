@@ -357,6 +357,7 @@ struct StatePtrs {
     // per-pixel states the forward stores at the segment boundaries.
     uint4* seg_list;      // [seg_cap] (tile, first position, walk end, boundary record) in launch order (after the forward)
     uint32_t* ckpt_base;  // [V*tiles] first boundary record of each tile
+    uint32_t* seg_base;   // [V*tiles] first entry of each tile's segments in the backward's list
     int32_t* tile_last;   // [V*tiles] last blended position in each tile (forward)
     void* ckpt;           // [ckpt_cap][6][64] T, colour (3), depth, target probability before each boundary
     int64_t seg_cap, ckpt_cap;
@@ -453,8 +454,6 @@ inline int resident_blocks() {
     return n;
 }
 hipError_t launch_clear_written(const StatePtrs& s, hipStream_t st);
-hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, const void* last, const void* target,
-                               hipStream_t st);
 // Whether the 64-pixel-tile backward of a frame with these tiles runs
 // segmented (the forward then stores boundary states and the sort their
 // offsets).

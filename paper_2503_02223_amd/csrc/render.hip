@@ -209,7 +209,8 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     int32_t* __restrict__ last, T* __restrict__ probs, int32_t* __restrict__ idmap,
     const int32_t* __restrict__ target, T* __restrict__ ptarget, int32_t* __restrict__ nblend, uint32_t cap,
     uint32_t M, const uint32_t* __restrict__ ckpt_base, T* __restrict__ ckpt, uint32_t ckpt_cap,
-    int32_t* __restrict__ tile_last) {
+    int32_t* __restrict__ tile_last, const uint32_t* __restrict__ seg_base, uint4* __restrict__ seg_list,
+    uint32_t seg_cap, Ctrl* __restrict__ ctrl) {
     constexpr int BLOCK = TW * TH;
     constexpr int NW = BLOCK / kWave;
     __shared__ __align__(16) T s_sp[BLOCK * kWalkWords];
@@ -232,6 +233,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     const T u = T(tid % TW) + T(0.5), v = T(tid / TW) + T(0.5);
     const T ox = T(tx * TW), oy = T(ty * TH);
     const uint32_t re = min(ranges[2 * tile + 1], cap), rs = min(ranges[2 * tile], re);
+    const uint32_t sbase = (BLOCK == kWave && ckpt) ? seg_base[tile] : 0u;  // used at the end
 #ifndef DQO_FWD_PRIO
 #define DQO_FWD_PRIO 0
 #endif
@@ -385,6 +387,32 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) m = max(m, __shfl_xor(m, d));
             if (tid == 0) tile_last[tile] = m;
+            // The tile's entries of the backward's segment list, at the place
+            // the sort reserved for its segments: every 64-pair segment up to
+            // the last blended position, with the end of its walk (one past
+            // that position when it lies in the segment) and the boundary
+            // record at its end (none where no pixel blends past it: the
+            // segment holding the last blended position and the range's
+            // last); the segments behind are marked empty (no walk).
+            const uint32_t nseg = tile_segments(re - rs);
+            const uint32_t k = (m >= (int)rs && m < (int)re) ? min(((uint32_t)m - rs) / (uint32_t)kSegLen + 1u, nseg) : 0u;
+            const uint32_t last_end = (uint32_t)m + 1u, cb = ckpt_base[tile];
+            for (uint32_t j = (uint32_t)tid; j < nseg; j += kWave) {
+                const uint32_t pos = sbase + j;
+                if (pos >= seg_cap) break;
+                const uint32_t s0 = rs + j * (uint32_t)kSegLen;
+                const bool tail = j + 1u >= nseg;  // the last segment takes the rest of the range
+                const uint32_t s1 = tail ? re : s0 + (uint32_t)kSegLen;
+                const bool past = !tail && last_end > s1;
+                seg_list[pos] = j < k ? make_uint4((uint32_t)tile, s0, min(last_end, s1), past ? cb + j : kNoBoundary)
+                                      : make_uint4((uint32_t)tile, 0u, 0u, kNoBoundary);
+            }
+            if (blockIdx.x == 0 && tid == 0) {
+                // the forward these states belong to (checked by the backward)
+                ctrl->seg_stamp[0] = ctrl->epoch;
+                ctrl->seg_stamp[1] = (uint64_t)(uintptr_t)last;
+                ctrl->seg_stamp[2] = (uint64_t)(uintptr_t)target;
+            }
         }
     }
     if (!in_img) return;
@@ -713,6 +741,7 @@ __device__ __forceinline__ void backward_unit(
     uint32_t s0, s1, hi_seg = 0u, bnd = kNoBoundary;
     if (seg_list) {
         const uint4 en = seg_list[unit];
+        if (en.z <= en.y) return;  // a segment behind its tile's last blended position (uniform)
         tile = (int)min(en.x, n_tiles - 1u);
         s0 = min(en.y, cap);
         hi_seg = min(max(en.z, s0), cap);
@@ -1064,19 +1093,16 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)img.probs, img.id_map, img.target,
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
-                           (T*)(seg ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
+                           (T*)(seg ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last, s.seg_base, s.seg_list,
+                           (uint32_t)s.seg_cap, s.ctrl);
     } else {
         auto kern = img.n_blend ? render_forward_kernel<T, TW, TH, false, true> : render_forward_kernel<T, TW, TH, false, false>;
         hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)nullptr, (int32_t*)nullptr, img.target,
                            (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
-                           (T*)(seg ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last);
-    }
-    if (seg) {
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        return launch_segment_list(s, blocks, img.last, img.target, st);
+                           (T*)(seg ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last, s.seg_base, s.seg_list,
+                           (uint32_t)s.seg_cap, s.ctrl);
     }
     return hipGetLastError();
 }

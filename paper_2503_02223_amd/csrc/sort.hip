@@ -229,9 +229,14 @@ constexpr int kSchedBins = 4096;
 constexpr int kSchedRegs = 8;
 __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint32_t* __restrict__ ranges,
                                                                      int tiles, uint32_t* __restrict__ schedule,
-                                                                     uint32_t* __restrict__ ckpt_base) {
+                                                                     uint32_t* __restrict__ ckpt_base,
+                                                                     uint32_t* __restrict__ seg_base,
+                                                                     Ctrl* __restrict__ ctrl) {
     __shared__ uint32_t s_cnt[kSchedBins];  // bin b holds count kSchedBins - 1 - b (descending order)
     __shared__ uint32_t s_tmp[kSchedThreads / kWave];
+    // segmented backward (at most kSegTilesMax tiles): the launch order and
+    // each tile's pair count, for the layout of the segment list
+    __shared__ uint32_t s_order[kSegTilesMax], s_width[kSegTilesMax];
     constexpr int kPer = kSchedBins / kSchedThreads;
     const int tid = threadIdx.x;
     auto bin_of_w = [](uint32_t w) { return kSchedBins - 1 - (int)min(w, (uint32_t)(kSchedBins - 1)); };
@@ -271,14 +276,44 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
         off += c[k];
     }
     __syncthreads();
+    const bool seg = ckpt_base && tiles <= kSegTilesMax;  // uniform
     if (regs) {
 #pragma unroll
         for (int k = 0; k < kSchedRegs; ++k)
-            if (lo + k < hi) schedule[atomicAdd(&s_cnt[bin_of_w(w[k])], 1u)] = (uint32_t)(lo + k);
+            if (lo + k < hi) {
+                const uint32_t p = atomicAdd(&s_cnt[bin_of_w(w[k])], 1u);
+                schedule[p] = (uint32_t)(lo + k);
+                if (seg) {
+                    s_order[p] = (uint32_t)(lo + k);
+                    s_width[lo + k] = w[k];
+                }
+            }
     } else {
-        for (int t = lo; t < hi; ++t) schedule[atomicAdd(&s_cnt[bin_of_w(width(t))], 1u)] = (uint32_t)t;
+        for (int t = lo; t < hi; ++t) {
+            const uint32_t wt = width(t), p = atomicAdd(&s_cnt[bin_of_w(wt)], 1u);
+            schedule[p] = (uint32_t)t;
+            if (seg) {
+                s_order[p] = (uint32_t)t;
+                s_width[t] = wt;
+            }
+        }
     }
-    if (!ckpt_base) return;  // uniform
+    if (!seg) return;  // uniform
+    // The backward's segment list holds every 64-pair segment of every tile,
+    // tiles in launch order (heaviest first); the forward fills in each
+    // tile's entries once it knows how far its pixels blend (the rest it
+    // marks empty).  Here: each tile's first entry and the list's length.
+    __syncthreads();
+    {
+        uint32_t own = 0;
+        for (int p = lo; p < hi; ++p) own += tile_segments(s_width[s_order[p]]);
+        uint32_t run = block_exclusive_scan<kSchedThreads>(own, s_tmp);
+        for (int p = lo; p < hi; ++p) {
+            seg_base[s_order[p]] = run;
+            run += tile_segments(s_width[s_order[p]]);
+        }
+        if (tid == kSchedThreads - 1) ctrl->counters[kCounterSegTotal] = run;
+    }
     // Segmented backward of 64-pixel tiles: the first boundary record of
     // each tile (index order), where the forward stores its boundary states.
     auto bounds = [](uint32_t wt) {
@@ -306,82 +341,6 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
             run += bounds(width(t));
         }
     }
-}
-
-// The backward's work list, built after the forward: every 64-pair segment
-// of every tile up to the tile's last blended position, one wavefront each,
-// in launch order (heaviest tile first), and the list's length.  An entry
-// holds what the wavefront's first loads need: the tile, the segment's first
-// position, the end of its walk (one past the tile's last blended position
-// when that lies in the segment, else the segment's end) and the record of
-// the boundary state at the segment's end (kNoBoundary where no pixel blends
-// past the segment: the one holding the tile's last blended position, and
-// the last of its range).  One thread per tile of the launch order, 1024 per
-// block; each block also sums the segments of all tiles before its own (at
-// most 7 per thread), so the blocks need nothing from one another.  At most
-// kSegTilesMax tiles.  Block 0 stamps the list with the binning epoch and
-// the forward's images, which the backward checks.
-__global__ __launch_bounds__(kSchedThreads) void segment_list_kernel(const uint32_t* __restrict__ ranges,
-                                                                    const uint32_t* __restrict__ schedule,
-                                                                    const int32_t* __restrict__ tile_last,
-                                                                    const uint32_t* __restrict__ ckpt_base, int tiles,
-                                                                    uint4* __restrict__ seg_list, int64_t seg_cap,
-                                                                    Ctrl* __restrict__ ctrl, uint64_t last_addr,
-                                                                    uint64_t target_addr) {
-    __shared__ uint32_t s_tmp[kSchedThreads / kWave];
-    const int tid = threadIdx.x;
-    const int b = blockIdx.x;
-    auto segs = [&](int p) -> uint32_t {
-        const uint32_t t = schedule[p];
-        const uint32_t rs = ranges[2 * t], re = ranges[2 * t + 1];
-        const int ml = tile_last[t];
-        return (ml >= (int)rs && ml < (int)re) ? min(((uint32_t)ml - rs) / (uint32_t)kSegLen + 1u, tile_segments(re - rs))
-                                               : 0u;
-    };
-    constexpr int kMaxBefore = kSegTilesMax / kSchedThreads - 1;
-    uint32_t before = 0;  // segments of the tiles before this block's, this thread's share
-#pragma unroll
-    for (int i = 0; i < kMaxBefore; ++i) {
-        const int p = i * kSchedThreads + tid;
-        if (i < b) before += segs(p);
-    }
-    const int p = b * kSchedThreads + tid;
-    const uint32_t t = p < tiles ? schedule[p] : 0u;
-    const uint32_t k = p < tiles ? segs(p) : 0u;
-    const uint32_t rs = p < tiles ? ranges[2 * t] : 0u, re = p < tiles ? ranges[2 * t + 1] : 0u;
-    const uint32_t nseg = tile_segments(re - rs), last_end = (uint32_t)(p < tiles ? tile_last[t] : 0) + 1u;
-    const uint32_t cb = p < tiles ? ckpt_base[t] : 0u;
-    const uint32_t base = block_exclusive_scan<kSchedThreads>(before, s_tmp) + before;  // inclusive: thread 1023 has all
-    __shared__ uint32_t s_base;
-    if (tid == kSchedThreads - 1) s_base = base;
-    __syncthreads();
-    uint32_t pos = s_base + block_exclusive_scan<kSchedThreads>(k, s_tmp);
-    for (uint32_t j = 0; j < k; ++j, ++pos)
-        if ((int64_t)pos < seg_cap) {
-            const uint32_t s0 = rs + j * (uint32_t)kSegLen;
-            const bool tail = j + 1u >= nseg;  // the tile's last segment takes the rest of the range
-            const uint32_t s1 = tail ? re : s0 + (uint32_t)kSegLen;
-            const bool past = !tail && last_end > s1;
-            seg_list[pos] = make_uint4(t, s0, min(last_end, s1), past ? cb + j : kNoBoundary);
-        }
-    if (b == (int)gridDim.x - 1 && tid == kSchedThreads - 1)
-        ctrl->counters[kCounterSegTotal] = (uint32_t)min((int64_t)pos, seg_cap);
-    if (b == 0 && tid == 0) {
-        // the forward these states belong to (checked by the backward)
-        ctrl->seg_stamp[0] = ctrl->epoch;
-        ctrl->seg_stamp[1] = last_addr;
-        ctrl->seg_stamp[2] = target_addr;
-    }
-}
-
-hipError_t launch_segment_list(const StatePtrs& s, int tiles_total, const void* last, const void* target,
-                               hipStream_t st) {
-    if (tiles_total > kSegTilesMax) return hipErrorInvalidValue;
-    const int blocks = (tiles_total + kSchedThreads - 1) / kSchedThreads;
-    hipLaunchKernelGGL(segment_list_kernel, dim3(blocks), dim3(kSchedThreads), 0, st, s.ranges, s.schedule,
-                       s.tile_last, s.ckpt_base, tiles_total, s.seg_list, s.seg_cap, s.ctrl, (uint64_t)(uintptr_t)last,
-                       (uint64_t)(uintptr_t)target);
-    return hipGetLastError();
 }
 
 template <int NT, int IPT>
@@ -634,7 +593,7 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges,
                            (uint32_t*)s.written);
         hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
-                           s.schedule, segmented_backward(s, tiles_total) ? s.ckpt_base : nullptr);
+                           s.schedule, segmented_backward(s, tiles_total) ? s.ckpt_base : nullptr, s.seg_base, s.ctrl);
         if (s.tile_sort)
             hipLaunchKernelGGL(tile_sort_kernel, dim3((unsigned)tiles_total), dim3(kTileSortThreads), 0, st, s.ranges,
                                s.schedule, s.depth_keys[0], (uint32_t)s.items, cap, (uint32_t)s.tile_sort_lds,
