@@ -34,7 +34,7 @@ struct Geo {
     int depth_blocks, scan_blocks, pair_blocks, pair_passes, pair_first_buf;
     int64_t lb_words;
     // scratch sub-offsets (relative to DQO_BUF_SCRATCH)
-    int64_t off_dk1, off_dv1, off_dk2, off_dv2, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_sbase, off_seg, off_cbase,
+    int64_t off_dk1, off_dv1, off_dk2, off_dv2, off_pk1, off_pv1, off_sched, off_sums, off_pose, off_written, off_sbase, off_seg,
         off_sgbase, off_tlast, off_ckpt, off_lbd, off_lbs, off_lbp;
     int64_t seg_cap, ckpt_cap;
     bool tile_sort;     // per-tile depth order (dqo_depth_order TILE)
@@ -130,7 +130,6 @@ Geo geometry(const dqo_ctx* ctx, const dqo_frame_desc* d, const dqo_camera* cams
     g.ckpt_cap = (tw * th == kWave && tiles_total <= kSegTilesMax) ? cap / kSegLen + 1 : 0;
     g.seg_cap = tiles_total + g.ckpt_cap;
     g.off_seg = so; so = align256(so + g.seg_cap * 16);
-    g.off_cbase = so; so = align256(so + tiles_total * 4);
     g.off_sgbase = so; so = align256(so + tiles_total * 4);
     g.off_tlast = so; so = align256(so + tiles_total * 4);
     g.off_ckpt = so; so = align256(so + g.ckpt_cap * 6 * kWave * ts);
@@ -176,7 +175,6 @@ StatePtrs state_ptrs(const Geo& g, void* state) {
     s.written = (uint8_t*)(sc + g.off_written);
     s.scan_base = (uint32_t*)(sc + g.off_sbase);
     s.seg_list = (uint4*)(sc + g.off_seg);
-    s.ckpt_base = (uint32_t*)(sc + g.off_cbase);
     s.seg_base = (uint32_t*)(sc + g.off_sgbase);
     s.tile_last = (int32_t*)(sc + g.off_tlast);
     s.ckpt = sc + g.off_ckpt;

@@ -25,8 +25,8 @@ constexpr int kSortThreads = 256;
 // Items per thread of a radix pass.  The decoupled look-back costs one memory
 // latency per window of preceding blocks, so longer blocks shorten the chain
 // but lengthen each block's own ranking and scatter.  Measured on one MI355X:
-// the pair passes take 4096-item blocks while that grid fits on the device at
-// once (1.5M pairs of the 640x480 view: 1761 -> 1788 it/s against 8192) and
+// the pair passes take short blocks (then 4096 items; 4608 now, below) while
+// that grid fits on the device at once (1.5M pairs of the 640x480 view: 1761 -> 1788 it/s against 8192) and
 // 8192-item blocks beyond (49M pairs of eight keyframes: 163 -> 175 it/s); the
 // depth passes are fastest with 2048-item blocks at 200k items (4096: 1700 ->
 // 1672 it/s, 8192 slower still) and with 8192-item blocks from about a
@@ -36,17 +36,21 @@ constexpr int kSortThreads = 256;
 #define DQO_DEPTH_NT 256
 #endif
 #ifndef DQO_PAIR_NT
-#define DQO_PAIR_NT 256
+#define DQO_PAIR_NT 512
 #endif
 #ifndef DQO_PAIR_IPT_SHORT
-#define DQO_PAIR_IPT_SHORT (DQO_PAIR_NT == 256 ? 16 : 8)
+#define DQO_PAIR_IPT_SHORT (DQO_PAIR_NT == 512 ? 9 : DQO_PAIR_NT == 256 ? 16 : 8)
 #endif
 #ifndef DQO_DEPTH_IPT_SMALL
 #define DQO_DEPTH_IPT_SMALL (DQO_DEPTH_NT == 256 ? 8 : 4)
 #endif
-constexpr int kDepthNt = DQO_DEPTH_NT, kPairNt = DQO_PAIR_NT;
-constexpr int kPairIptShort = DQO_PAIR_IPT_SHORT, kPairIptLong = 2 * DQO_PAIR_IPT_SHORT;
-constexpr int kPairTileMin = kPairNt * kPairIptShort;  // sizes the pair look-back arrays
+// Pair passes whose grid fits on the device at once: 512 threads x 9 pairs
+// (4608-pair blocks, two per CU; 22.7 -> 21.3 us per pass at 1.5M pairs
+// against 256 x 16); longer grids: 256 x 32.
+constexpr int kDepthNt = DQO_DEPTH_NT, kPairNt = DQO_PAIR_NT, kPairNtLong = 256;
+constexpr int kPairIptShort = DQO_PAIR_IPT_SHORT, kPairIptLong = 32;
+constexpr int kPairTileMin = kPairNt * kPairIptShort < kPairNtLong * kPairIptLong ? kPairNt * kPairIptShort
+                                                                                   : kPairNtLong * kPairIptLong;  // sizes the pair look-back arrays
 inline int depth_ipt(int64_t items) {
     constexpr int s = DQO_DEPTH_IPT_SMALL;
     return items < (int64_t(1) << 18) ? s : items < (int64_t(1) << 19) ? 2 * s : 4 * s;
@@ -159,6 +163,12 @@ struct Consts {
 // only add work (measured: 1M Gaussians at 1200x680, 12750 tiles, backward
 // 11% slower segmented).
 constexpr int kSegTilesMax = 8192;
+// The boundary state at pair position b (a multiple of kSegLen past its
+// tile's first position rs) is record rs / kSegLen + (b - rs) / kSegLen: the
+// records of different tiles never meet (a tile of n pairs has fewer than
+// n / kSegLen boundaries and the next starts n positions later), and they
+// stay below capacity / kSegLen + 1.
+__host__ __device__ constexpr uint32_t boundary_record(uint32_t rs, uint32_t k) { return rs / kSegLen + k; }
 __device__ __forceinline__ uint32_t tile_segments(uint32_t range) {
     return min((range + kSegLen - 1) / (uint32_t)kSegLen, (uint32_t)kSegMax);
 }
@@ -356,7 +366,6 @@ struct StatePtrs {
     // segments of kSegLen pairs, one wavefront each, restarted from
     // per-pixel states the forward stores at the segment boundaries.
     uint4* seg_list;      // [seg_cap] (tile, first position, walk end, boundary record) in launch order (after the forward)
-    uint32_t* ckpt_base;  // [V*tiles] first boundary record of each tile
     uint32_t* seg_base;   // [V*tiles] first entry of each tile's segments in the backward's list
     int32_t* tile_last;   // [V*tiles] last blended position in each tile (forward)
     void* ckpt;           // [ckpt_cap][6][64] T, colour (3), depth, target probability before each boundary

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ schedule, T* __restrict__ color, T* __restrict__ depth, T* __restrict__ tfinal,
     int32_t* __restrict__ last, T* __restrict__ probs, int32_t* __restrict__ idmap,
     const int32_t* __restrict__ target, T* __restrict__ ptarget, int32_t* __restrict__ nblend, uint32_t cap,
-    uint32_t M, const uint32_t* __restrict__ ckpt_base, T* __restrict__ ckpt, uint32_t ckpt_cap,
+    uint32_t M, T* __restrict__ ckpt, uint32_t ckpt_cap,
     int32_t* __restrict__ tile_last, const uint32_t* __restrict__ seg_base, uint4* __restrict__ seg_list,
     uint32_t seg_cap, Ctrl* __restrict__ ctrl) {
     constexpr int BLOCK = TW * TH;
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
             // segmented backward (which restarts there).
             const uint32_t rel = b0 - rs;
             if (ckpt && rel > 0 && rel % kSegLen == 0 && rel / kSegLen < (uint32_t)kSegMax) {
-                const uint32_t e = ckpt_base[tile] + rel / kSegLen - 1u;
+                const uint32_t e = boundary_record(rs, rel / kSegLen);
                 if (e < ckpt_cap) {
                     T* c = ckpt + (size_t)e * 6 * kWave + tid;
                     c[0 * kWave] = Tt;
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
             // last); the segments behind are marked empty (no walk).
             const uint32_t nseg = tile_segments(re - rs);
             const uint32_t k = (m >= (int)rs && m < (int)re) ? min(((uint32_t)m - rs) / (uint32_t)kSegLen + 1u, nseg) : 0u;
-            const uint32_t last_end = (uint32_t)m + 1u, cb = ckpt_base[tile];
+            const uint32_t last_end = (uint32_t)m + 1u;
             for (uint32_t j = (uint32_t)tid; j < nseg; j += kWave) {
                 const uint32_t pos = sbase + j;
                 if (pos >= seg_cap) break;
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(TW* TH) void render_forward_kernel(
                 const bool tail = j + 1u >= nseg;  // the last segment takes the rest of the range
                 const uint32_t s1 = tail ? re : s0 + (uint32_t)kSegLen;
                 const bool past = !tail && last_end > s1;
-                seg_list[pos] = j < k ? make_uint4((uint32_t)tile, s0, min(last_end, s1), past ? cb + j : kNoBoundary)
+                seg_list[pos] = j < k ? make_uint4((uint32_t)tile, s0, min(last_end, s1), past ? boundary_record(rs, j + 1u) : kNoBoundary)
                                       : make_uint4((uint32_t)tile, 0u, 0u, kNoBoundary);
             }
             if (blockIdx.x == 0 && tid == 0) {
@@ -1092,7 +1092,7 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
         hipLaunchKernelGGL((render_forward_kernel<T, TW, TH, true>), dim3(blocks), dim3(TW * TH), dyn, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)img.probs, img.id_map, img.target,
-                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
+                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items,
                            (T*)(seg ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last, s.seg_base, s.seg_list,
                            (uint32_t)s.seg_cap, s.ctrl);
     } else {
@@ -1100,7 +1100,7 @@ static hipError_t fwd_tile(const Frame<T>& f, const dqo_images& img, hipStream_t
         hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, st, f.views,
                            f.consts, f.K, (const T*)s.splats, s.pair_vals[0], s.ranges, s.schedule, (T*)img.color,
                            (T*)img.depth, (T*)img.t_final, img.last, (T*)nullptr, (int32_t*)nullptr, img.target,
-                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items, s.ckpt_base,
+                           (T*)img.p_target, img.n_blend, (uint32_t)s.capacity, (uint32_t)s.items,
                            (T*)(seg ? s.ckpt : nullptr), (uint32_t)s.ckpt_cap, s.tile_last, s.seg_base, s.seg_list,
                            (uint32_t)s.seg_cap, s.ctrl);
     }

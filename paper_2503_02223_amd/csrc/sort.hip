@@ -229,14 +229,13 @@ constexpr int kSchedBins = 4096;
 constexpr int kSchedRegs = 8;
 __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint32_t* __restrict__ ranges,
                                                                      int tiles, uint32_t* __restrict__ schedule,
-                                                                     uint32_t* __restrict__ ckpt_base,
-                                                                     uint32_t* __restrict__ seg_base,
+                                                                     int seg, uint32_t* __restrict__ seg_base,
                                                                      Ctrl* __restrict__ ctrl) {
     __shared__ uint32_t s_cnt[kSchedBins];  // bin b holds count kSchedBins - 1 - b (descending order)
+    // segmented backward: the segments of each bin's tiles, then the bin's
+    // cursor in the segment list
+    __shared__ uint32_t s_seg[kSchedBins];
     __shared__ uint32_t s_tmp[kSchedThreads / kWave];
-    // segmented backward (at most kSegTilesMax tiles): the launch order and
-    // each tile's pair count, for the layout of the segment list
-    __shared__ uint32_t s_order[kSegTilesMax], s_width[kSegTilesMax];
     constexpr int kPer = kSchedBins / kSchedThreads;
     const int tid = threadIdx.x;
     auto bin_of_w = [](uint32_t w) { return kSchedBins - 1 - (int)min(w, (uint32_t)(kSchedBins - 1)); };
@@ -244,7 +243,7 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
         const uint2 r = reinterpret_cast<const uint2*>(ranges)[t];
         return r.y - r.x;
     };
-    // thread tid holds tiles [tid * per, tid * per + per): contiguous, for the index-order scan below
+    // thread tid holds tiles [tid * per, tid * per + per)
     const int per = (tiles + kSchedThreads - 1) / kSchedThreads;
     const bool regs = per <= kSchedRegs;
     const int lo = min(tiles, tid * per), hi = min(tiles, lo + per);
@@ -253,93 +252,52 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
 #pragma unroll
         for (int k = 0; k < kSchedRegs; ++k) w[k] = lo + k < hi ? width(lo + k) : 0u;
     }
-    for (int b = tid; b < kSchedBins; b += kSchedThreads) s_cnt[b] = 0u;
+    for (int b = tid; b < kSchedBins; b += kSchedThreads) s_cnt[b] = s_seg[b] = 0u;
     __syncthreads();
+    auto count = [&](uint32_t wt) {
+        atomicAdd(&s_cnt[bin_of_w(wt)], 1u);
+        if (seg) atomicAdd(&s_seg[bin_of_w(wt)], tile_segments(wt));
+    };
     if (regs) {
 #pragma unroll
         for (int k = 0; k < kSchedRegs; ++k)
-            if (lo + k < hi) atomicAdd(&s_cnt[bin_of_w(w[k])], 1u);
+            if (lo + k < hi) count(w[k]);
     } else {
-        for (int t = lo; t < hi; ++t) atomicAdd(&s_cnt[bin_of_w(width(t))], 1u);
+        for (int t = lo; t < hi; ++t) count(width(t));
     }
     __syncthreads();
-    uint32_t c[kPer], sum = 0;
+    uint32_t c[kPer], g[kPer], sum = 0, gsum = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         c[k] = s_cnt[tid * kPer + k];
+        g[k] = s_seg[tid * kPer + k];
         sum += c[k];
+        gsum += g[k];
     }
     uint32_t off = block_exclusive_scan<kSchedThreads>(sum, s_tmp);
+    uint32_t goff = seg ? block_exclusive_scan<kSchedThreads>(gsum, s_tmp) : 0u;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         s_cnt[tid * kPer + k] = off;
+        s_seg[tid * kPer + k] = goff;
         off += c[k];
+        goff += g[k];
     }
-    __syncthreads();
-    const bool seg = ckpt_base && tiles <= kSegTilesMax;  // uniform
-    if (regs) {
-#pragma unroll
-        for (int k = 0; k < kSchedRegs; ++k)
-            if (lo + k < hi) {
-                const uint32_t p = atomicAdd(&s_cnt[bin_of_w(w[k])], 1u);
-                schedule[p] = (uint32_t)(lo + k);
-                if (seg) {
-                    s_order[p] = (uint32_t)(lo + k);
-                    s_width[lo + k] = w[k];
-                }
-            }
-    } else {
-        for (int t = lo; t < hi; ++t) {
-            const uint32_t wt = width(t), p = atomicAdd(&s_cnt[bin_of_w(wt)], 1u);
-            schedule[p] = (uint32_t)t;
-            if (seg) {
-                s_order[p] = (uint32_t)t;
-                s_width[t] = wt;
-            }
-        }
-    }
-    if (!seg) return;  // uniform
     // The backward's segment list holds every 64-pair segment of every tile,
-    // tiles in launch order (heaviest first); the forward fills in each
-    // tile's entries once it knows how far its pixels blend (the rest it
-    // marks empty).  Here: each tile's first entry and the list's length.
+    // tiles by bin (heaviest first); the forward fills in each tile's entries
+    // once it knows how far its pixels blend (the rest it marks empty).
+    if (seg && tid == kSchedThreads - 1) ctrl->counters[kCounterSegTotal] = goff;
     __syncthreads();
-    {
-        uint32_t own = 0;
-        for (int p = lo; p < hi; ++p) own += tile_segments(s_width[s_order[p]]);
-        uint32_t run = block_exclusive_scan<kSchedThreads>(own, s_tmp);
-        for (int p = lo; p < hi; ++p) {
-            seg_base[s_order[p]] = run;
-            run += tile_segments(s_width[s_order[p]]);
-        }
-        if (tid == kSchedThreads - 1) ctrl->counters[kCounterSegTotal] = run;
-    }
-    // Segmented backward of 64-pixel tiles: the first boundary record of
-    // each tile (index order), where the forward stores its boundary states.
-    auto bounds = [](uint32_t wt) {
-        const uint32_t k = tile_segments(wt);
-        return k ? k - 1u : 0u;
+    auto place = [&](int t, uint32_t wt) {
+        schedule[atomicAdd(&s_cnt[bin_of_w(wt)], 1u)] = (uint32_t)t;
+        if (seg) seg_base[t] = atomicAdd(&s_seg[bin_of_w(wt)], tile_segments(wt));
     };
-    uint32_t own = 0;
-    if (regs) {
-#pragma unroll
-        for (int k = 0; k < kSchedRegs; ++k) own += lo + k < hi ? bounds(w[k]) : 0u;
-    } else {
-        for (int t = lo; t < hi; ++t) own += bounds(width(t));
-    }
-    uint32_t run = block_exclusive_scan<kSchedThreads>(own, s_tmp);
     if (regs) {
 #pragma unroll
         for (int k = 0; k < kSchedRegs; ++k)
-            if (lo + k < hi) {
-                ckpt_base[lo + k] = run;
-                run += bounds(w[k]);
-            }
+            if (lo + k < hi) place(lo + k, w[k]);
     } else {
-        for (int t = lo; t < hi; ++t) {
-            ckpt_base[t] = run;
-            run += bounds(width(t));
-        }
+        for (int t = lo; t < hi; ++t) place(t, width(t));
     }
 }
 
@@ -575,7 +533,7 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
     const uint32_t* n_dev = &s.ctrl->num_pairs;
     // short blocks while that grid is resident at once, else long ones
     const bool short_ok = radix_resident(kPairNt, kPairIptShort, cap);
-    const int ipt = short_ok ? kPairIptShort : kPairIptLong;
+    const int nt = short_ok ? kPairNt : kPairNtLong, ipt = short_ok ? kPairIptShort : kPairIptLong;
     // the fused emission has done pass 0 (its output is in the other buffer)
     const int p0 = s.fused_emit ? 1 : 0;
     int src = s.pair_first_buf ^ p0;
@@ -583,7 +541,7 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         hipError_t e = launch_radix_pass(s.pair_keys[src], s.pair_vals[src], s.pair_keys[src ^ 1],
                                          s.pair_vals[src ^ 1], n_dev, cap, p * kRadixBits,
                                          &s.ctrl->hist_pair[0][p][0], kMaxPairPasses * kRadixBins, s.hist_copies_pair, s.lb_pair + (size_t)p * lb_blocks(s.pair_blocks) * kRadixBins,
-                                         &s.ctrl->counters[kCounterPair + p], s.ctrl, st, kPairNt, ipt);
+                                         &s.ctrl->counters[kCounterPair + p], s.ctrl, st, nt, ipt);
         if (e != hipSuccess) return e;
         src ^= 1;
     }
@@ -593,7 +551,7 @@ hipError_t launch_pair_sort(const StatePtrs& s, int tiles_total, hipStream_t st)
         hipLaunchKernelGGL(tile_bounds_kernel, dim3(grid), dim3(256), 0, st, s.pair_keys[0], n_dev, cap, s.ranges,
                            (uint32_t*)s.written);
         hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, st, s.ranges, tiles_total,
-                           s.schedule, segmented_backward(s, tiles_total) ? s.ckpt_base : nullptr, s.seg_base, s.ctrl);
+                           s.schedule, segmented_backward(s, tiles_total) ? 1 : 0, s.seg_base, s.ctrl);
         if (s.tile_sort)
             hipLaunchKernelGGL(tile_sort_kernel, dim3((unsigned)tiles_total), dim3(kTileSortThreads), 0, st, s.ranges,
                                s.schedule, s.depth_keys[0], (uint32_t)s.items, cap, (uint32_t)s.tile_sort_lds,
