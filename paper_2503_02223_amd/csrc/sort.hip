@@ -223,9 +223,8 @@ constexpr int kSchedThreads = 1024;
 constexpr int kSchedBins = 4096;
 
 // Up to kSchedRegs tiles per thread are loaded once, all at once, and kept in
-// registers (their ranges are read by three dependent phases: the count
-// histogram, the scatter and the boundary bases); more tiles loop over
-// global memory.
+// registers (their ranges are read by two dependent phases: the count
+// histogram and the scatter); more tiles loop over global memory.
 constexpr int kSchedRegs = 8;
 __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint32_t* __restrict__ ranges,
                                                                      int tiles, uint32_t* __restrict__ schedule,
@@ -243,14 +242,15 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
         const uint2 r = reinterpret_cast<const uint2*>(ranges)[t];
         return r.y - r.x;
     };
-    // thread tid holds tiles [tid * per, tid * per + per)
-    const int per = (tiles + kSchedThreads - 1) / kSchedThreads;
-    const bool regs = per <= kSchedRegs;
-    const int lo = min(tiles, tid * per), hi = min(tiles, lo + per);
+    // thread tid holds tiles tid + k * kSchedThreads (coalesced loads)
+    const bool regs = tiles <= kSchedRegs * kSchedThreads;
     uint32_t w[kSchedRegs];
     if (regs) {
 #pragma unroll
-        for (int k = 0; k < kSchedRegs; ++k) w[k] = lo + k < hi ? width(lo + k) : 0u;
+        for (int k = 0; k < kSchedRegs; ++k) {
+            const int t = tid + k * kSchedThreads;
+            w[k] = t < tiles ? width(t) : 0u;
+        }
     }
     for (int b = tid; b < kSchedBins; b += kSchedThreads) s_cnt[b] = s_seg[b] = 0u;
     __syncthreads();
@@ -261,9 +261,9 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
     if (regs) {
 #pragma unroll
         for (int k = 0; k < kSchedRegs; ++k)
-            if (lo + k < hi) count(w[k]);
+            if (tid + k * kSchedThreads < tiles) count(w[k]);
     } else {
-        for (int t = lo; t < hi; ++t) count(width(t));
+        for (int t = tid; t < tiles; t += kSchedThreads) count(width(t));
     }
     __syncthreads();
     uint32_t c[kPer], g[kPer], sum = 0, gsum = 0;
@@ -295,9 +295,9 @@ __global__ __launch_bounds__(kSchedThreads) void tile_schedule_kernel(const uint
     if (regs) {
 #pragma unroll
         for (int k = 0; k < kSchedRegs; ++k)
-            if (lo + k < hi) place(lo + k, w[k]);
+            if (tid + k * kSchedThreads < tiles) place(tid + k * kSchedThreads, w[k]);
     } else {
-        for (int t = lo; t < hi; ++t) place(t, width(t));
+        for (int t = tid; t < tiles; t += kSchedThreads) place(t, width(t));
     }
 }
 
