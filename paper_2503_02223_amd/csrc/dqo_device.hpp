@@ -55,8 +55,10 @@ inline int depth_ipt(int64_t items) {
     constexpr int s = DQO_DEPTH_IPT_SMALL;
     return items < (int64_t(1) << 18) ? s : items < (int64_t(1) << 19) ? 2 * s : 4 * s;
 }
-// Scan + emission: one record per thread, 1024 per block, so that each of the
-// 16 wavefronts emits the pairs of its own 64 records.
+// Scan + emission: one record per thread, 512 per block, so that each of the
+// 8 wavefronts emits the pairs of its own 64 records (with the first pair
+// pass fused, two blocks share a CU: 35.8 -> 34.4 us at the 200k view against
+// 1024; 256 per block: 46.5 us).
 constexpr int kSegLen = 64;        // pairs per backward segment of a 64-pixel tile
 constexpr int kSegMax = 255;       // segments per tile (the last one takes the rest of the range)
 constexpr uint32_t kNoBoundary = 0xFFFFFFFFu;  // segment-list entry of a tile's last segment: no restart
@@ -66,7 +68,7 @@ constexpr uint32_t kNoBoundary = 0xFFFFFFFFu;  // segment-list entry of a tile's
 constexpr uint32_t kPairSkip = 0x80000000u;
 constexpr uint32_t kPairItem = 0x7FFFFFFFu;
 #ifndef DQO_SCAN_THREADS
-#define DQO_SCAN_THREADS 1024
+#define DQO_SCAN_THREADS 512
 #endif
 constexpr int kScanThreads = DQO_SCAN_THREADS;
 constexpr int kScanIpt = 1;  // 2 and 4 measured slower at 200k items (1646 -> 1627 / 1573 it/s)

@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_emit_kernel(
     // order and written out in runs (one per digit), so stores coalesce;
     // longer blocks store each pair where it goes.  s_gb: output position of
     // the block's staged pair 0 of each digit, minus the digit's staged start.
-    constexpr int kStage = FUSED ? 12288 : 1;
+    constexpr int kStage = FUSED ? 12 * kScanThreads : 1;
     __shared__ uint32_t s_pk[kStage], s_pv[kStage];
     __shared__ uint32_t s_gb[FUSED ? kRadixBins : 1];
     const int tid = threadIdx.x;

@@ -57,13 +57,13 @@ def test_timeout_bit_switches_sort_to_ticket_order(view):
     assert rc == B.EINTERNAL and st & B.STATUS_TIMEOUT and npairs2 == npairs
     ctrl = f.buf("control", torch.int32)
     # every block of every pass took a ticket: the depth passes' blocks of
-    # 2048 items, the scan's blocks of 1024; the emission performs the first
+    # 2048 items, the scan's blocks of 512; the emission performs the first
     # pair pass itself (its grid fits on the device), so only a second pair
     # pass runs (its grid is sized by the pair capacity)
     # (the fourth depth pass draws none when three passes suffice for the key range)
     dt = ctrl[DEPTH_TICKETS].cpu().numpy()
     assert (dt[:3] == (n + 2047) // 2048).all() and dt[3] in (0, (n + 2047) // 2048), dt
-    assert int(ctrl[SCAN_TICKET]) == (n + 1023) // 1024
+    assert int(ctrl[SCAN_TICKET]) == (n + 511) // 512
     assert int(ctrl[PAIR_TICKETS][0]) == 0, ctrl[PAIR_TICKETS]
     if view == "640x480":
         assert int(ctrl[PAIR_TICKETS][1]) >= 2, ctrl[PAIR_TICKETS]
