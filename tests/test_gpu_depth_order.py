@@ -103,3 +103,47 @@ def test_depth_order_is_the_stable_key_order(zlo, zhi):
     kv = key[visible]
     three = kv.max() - (kv.min() & ~255) < 0xFFFFFF
     assert three == (zhi / zlo < 2.0)
+
+
+def test_fused_emission_with_three_pair_passes():
+    """Six 1280x720 views at 8x8 tiles: 86,400 tile ids (17 bits, three
+    8-bit pair passes), 20,000 Gaussians per view (the emission grid fits on
+    the device, so the emission performs the first pass and two remain).  The
+    pair list is the stable (tile, depth bits, index) order of exactly the
+    pairs of the tile rectangles."""
+    n, V = 20000, 6
+    sc = scenes.slam_view_scene(seed=21, n=n)
+    cams = []
+    for v in range(V):
+        ang = 0.15 * (v - 2.5)
+        R = np.array([[np.cos(ang), 0.0, -np.sin(ang)], [0.0, 1.0, 0.0], [np.sin(ang), 0.0, np.cos(ang)]])
+        cams.append(scenes.camera(R=R, t=[0.0, 0.0, 7.63], fx=900, fy=900, cx=640, cy=360, width=1280, height=720))
+    ctx = B.Context(tile_w=8, tile_h=8, depth_order=B.DEPTH_ORDER_GLOBAL)
+    r = B.Rasterizer(cams, n, sc["K"], ctx=ctx)
+    p = to_dev(sc["params"])
+    ids = torch.tensor(sc["ids"], device="cuda")
+    r.bin(p, ids)
+    torch.cuda.synchronize()
+    f = r.frame
+    rc, st, P = f.read_status()
+    assert rc == 0 and st == 0 and P > 10000
+    M = V * n
+    tiles_x, tiles_per_view = 160, 160 * 90
+    keys = f.buf("pair_keys", torch.int32, P).cpu().numpy().astype(np.int64)
+    vals = pair_items(f.buf("pair_vals", torch.int32, P).cpu().numpy()).astype(np.int64)
+    assert keys.max() >= 65536  # the third pass sorts something
+    spl = f.buf("splats", torch.float32, M * B.SPLAT_WORDS).view(M, B.SPLAT_WORDS).cpu().numpy()
+    zbits = spl[:, 6].astype(np.float32).view(np.uint32).astype(np.int64)
+    assert (np.lexsort((vals, zbits[vals], keys)) == np.arange(P)).all()
+    cnt = f.buf("counts", torch.int32, M).cpu().numpy()
+    rect = f.buf("rects", torch.int16, M * 4).view(M, 4).cpu().numpy().astype(np.int64)
+    want = []
+    for i in np.nonzero(cnt)[0]:
+        base = (i // n) * tiles_per_view
+        ys, xs = np.meshgrid(np.arange(rect[i, 1], rect[i, 3] + 1), np.arange(rect[i, 0], rect[i, 2] + 1), indexing="ij")
+        want.append(np.stack([base + ys.ravel() * tiles_x + xs.ravel(), np.full(ys.size, i)], 1))
+    want = np.concatenate(want)
+    want = want[np.lexsort((want[:, 1], want[:, 0]))]
+    got = np.stack([keys, vals], 1)
+    got = got[np.lexsort((got[:, 1], got[:, 0]))]
+    assert got.shape == want.shape and (got == want).all()
