@@ -97,6 +97,7 @@ __global__ __launch_bounds__(NT) void radix_pass_kernel(
         if (rel.pass == 2 && three) {
             kout = rel.kout_final;
             vout = rel.vout_final;
+            rel.next_hist = nullptr;  // no fourth pass to count for
         }
     }
     auto digit = [&](uint32_t k, int sh) -> uint32_t {
