@@ -39,7 +39,7 @@ BYTES_PER_PAIR, BYTES_PER_PIXEL, BYTES_PER_WRITTEN = 44.0, 32.0, 40.0
 # HBM bytes per launch of the render backward from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (scaled by a 256 MiB copy: x2.000 and x1.000), valid only for the kernel source
 # they were taken with (render.hip and dqo_device.hpp); reported as null otherwise.
-MEASURED_TRAFFIC = {"render_src_sha256_16": "5113419c6b02e3c7", "bytes_per_launch": 145775000}
+MEASURED_TRAFFIC = {"render_src_sha256_16": "5113419c6b02e3c7", "bytes_per_launch": 145690000}
 
 
 def measured_traffic():
